@@ -1,0 +1,186 @@
+"""Pins of the oracle's Gramian and RRCG iteration (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import bttb, prism, rrcg
+
+G6 = prism.Geometry(6, 6, 6, 6, 3, 50.0, 50.0, 50.0)   # n = 108 unknowns, m = 36 data
+
+
+def _ops(g):
+    return [bttb.DenseOperator(prism.dense_matrix(k, g), g) for k in (prism.GRAVITY, prism.MAGNETIC)]
+
+
+@pytest.fixture(scope="module")
+def ops6():
+    return _ops(G6)
+
+
+def test_gramian_identities():
+    r = np.random.default_rng(1)
+    m1 = r.standard_normal(50)
+    for gamma in (0.3, -2.0, 7.5):
+        m2 = gamma * m1
+        s = rrcg.gramian(m1, m2)
+        assert abs(s) <= 1e-12 * rrcg.dot(m1, m1) * rrcg.dot(m2, m2)
+        l1, l2 = rrcg.gramian_ascent(m1, m2)
+        assert np.abs(l1).max() <= 1e-12 * np.abs(m1).max() * rrcg.dot(m2, m2)
+        assert np.abs(l2).max() <= 1e-12 * np.abs(m2).max() * rrcg.dot(m1, m1)
+    for _ in range(5):
+        a, b = r.standard_normal(30), r.standard_normal(30)
+        assert rrcg.gramian(a, b) >= 0.0
+        # gradient of S_G by central differences equals 2 l_G (l_G is the half-gradient)
+        l1, l2 = rrcg.gramian_ascent(a, b)
+        h = 1e-6
+        for j in (0, 7, 29):
+            e = np.zeros(30)
+            e[j] = h
+            g1 = (rrcg.gramian(a + e, b) - rrcg.gramian(a - e, b)) / (2 * h)
+            g2 = (rrcg.gramian(a, b + e) - rrcg.gramian(a, b - e)) / (2 * h)
+            assert abs(g1 - 2 * l1[j]) <= 1e-6 * max(1.0, abs(g1))
+            assert abs(g2 - 2 * l2[j]) <= 1e-6 * max(1.0, abs(g2))
+    # scalar weights: S~_G = (w1 w2)^2 S_G
+    a, b = r.standard_normal(30), r.standard_normal(30)
+    w1, w2 = 2.5, 0.7
+    assert rrcg.gramian(w1 * a, w2 * b) == pytest.approx((w1 * w2) ** 2 * rrcg.gramian(a, b), rel=1e-12)
+
+
+def test_l1_weight():
+    eps2 = 1e-9
+    m = np.array([0.0, 1e-3, 0.2, -0.5])
+    w = rrcg.l1_weight(m, np.zeros(4), eps2)
+    assert w[0] == pytest.approx(eps2 ** -0.25, rel=1e-15)     # = 177.83
+    assert w[0] == pytest.approx(177.8279410038923, rel=1e-12)
+    # ||W_L1 (m - m_apr)||^2 -> ||m - m_apr||_1 as eps -> 0
+    assert np.sum((w * m) ** 2) == pytest.approx(np.abs(m).sum(), rel=1e-5)
+
+
+def _data(g, ops, seed=0, noise=0.0, wdepth=None):
+    r = np.random.default_rng(seed)
+    m_true = [np.zeros((g.nz, g.nx, g.ny)) for _ in range(2)]
+    m_true[0][1:3, 2:4, 1:4] = 0.8
+    m_true[1][1:3, 2:4, 1:4] = 0.08
+    d = [ops[i].matvec(m_true[i]) for i in range(2)]
+    sig = [0.02 * np.abs(d[i]) + 0.01 * np.abs(d[i]).max() for i in range(2)]
+    dobs = [d[i] + noise * sig[i] * r.standard_normal(d[i].shape) for i in range(2)]
+    if wdepth is None:
+        wdepth = [np.ones(m_true[0].shape), np.ones(m_true[0].shape)]
+    return rrcg.Data(dobs=dobs, wd=[1.0 / s for s in sig], wdepth=wdepth), m_true
+
+
+def test_cg_reduces_to_tikhonov_normal_equations(ops6):
+    # lambda = 0, W_L1 = I (p = 2), fixed W, q = 1, no bounds: one outer step of n
+    # inner CG steps solves (A~^T A~ + alpha I) m~ = A~^T d~ (normal equations); a few
+    # outer steps (restarts from the true residual) remove the recurrence's drift
+    g = G6
+    r = np.random.default_rng(2)
+    wdepth = [r.uniform(0.5, 2.0, (g.nz, g.nx, g.ny)) for _ in range(2)]
+    data, _ = _data(g, ops6, noise=1.0, wdepth=wdepth)
+    alpha = (3.0, 0.5)
+    prm = rrcg.Params(alpha0=alpha, q=(1.0, 1.0), lam=(0.0, 0.0), p_norm=2, restart=True)
+    st0 = rrcg.initial_state(data, prm, (g.nz, g.nx, g.ny))
+    st1, _ = rrcg.run(ops6, data, prm, n_outer=4, n_inner=2 * g.n, state=st0)
+    for i in range(2):
+        A = ops6[i].A
+        W = wdepth[i].ravel()
+        At = np.diag(data.wd[i].ravel()) @ A @ np.diag(1.0 / W)
+        mt = np.linalg.solve(At.T @ At + alpha[i] * np.eye(g.n), At.T @ (data.wd[i] * data.dobs[i]).ravel())
+        ref = mt / W
+        assert np.linalg.norm(st1.m[i].ravel() - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_objective_decreases_within_inner_cycle(ops6):
+    g = G6
+    data, _ = _data(g, ops6, noise=1.0)
+    prm = rrcg.Params(alpha0=(10.0, 10.0), q=(1.0, 1.0), p_norm=2, restart=True)
+    st0 = rrcg.initial_state(data, prm, (g.nz, g.nx, g.ny))
+
+    def objective(m):
+        val = 0.0
+        for i in range(2):
+            rr = data.wd[i] * (ops6[i].matvec(m[i]) - data.dobs[i])
+            val += rrcg.dot(rr, rr) + prm.alpha0[i] * rrcg.dot(data.wdepth[i] * m[i], data.wdepth[i] * m[i])
+        return val
+    vals = [objective(st0.m)]
+    for J in range(1, 12):
+        st, _ = rrcg.outer_step(ops6, data, prm, st0, n_inner=J)
+        vals.append(objective(st.m))
+    assert all(vals[j + 1] <= vals[j] * (1 + 1e-12) for j in range(len(vals) - 1))
+    assert vals[-1] < 0.5 * vals[0]
+
+
+def test_gramian_term_reaches_stationary_point_of_objective(ops6):
+    # W = I, lambda1 = lambda2: l is half the gradient of
+    # sum ||W_d(A m - d)||^2 + alpha ||m||^2 + lambda S_G, so the iteration's limit is a
+    # stationary point of that objective.  The residual gradient there must be small
+    # next to the Gramian part of the gradient: a dropped, halved or sign-flipped
+    # coupling term leaves a residual of the same size as that part.
+    g = G6
+    data, _ = _data(g, ops6, noise=0.5)
+    lam, alpha = 1e3, 20.0
+    prm = rrcg.Params(alpha0=(alpha, alpha), q=(1.0, 1.0), lam=(lam, lam), p_norm=2, restart=True)
+    st = rrcg.initial_state(data, prm, (g.nz, g.nx, g.ny))
+    for _ in range(160):
+        st, _ = rrcg.outer_step(ops6, data, prm, st, n_inner=20)
+    A = [ops6[i].A for i in range(2)]
+    Wd = [data.wd[i].ravel() for i in range(2)]
+    d = [data.dobs[i].ravel() for i in range(2)]
+    m1, m2 = st.m[0].ravel(), st.m[1].ravel()
+    r1 = Wd[0] * (A[0] @ m1 - d[0])
+    r2 = Wd[1] * (A[1] @ m2 - d[1])
+    l1, l2 = rrcg.gramian_ascent(m1, m2)
+    grad = np.concatenate([2 * A[0].T @ (Wd[0] * r1) + 2 * alpha * m1 + 2 * lam * l1,
+                           2 * A[1].T @ (Wd[1] * r2) + 2 * alpha * m2 + 2 * lam * l2])
+    coupling = np.concatenate([2 * lam * l1, 2 * lam * l2])
+    assert np.linalg.norm(grad) <= 0.1 * np.linalg.norm(coupling)
+    assert rrcg.gramian(m1, m2) > 0
+
+
+def test_bounds_hold_and_alpha_schedule(ops6):
+    g = G6
+    data, _ = _data(g, ops6, noise=1.0)
+    prm = rrcg.Params(alpha0=(100.0, 100.0), q=(0.5, 0.8), alpha_min=(10.0, 0.0), lam=(1e-3, 1e-1),
+                      lo=(0.0, 0.0), hi=(1.0, 0.1), restart=False)
+    st = rrcg.initial_state(data, prm, (g.nz, g.nx, g.ny))
+    thr = g.sx * g.sy + math.sqrt(2 * g.sx * g.sy)
+    for _ in range(12):
+        new, rec = rrcg.outer_step(ops6, data, prm, st, n_inner=1)
+        assert new.m[0].min() >= 0.0 and new.m[0].max() <= 1.0
+        assert new.m[1].min() >= 0.0 and new.m[1].max() <= 0.1
+        assert rec["threshold"] == pytest.approx(thr)
+        for i in range(2):
+            if new.frozen[i]:
+                assert new.alpha[i] == st.alpha[i]
+            else:
+                assert new.alpha[i] == max(prm.q[i] * st.alpha[i], prm.alpha_min[i])
+            assert new.frozen[i] == (st.frozen[i] or rec["phi"][i] <= thr)
+        st = new
+    assert st.k == 12
+
+
+def test_swap_symmetry(ops6):
+    g = G6
+    data, _ = _data(g, ops6, noise=1.0)
+    prm = rrcg.Params(alpha0=(50.0, 20.0), q=(0.9, 0.8), lam=(1e-2, 3e-1), lo=(0.0, 0.0), hi=(1.0, 0.1))
+    st, _ = rrcg.run(ops6, data, prm, n_outer=4, n_inner=3)
+    sw = lambda x: [x[1], x[0]]
+    data_s = rrcg.Data(dobs=sw(data.dobs), wd=sw(data.wd), wdepth=sw(data.wdepth))
+    prm_s = rrcg.Params(alpha0=sw(prm.alpha0), q=sw(prm.q), lam=sw(prm.lam), lo=sw(prm.lo), hi=sw(prm.hi))
+    st_s, _ = rrcg.run(sw(ops6), data_s, prm_s, n_outer=4, n_inner=3)
+    assert np.array_equal(st.m[0], st_s.m[1]) and np.array_equal(st.m[1], st_s.m[0])
+
+
+def test_standalone_equals_two_separate_inversions(ops6):
+    # coupled=False with lambda = 0 runs two independent RRCGs (Sec. 3.1.1)
+    g = G6
+    data, _ = _data(g, ops6, noise=1.0)
+    prm = rrcg.Params(alpha0=(50.0, 20.0), q=(0.9, 0.8), coupled=False, lo=(0.0, 0.0), hi=(1.0, 0.1))
+    st, _ = rrcg.run(ops6, data, prm, n_outer=3, n_inner=4)
+    # the same data set twice gives the same answer whatever the other one is
+    data2 = rrcg.Data(dobs=[data.dobs[0], data.dobs[0]], wd=[data.wd[0], data.wd[0]],
+                      wdepth=data.wdepth)
+    prm2 = rrcg.Params(alpha0=(50.0, 50.0), q=(0.9, 0.9), coupled=False, lo=(0.0, 0.0), hi=(1.0, 1.0))
+    st2, _ = rrcg.run([ops6[0], ops6[0]], data2, prm2, n_outer=3, n_inner=4)
+    assert np.array_equal(st.m[0], st2.m[0]) and np.array_equal(st2.m[0], st2.m[1])
