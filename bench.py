@@ -1,0 +1,280 @@
+"""Benchmark of the BTTB operators and the joint RRCG solve on one MI355X.
+
+Workload: 256 x 256 stations over 256 x 256 x 32 prisms (40 x 40 x 25 m cells), a
+dyke-and-block density / susceptibility model, gravity and total-field data with 2 %
+plus 0.02 mGal / 1 nT Gaussian noise; joint RRCG with p = 1 reweighting and the
+Gramian coupling, 50 CG steps per outer step with restarts, FP32 FFTs and products
+with FP64 reductions and scalars.
+
+A step is one outer step of that solve (50 CG steps, each with one forward and one
+transpose product of both operators, plus the reweighting); K = 20 steps is the full
+20 x 50 solve.  value = operator pairs (y = A x and z = A^T r of one operator) per
+second over the timed steps; the residual products of each outer step are not counted.
+
+Also reported: pure product throughput (FP32, FP64), the same solve in FP64, the
+roofline of the dominant kernel from HIP events recorded around every product kernel
+in the timed region, and the FP64 CPU oracle's product throughput on a bounded sample.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "G+G^T matvec pairs/s & HBM GB/s at 256x256x32; RRCG solve s, FP32 vs FP64"
+HBM_PEAK_GBS = 8000.0
+N_INNER = 50
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 solve")
+    ap.add_argument("--pairs", type=int, default=200, help="timed product pairs per precision")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(pk, torch, g):
+    import synth
+    rho, kap = synth.dyke_and_block(g)
+    ops64 = [pk.Operator.from_geometry(k, g, dtype=torch.float64) for k in (pk.GRAVITY, pk.MAGNETIC)]
+    d = [ops64[i].matvec(torch.as_tensor(m, device="cuda")).cpu().numpy() for i, m in enumerate((rho, kap))]
+    floors = (0.02, 1.0)   # mGal, nT
+    sig = [synth.noise_sigma(d[i], 0.02, floors[i]) for i in range(2)]
+    dobs = [d[i] + sig[i] * synth.normal_like(d[i].shape, 3, 100 + i) for i in range(2)]
+    wd = [1.0 / s for s in sig]
+    wdepth = [synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)]
+    for op in ops64:
+        op.close()
+    return (rho, kap), dobs, wd, wdepth
+
+
+def solver(pk, torch, ops, dobs, wd, wdepth):
+    return pk.JointRRCG(ops, dobs, wd, wdepth, lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0),
+                        q=(0.95, 0.95), lam=(2.0, 100.0), eps2=1e-9, coupled=True, restart=True, p_norm=1)
+
+
+def product_rate(torch, ops, pairs):
+    """Operator pairs per second of back-to-back products (inputs resident in HBM)."""
+    xs = [torch.rand(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
+    rs = [torch.randn(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
+    ys = [torch.empty(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
+    zs = [torch.empty(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
+    for _ in range(5):
+        for i, op in enumerate(ops):
+            op.matvec(xs[i], out=ys[i])
+            op.rmatvec(rs[i], out=zs[i])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n = 0
+    e0.record()
+    while n < pairs:
+        for i, op in enumerate(ops):
+            op.matvec(xs[i], out=ys[i])
+            op.rmatvec(rs[i], out=zs[i])
+            n += 1
+    e1.record()
+    torch.cuda.synchronize()
+    return n / (e0.elapsed_time(e1) / 1e3)
+
+
+def kernel_bytes(info, esz):
+    """Bytes each product kernel must move per launch (batch 1): its inputs once and its
+    outputs once.  Complex values are 2 esz bytes."""
+    nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
+    Px, Py = info["Px"], info["Py"]
+    K2 = Py // 2 + 1
+    c = 2 * esz
+    nch = info["layer_chunks"]
+    eig = nz * K2 * Px * c
+    return {
+        "fwd_row_r2c": nz * nx * ny * esz + nz * K2 * nx * c,
+        "fwd_col_eig_sum": eig + nz * K2 * nx * c + nch * K2 * sx * c,
+        "fwd_row_c2r": nch * K2 * sx * c + sx * sy * esz,
+        "adj_row_r2c": sx * sy * esz + K2 * sx * c,
+        "adj_col_conj_eig": eig + K2 * sx * c + nz * K2 * nx * c,
+        "adj_row_c2r": nz * K2 * nx * c + nz * nx * ny * esz,
+    }
+
+
+def pair_bytes(info, esz):
+    """Algorithmic bytes of one operator pair: the eigenvalues read by both products,
+    the model read and written, the data written and read."""
+    nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
+    K2 = info["Py"] // 2 + 1
+    return 2 * nz * info["Px"] * K2 * 2 * esz + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
+
+
+def cpu_baseline(g, budget_s=12.0):
+    """FP64 oracle FFT2 products on the host cores: operator pairs per second."""
+    import synth
+    from oracle import bttb as obttb
+    from oracle import prism as oprism
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    og = oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+    ops = [obttb.FFTOperator(obttb.kernel_array(k, og), g.sx, g.sy, workers=cores)
+           for k in (oprism.GRAVITY, oprism.MAGNETIC)]
+    rho, kap = synth.dyke_and_block(g)
+    r = synth.normal_like(g.data_shape, 3, 7)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        for op, m in zip(ops, (rho, kap)):
+            op.matvec(m)
+            op.rmatvec(r)
+            n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "op-pairs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} operator pairs (G m and G^T r, gravity and magnetic alternating) of the "
+                      f"256x256x32 operators, scipy.fft FP64 on the unpadded 511x511 circle, "
+                      f"workers={cores}, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is described "
+              f"in the design notes, not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import __graft_entry__
+    b = __graft_entry__._builder()
+    if not b.is_built():
+        b.build()
+    import paper_2112_15562_amd as pk
+    import synth
+    g = synth.LARGE
+    torch.cuda.set_device(0)
+    log("bench: inputs")
+    models, dobs, wd, wdepth = make_inputs(pk, torch, g)
+
+    # ---------------- FP32 joint RRCG (the timed workload) ----------------
+    log("bench: fp32 setup")
+    ops32 = [pk.Operator.from_geometry(k, g, dtype=torch.float32) for k in (pk.GRAVITY, pk.MAGNETIC)]
+    s32 = solver(pk, torch, ops32, dobs, wd, wdepth)
+    for _ in range(args.warmup):
+        s32.step(N_INNER)
+    torch.cuda.synchronize()
+    s32.close()
+    s32 = solver(pk, torch, ops32, dobs, wd, wdepth)   # fresh start for the timed solve
+    launches = args.steps * (N_INNER * 3 + 3) + 16
+    for op in ops32:
+        op.timing_enable(launches)
+    torch.cuda.synchronize()
+    log("bench: fp32 timed solve")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s32.step(N_INNER)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    sc32 = s32.scalars()
+    timings = [op.timing_read() for op in ops32]
+    for op in ops32:
+        op.timing_enable(0)
+    info32 = ops32[0].info()
+    pairs = 2 * N_INNER * args.steps
+    value = pairs / t32
+
+    # dominant kernel and its roofline
+    tot = {}
+    for tm in timings:
+        for k, (ms, n) in tm.items():
+            a = tot.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += n
+    dom = max(tot, key=lambda k: tot[k][0])
+    avg_ms = tot[dom][0] / max(tot[dom][1], 1)
+    kb = kernel_bytes(info32, 4)[dom]
+    achieved = kb / (avg_ms * 1e-3) / 1e9
+    kernel_table = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1),
+                        "GBps": kernel_bytes(info32, 4)[k] / (ms / max(n, 1) * 1e-3) / 1e9 if n else None}
+                    for k, (ms, n) in tot.items()}
+
+    # ---------------- product throughput ----------------
+    log("bench: product rates")
+    rate32 = product_rate(torch, ops32, args.pairs)
+    s32.close()
+    for op in ops32:
+        op.close()
+    ops64 = [pk.Operator.from_geometry(k, g, dtype=torch.float64) for k in (pk.GRAVITY, pk.MAGNETIC)]
+    info64 = ops64[0].info()
+    rate64 = product_rate(torch, ops64, args.pairs)
+
+    # ---------------- FP64 solve ----------------
+    t64 = None
+    if not args.no_f64:
+        log("bench: fp64 solve")
+        s64 = solver(pk, torch, ops64, dobs, wd, wdepth)
+        s64.step(N_INNER)
+        torch.cuda.synchronize()
+        s64.close()
+        s64 = solver(pk, torch, ops64, dobs, wd, wdepth)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s64.step(N_INNER)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        s64.close()
+    for op in ops64:
+        op.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: cpu oracle baseline")
+        cpu = cpu_baseline(g)
+
+    b32, b64 = pair_bytes(info32, 4), pair_bytes(info64, 8)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "op-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP64 reductions and scalars)",
+        "data": "synthetic: dyke-and-block model, 2% + 0.02 mGal / 1 nT Gaussian noise",
+        "config": {"workload": "joint RRCG, 256x256 stations over 256x256x32 prisms, 20 outer x 50 inner, "
+                               "FP32 FFT with FP64 reductions",
+                   "stations": [g.sx, g.sy], "prisms": [g.nx, g.ny, g.nz], "transform": [info32["Px"],
+                                                                                      info32["Py"]],
+                   "inner_per_step": N_INNER},
+        "rrcg_solve_s": {"f32": t32 * 20 / args.steps, "f64": (t64 * 20 / args.steps) if t64 else None,
+                         "outer": 20, "inner": N_INNER},
+        "product_pairs_per_s": {"f32": rate32, "f64": rate64},
+        "product_GBps_alg": {"f32": rate32 * b32 / 1e9, "f64": rate64 * b64 / 1e9,
+                             "bytes_per_pair": {"f32": b32, "f64": b64}},
+        "final_chi2": {"phi": sc32["phi"], "threshold": sc32["threshold"], "alpha": sc32["alpha"]},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": kb,
+                     "avg_launch_us": 1e3 * avg_ms},
+        "kernels": kernel_table,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,245 @@
+/*
+ * bttb.h -- C ABI of the MI355X (gfx950) BTTB operator and joint RRCG library.
+ *
+ * What it computes (Vatankhah, Renaut, Huang, Mickus, Gharloghi, arXiv:2112.15562):
+ *
+ *   * Sec. 2.1, eq. (d=gm): d = A m, A the m x n sensitivity of the vertical gravity
+ *     (A^(1)) or the total-field anomaly (A^(2)) of right rectangular prisms.
+ *   * Sec. 2.7.1: A = [A_(1) ... A_(nz)] by depth layer, A x = sum_r A_(r) x_(r); each
+ *     A_(r) is BTTB and fixed by an array T_(r) of (sx+nx-1) x (sy+ny-1) values; its
+ *     products are IFFT2(FFT2(T) . FFT2(X)) (forward) and IFFT2(conj(FFT2(T)) . FFT2(V))
+ *     (transpose) with X / V embedded in the upper-left corner of a zero array.
+ *   * eq. (matrixvector): weighted products A~ x = W_d . (A (W^-1 . x)),
+ *     A~^T y = W^-1 . (A^T (W_d . y)), the diagonals passed as vectors.
+ *   * Sec. 2.4, eqs. (RRCG:1-8) with Sec. 2.5 (bounds), 2.6 (chi^2 test) and 2.8
+ *     (alpha schedule, fixed Lagrange parameters): the joint RRCG solver.
+ *
+ * Conventions shared by every entry point:
+ *   * Every function returns an int status: BTTB_OK (0) or a negative bttb_status.
+ *     None throws, aborts or exits.  bttb_last_error() returns a message for the
+ *     calling thread's last failure.
+ *   * Array layouts are C order.  A model vector is [nz][nx][ny] (x = East index a,
+ *     y = North index b, layer r); a data vector is [sx][sy] (station p, q).  The
+ *     kernel array is [nz][sx+nx-1][sy+ny-1] with
+ *       kernels[r][i][j] = K_r(u = i-(nx-1), v = j-(ny-1)),
+ *     u = station x index minus prism x index, v likewise along y, K_r the response
+ *     at the station of a unit-property prism of layer r.
+ *   * "dev" pointers are HIP device pointers; the caller owns them, the library
+ *     only reads or writes them.  A plan owns its eigenvalues and scratch; they are
+ *     allocated in bttb_setup / rrcg_create and freed by bttb_destroy / rrcg_destroy.
+ *     No other call allocates, so products and RRCG steps may be captured in a HIP
+ *     graph.
+ *   * Data type: vectors are double for a BTTB_F64 plan and float for a BTTB_F32 plan.
+ *     RRCG scalars are always double.
+ *   * Every call is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     returns without waiting, except where stated.  One plan or RRCG handle must not
+ *     be used from two streams at once.
+ *   * Pointers must be non-NULL unless stated nullable, and aligned to their element
+ *     size; sizes must be >= 1.  Violations return BTTB_EINVAL.  The padded transform
+ *     sizes must not exceed BTTB_MAX_TRANSFORM, else BTTB_ESIZE.
+ */
+#ifndef BTTB_H
+#define BTTB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define BTTB_API __attribute__((visibility("default")))
+#else
+#define BTTB_API
+#endif
+
+#define BTTB_MAX_TRANSFORM 2048
+
+typedef struct bttb_plan_s* bttb_plan;
+typedef struct rrcg_s* rrcg_handle;
+
+typedef enum {
+  BTTB_OK = 0,
+  BTTB_EINVAL = -1, /* bad argument: NULL / misaligned pointer, size < 1, bad enum */
+  BTTB_ENOMEM = -2, /* device allocation failed (setup / create only) */
+  BTTB_EHIP = -3,   /* a HIP runtime call or kernel launch failed */
+  BTTB_ESIZE = -4,  /* padded transform size above BTTB_MAX_TRANSFORM, or batch too large */
+  BTTB_ESTATE = -5, /* incompatible plans or handle state */
+  BTTB_ENAN = -6    /* a non-finite value was produced (RRCG status) */
+} bttb_status;
+
+typedef enum { BTTB_F64 = 0, BTTB_F32 = 1 } bttb_precision;
+typedef enum { BTTB_GRAVITY = 0, BTTB_MAGNETIC = 1 } bttb_kind;
+typedef enum { BTTB_OP_FORWARD = 0, BTTB_OP_ADJOINT = 1 } bttb_op;
+
+/* Station and prism grid.  x = East, y = North, z = down.  Prism (a, b, r) spans
+ * [a dx,(a+1) dx] x [b dy,(b+1) dy] x [top + r dz, top + (r+1) dz]; station (p, q) sits at
+ * ((p+1/2) dx, (q+1/2) dy, -height), i.e. above the prism centres (Sec. 2.7.1).
+ * The inducing field has inclination incl_deg, declination decl_deg and intensity
+ * field_nt (nT).  Units: metres, g/cc -> mGal, SI susceptibility -> nT. */
+typedef struct {
+  int sx, sy, nx, ny, nz;
+  double dx, dy, dz, height, top;
+  double incl_deg, decl_deg, field_nt;
+} bttb_geometry;
+
+/* Plan description returned by bttb_plan_info. */
+typedef struct {
+  int sx, sy, nx, ny, nz;
+  int Px, Py;              /* padded BCCB transform sizes (5-smooth multiples of 8) */
+  int precision;           /* bttb_precision */
+  int max_batch;
+  size_t eig_bytes;        /* bytes of the stored eigenvalues */
+  size_t scratch_bytes;    /* bytes of the product scratch */
+  int col_fft_per_block;   /* launch shape in use (see bttb_set_launch) */
+  int row_fft_per_block;
+  int layer_chunks;
+} bttb_plan_desc;
+
+/* Kernel array of eq. (d=gm) for one operator, computed on the GPU in FP64 from the
+ * closed forms of the prism's vertical gravity (kind = BTTB_GRAVITY, Haaz) or total
+ * field anomaly for induced magnetisation (kind = BTTB_MAGNETIC, Rao & Babu),
+ * Sec. 2.1.  out: dev double [nz][sx+nx-1][sy+ny-1] in the layout above. */
+BTTB_API int bttb_prism_kernels(int kind, const bttb_geometry* g, double* out, void* stream);
+
+/* Build a plan: place each layer's kernel array on a Px x Py circle (Px, Py the
+ * smallest 5-smooth multiples of 8 >= sx+nx-1, sy+ny-1) and take its FFT2 once
+ * (the BCCB eigenvalues, Sec. 2.7.1), in FP64; a BTTB_F32 plan rounds them to float.
+ * kernels: dev double [nz][sx+nx-1][sy+ny-1], read during the call only.
+ * max_batch: largest batch a single product call may take (>= 1).
+ * Synchronises `stream` before returning.  *out receives the plan. */
+BTTB_API int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny, int nz,
+               int precision, int max_batch, void* stream, bttb_plan* out);
+
+/* y = A x  (Sec. 2.7.1 forward).  x: dev [nz][nx][ny]; y: dev [sx][sy]. */
+BTTB_API int bttb_matvec(bttb_plan plan, const void* x, void* y, void* stream);
+
+/* z = A^T r  (Sec. 2.7.1 transpose, conj eigenvalues).  r: dev [sx][sy]; z: dev [nz][nx][ny]. */
+BTTB_API int bttb_rmatvec(bttb_plan plan, const void* r, void* z, void* stream);
+
+/* General product, batched and weighted (eq. matrixvector):
+ *   op = BTTB_OP_FORWARD: out_b = wd . (A (winv . in_b))        in_b [nz][nx][ny] -> out_b [sx][sy]
+ *   op = BTTB_OP_ADJOINT: out_b = winv . (A^T (wd . in_b))      in_b [sx][sy] -> out_b [nz][nx][ny]
+ * for b < batch (1 <= batch <= max_batch), element strides in_stride / out_stride between
+ * batch members (>= the member size).  winv (dev [nz][nx][ny], = 1/W) and wd (dev [sx][sy])
+ * are nullable (NULL = identity) and shared by the whole batch. */
+BTTB_API int bttb_apply(bttb_plan plan, int op, int batch, const void* in, long long in_stride,
+               void* out, long long out_stride, const void* winv, const void* wd, void* stream);
+
+/* Launch shape: FFTs per block for the column and row passes and the number of layer
+ * chunks of the forward column pass.  Values <= 0 keep the current choice.  Changes
+ * only the work split, never the arithmetic of an output element.  BTTB_EINVAL if a
+ * value does not fit the plan (LDS or size limits). */
+BTTB_API int bttb_set_launch(bttb_plan plan, int col_fft_per_block, int row_fft_per_block, int layer_chunks);
+
+BTTB_API int bttb_plan_info(bttb_plan plan, bttb_plan_desc* out);
+
+/* Copy the plan's eigenvalues (complex [nz][Py/2+1][Px] of the plan's type, interleaved
+ * re, im, already scaled by 1/(Px Py); eig_bytes of bttb_plan_info) into the dev buffer
+ * `out`, enqueued on `stream`.  For inspection and tests. */
+BTTB_API int bttb_plan_eigenvalues(bttb_plan plan, void* out, void* stream);
+
+BTTB_API int bttb_destroy(bttb_plan plan);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around each kernel
+ * of the products, for measurement.  bttb_timing_enable(plan, n) allocates n event
+ * pairs (n = 0 disables and frees them; not to be called during stream capture);
+ * launches beyond n are not timed.  bttb_timing_read synchronises on the events, adds
+ * the elapsed milliseconds and launch counts of every timed kernel into
+ * total_ms[BTTB_NKERNELS] and count[BTTB_NKERNELS] (overwritten), and starts over.
+ * Kernel ids: 0 forward row transform, 1 forward column pass (eigenvalue multiply and
+ * layer sum), 2 forward inverse row transform, 3 transpose row transform, 4 transpose
+ * column pass (conjugate eigenvalue multiply), 5 transpose inverse row transform. */
+#define BTTB_NKERNELS 6
+BTTB_API int bttb_timing_enable(bttb_plan plan, int max_launches);
+BTTB_API int bttb_timing_read(bttb_plan plan, double* total_ms, int* count);
+
+/* ---------------------------------------------------------------------------------- */
+/* Joint RRCG (Sec. 2.4 eqs. RRCG:1-8, Sec. 2.5-2.6, Sec. 2.8)                          */
+/* ---------------------------------------------------------------------------------- */
+
+/* Description of one joint inversion.  Index 0 = gravity (density), 1 = magnetic
+ * (susceptibility); both plans share nx, ny, nz, sx, sy and precision.  All vectors are
+ * dev, caller-owned, of the plans' type, and must stay alive until rrcg_destroy.
+ * State (read and written by the solver):
+ *   m[i]      [nz][nx][ny] the model m in the original space; holds the starting model
+ *             at rrcg_create (m_0 = m_apr for the paper's start) and m_k after k steps
+ *   p[i]      [nz][nx][ny] the last search direction (weighted space); zero it for a
+ *             fresh start
+ *   resid[i]  [sx][sy] the weighted residual W_d (A m - d) of the current m
+ * Inputs:
+ *   dobs[i]   [sx][sy] observed data
+ *   wd[i]     [sx][sy] diagonal of W_d = 1/sigma
+ *   wdepth[i] [nz][nx][ny] diagonal of W_depth
+ *   whard[i]  [nz][nx][ny] diagonal of W_hard, nullable (= 1)
+ *   mapr[i]   [nz][nx][ny] a-priori model, nullable (= 0)
+ * Scalars: bounds lo/hi (Sec. 2.5), alpha0, decay q and floor alpha_min (eq. regpara),
+ * lambda (fixed Lagrange parameters), eps2 (eq. WL; the paper uses 1e-9).
+ * Flags: coupled = 1 joint beta and step length (eqs. RRCG:5-6), 0 = per data set
+ *        (the stand-alone form of Sec. 3.1.1);
+ *        restart = 1 sets beta = 0 at the first CG step of every outer step;
+ *        p_norm = 1 refreshes W_L1 from the iterate (eq. WL), 2 keeps W_L1 = I;
+ *        gramian_weighted = 0 takes the Gramian directions on m (eqs. RRCG:2-3),
+ *        1 on m~ (eqs. steepestascenta/b). */
+typedef struct {
+  bttb_plan plan[2];
+  void* m[2];
+  void* p[2];
+  void* resid[2];
+  const void* dobs[2];
+  const void* wd[2];
+  const void* wdepth[2];
+  const void* whard[2];
+  const void* mapr[2];
+  double lo[2], hi[2];
+  double alpha0[2], q[2], alpha_min[2], lambda[2];
+  double eps2;
+  int coupled, restart, p_norm, gramian_weighted;
+} rrcg_desc;
+
+/* Scalar state (FP64) of a handle. */
+typedef struct {
+  double alpha[2];     /* alpha^(i) used by the next outer step */
+  double L_prev[2];    /* ||l^(i)||^2 of the last CG step (0 = none: next beta is 0) */
+  double phi[2];       /* ||W_d (A m - d)||^2 after the last outer step */
+  double threshold;    /* chi^2 threshold m + sqrt(2m), eq. (chi2) */
+  double beta[2];      /* beta and step length of the last CG step */
+  double step[2];
+  double gramian;      /* S_G(m1, m2) after the last outer step */
+  int frozen[2];       /* chi^2 met at some outer step: alpha^(i) no longer decays */
+  int k;               /* outer steps taken */
+  int converged;       /* both chi^2 tests met at the last outer step */
+  int nonfinite;       /* a NaN / Inf reached a reduction */
+} rrcg_scalars;
+
+/* Create a solver for one inversion: the scalars start at alpha = alpha0, no previous
+ * gradient, k = 0, and resid / Phi / S_G are computed from the given m.  Allocates the
+ * solver's own work vectors.  Synchronises `stream`. */
+BTTB_API int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out);
+
+/* One outer step: n_inner >= 1 CG steps at the outer step's W and alpha (RRCG:1-7, the
+ * residual taken exactly at the first and by r~ <- r~ - s A~ p after), then RRCG:8,
+ * projection onto [lo, hi], Phi^(i), the chi^2 test and the alpha update.
+ * n_inner = 1 with restart = 0 is the single loop printed in the paper.  Asynchronous:
+ * no device-to-host transfer. */
+BTTB_API int rrcg_step(rrcg_handle h, int n_inner, void* stream);
+
+/* Copy the scalar state to / from the host.  Synchronises `stream`. */
+BTTB_API int rrcg_read_scalars(rrcg_handle h, rrcg_scalars* out, void* stream);
+BTTB_API int rrcg_write_scalars(rrcg_handle h, const rrcg_scalars* in, void* stream);
+
+/* Recompute resid, Phi and S_G of the current m, e.g. after m was written to resume
+ * from a checkpoint (with rrcg_write_scalars for the scalar state). */
+BTTB_API int rrcg_refresh(rrcg_handle h, void* stream);
+
+BTTB_API int rrcg_destroy(rrcg_handle h);
+
+/* ---------------------------------------------------------------------------------- */
+
+BTTB_API const char* bttb_strerror(int status);
+BTTB_API const char* bttb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTTB_H */

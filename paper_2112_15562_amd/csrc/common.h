@@ -1,0 +1,75 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "bttb.h"
+#include "fft_engine.h"
+
+namespace bttb {
+
+// Records `msg` as the calling thread's last error and returns `status`.
+int fail(int status, const std::string& msg);
+// Maps a HIP error to BTTB_EHIP with a message naming `what`.
+int hip_fail(hipError_t e, const char* what);
+
+#define BTTB_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ::bttb::hip_fail(e_, #call); \
+  } while (0)
+
+#define BTTB_LAUNCHED(what)                              \
+  do {                                                   \
+    hipError_t e_ = hipGetLastError();                   \
+    if (e_ != hipSuccess) return ::bttb::hip_fail(e_, what); \
+  } while (0)
+
+inline void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
+
+// Radix plan for a 1-D length N (a 5-smooth multiple of 8).
+FFTDesc make_fft_desc(int N);
+// Smallest 5-smooth multiple of 8 that is >= L.
+int padded_size(int L);
+// Host table exp(-2 pi i e / N), e < N, in FP64 (argument reduced by octant symmetry).
+void twiddles_fp64(int N, double* re_im);
+
+// One operator plan (Sec. 2.7.1): eigenvalues of every layer's BCCB embedding plus
+// the scratch for one product of up to max_batch vectors.
+struct Plan {
+  int sx, sy, nx, ny, nz;
+  int Px, Py, K2;   // K2 = Py/2 + 1 (half spectrum along y)
+  int ldx, lds;     // padded row counts of the column-major intermediates (multiples of 16)
+  int precision;
+  int max_batch;
+  // launch shape
+  int col_fpb;      // column FFTs per block
+  int row_fpb;      // row-pair FFTs per block
+  int nchunk;       // layer chunks of the forward column pass
+  int nchunk_max;
+  FFTDesc fx, fy;
+  void* eig;        // complex [nz][K2][Px] of the plan's type, scaled by 1/(Px Py)
+  void* twx;        // complex [Px] of the plan's type
+  void* twy;        // complex [Py]
+  void* U;          // complex [max_batch][nz][K2][ldx]
+  void* V;          // complex [max_batch][nchunk_max][K2][lds]
+  size_t eig_bytes, scratch_bytes;
+  // optional per-kernel event timing
+  int t_cap, t_used;
+  hipEvent_t* t_ev;  // [2 * t_cap]
+  int* t_kid;        // [t_cap]
+};
+
+template <typename T>
+int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,
+               const T* winv, const T* wd, hipStream_t s);
+
+}  // namespace bttb

@@ -1,0 +1,571 @@
+// Joint RRCG on the GPU (Sec. 2.4 eqs. RRCG:1-8, Sec. 2.5 bounds, Sec. 2.6 chi^2 test,
+// Sec. 2.8 alpha schedule with fixed Lagrange parameters).
+//
+// State per data set i: the model m (original space), the search direction p (weighted
+// space), the current weights w = W_depth W_hard W_L1 and winv = 1/w, the weighted
+// residual r~ = W_d (A m - d), and the scalars (FP64, device resident).  One outer step:
+//   w, winv from m (eq. WL, eq. W)                                        k_weights
+//   repeat n_inner times:
+//     l = A~^T r~ + alpha (w m - w m_apr) + lambda l_G                    apply + k_grad
+//         l_G on m (RRCG:2-3) or on m~ = w m (steepestascenta/b)
+//     beta = sum ||l||^2 / sum ||l_prev||^2 (0 at a restart), p = l + beta p   fin_beta, k_dir
+//     q = A~ p                                                            apply
+//     s = sum (p,l) / sum (||q||^2 + (alpha + lambda) ||p||^2)            fin_step
+//     m <- m - s p / w   (m~ <- m~ - s p, RRCG:7-8);  r~ <- r~ - s q       k_update
+//   m <- clip(m, lo, hi)                                                  k_clip
+//   r~ = W_d (A m - d), Phi = ||r~||^2, chi^2 test, alpha <- max(q alpha, alpha_min)
+//   unless frozen                                                         k_resid, fin_outer
+// Dot products are accumulated in FP64 per block (fixed grid) and summed in a fixed
+// order by single-block kernels, so results are bitwise repeatable; no scalar leaves
+// the device during a step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace bttb {
+
+constexpr int RB = 256;     // threads per elementwise block
+constexpr int RGRID = 512;  // elementwise blocks (fixed, so reductions are repeatable)
+constexpr int NSLOT = 8;    // partial-sum slots
+
+// Scalar array layout (doubles).
+enum {
+  S_ALPHA = 0, S_LPREV = 2, S_PHI = 4, S_THR = 6, S_BETA = 7, S_STEP = 9, S_GRAM = 11, S_FROZEN = 12,
+  S_K = 14, S_CONV = 15, S_NONFIN = 16, S_G11 = 17, S_G22 = 18, S_G12 = 19, S_L = 20, S_PL = 22,
+  S_PP = 24, S_QQ = 26, S_COUNT = 32
+};
+
+struct Rrcg {
+  Plan* P[2];
+  int precision;
+  long long n, nd;
+  const void* dobs[2];
+  const void* wd[2];
+  const void* wdepth[2];
+  const void* whard[2];
+  const void* mapr[2];
+  double lo[2], hi[2], alpha0[2], q[2], amin[2], lam[2], eps2;
+  int coupled, restart, p_norm, gram_w;
+  void* m[2];      // caller-owned
+  void* p[2];      // caller-owned
+  void* rt[2];     // caller-owned
+  void* l[2];
+  void* w[2];
+  void* winv[2];
+  void* qv[2];
+  double* sc;  // [S_COUNT]
+  double* pb;  // [4][NSLOT][RGRID] partial sums (four independent reductions)
+};
+
+// Sum of v over the block, written to out[slot * RGRID + blockIdx.x] for each slot.
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* out) {
+  __shared__ double sh[K][RB / 64];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[k] = x;
+  }
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < RB / 64; ++w) s += sh[k][w];
+      out[k * RGRID + blockIdx.x] = s;
+    }
+  }
+}
+
+// Fixed-order sum of RGRID partials of `slot` (single block of RB threads).
+__device__ double sum_partials(const double* pb, int slot) {
+  __shared__ double sh[RB];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < RGRID; i += RB) s += pb[slot * RGRID + i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = RB / 2; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_weights(long long n, const T* m0, const T* m1, const T* ma0, const T* ma1,
+                                                const T* wz0, const T* wz1, const T* wh0, const T* wh1, double eps2,
+                                                int p_norm, int gram_w, T* w0, T* w1, T* wi0, T* wi1, double* pb) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
+    const double a = m0[j], b = m1[j];
+    double W0 = wz0[j], W1 = wz1[j];
+    if (wh0) W0 *= (double)wh0[j];
+    if (wh1) W1 *= (double)wh1[j];
+    if (p_norm == 1) {
+      const double d0 = a - (ma0 ? (double)ma0[j] : 0.0), d1 = b - (ma1 ? (double)ma1[j] : 0.0);
+      W0 *= 1.0 / pow(d0 * d0 + eps2, 0.25);
+      W1 *= 1.0 / pow(d1 * d1 + eps2, 0.25);
+    }
+    const T W0t = (T)W0, W1t = (T)W1;
+    w0[j] = W0t;
+    w1[j] = W1t;
+    wi0[j] = (T)(1.0 / (double)W0t);
+    wi1[j] = (T)(1.0 / (double)W1t);
+    const double u0 = gram_w ? (double)W0t * a : a, u1 = gram_w ? (double)W1t * b : b;
+    v[0] += u0 * u0;
+    v[1] += u1 * u1;
+    v[2] += u0 * u1;
+  }
+  block_partials<3>(v, pb);
+}
+
+__global__ void __launch_bounds__(RB) k_fin_gram(double* sc, const double* pb) {
+  const double g11 = sum_partials(pb, 0), g22 = sum_partials(pb, 1), g12 = sum_partials(pb, 2);
+  if (threadIdx.x == 0) {
+    sc[S_G11] = g11;
+    sc[S_G22] = g22;
+    sc[S_G12] = g12;
+    if (!isfinite(g11) || !isfinite(g22) || !isfinite(g12)) sc[S_NONFIN] = 1.0;
+  }
+}
+
+// l = A~^T r~ (already in l) + alpha (w m - w m_apr) + lambda l_G;  partials ||l_i||^2.
+template <typename T>
+__global__ void __launch_bounds__(RB) k_grad(long long n, T* l0, T* l1, const T* m0, const T* m1, const T* w0,
+                                             const T* w1, const T* ma0, const T* ma1, const double* sc,
+                                             double lam0, double lam1, int gram_w, double* pb) {
+  const double g11 = sc[S_G11], g22 = sc[S_G22], g12 = sc[S_G12];
+  const double al0 = sc[S_ALPHA], al1 = sc[S_ALPHA + 1];
+  double v[2] = {0.0, 0.0};
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
+    const double a = m0[j], b = m1[j], W0 = w0[j], W1 = w1[j];
+    const double u0 = gram_w ? W0 * a : a, u1 = gram_w ? W1 * b : b;
+    const double lg0 = g22 * u0 - g12 * u1, lg1 = g11 * u1 - g12 * u0;
+    const double mt0 = W0 * a, mt1 = W1 * b;
+    const double mta0 = ma0 ? W0 * (double)ma0[j] : 0.0, mta1 = ma1 ? W1 * (double)ma1[j] : 0.0;
+    const T r0 = (T)((double)l0[j] + al0 * (mt0 - mta0) + lam0 * lg0);
+    const T r1 = (T)((double)l1[j] + al1 * (mt1 - mta1) + lam1 * lg1);
+    l0[j] = r0;
+    l1[j] = r1;
+    v[0] += (double)r0 * (double)r0;
+    v[1] += (double)r1 * (double)r1;
+  }
+  block_partials<2>(v, pb);
+}
+
+__global__ void __launch_bounds__(RB) k_fin_beta(double* sc, const double* pb, int restart_now, int coupled) {
+  const double L0 = sum_partials(pb, 0), L1 = sum_partials(pb, 1);
+  if (threadIdx.x == 0) {
+    const double P0 = sc[S_LPREV], P1 = sc[S_LPREV + 1];
+    double b0, b1;
+    if (coupled) {
+      const double Lp = P0 + P1;
+      b0 = b1 = (restart_now || Lp == 0.0) ? 0.0 : (L0 + L1) / Lp;
+    } else {
+      b0 = (restart_now || P0 == 0.0) ? 0.0 : L0 / P0;
+      b1 = (restart_now || P1 == 0.0) ? 0.0 : L1 / P1;
+    }
+    sc[S_L] = L0;
+    sc[S_L + 1] = L1;
+    sc[S_BETA] = b0;
+    sc[S_BETA + 1] = b1;
+    if (!isfinite(L0) || !isfinite(L1)) sc[S_NONFIN] = 1.0;
+  }
+}
+
+// p = l + beta p; partials (p, l)_i and ||p_i||^2.
+template <typename T>
+__global__ void __launch_bounds__(RB) k_dir(long long n, const T* l0, const T* l1, T* p0, T* p1, const double* sc,
+                                            double* pb) {
+  const double b0 = sc[S_BETA], b1 = sc[S_BETA + 1];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
+    const double la = l0[j], lb = l1[j];
+    const T pa = (T)(la + b0 * (double)p0[j]);
+    const T pbv = (T)(lb + b1 * (double)p1[j]);
+    p0[j] = pa;
+    p1[j] = pbv;
+    v[0] += (double)pa * la;
+    v[1] += (double)pbv * lb;
+    v[2] += (double)pa * (double)pa;
+    v[3] += (double)pbv * (double)pbv;
+  }
+  block_partials<4>(v, pb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_sumsq2(long long n, const T* a0, const T* a1, double* pb) {
+  double v[2] = {0.0, 0.0};
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
+    const double x = a0[j], y = a1[j];
+    v[0] += x * x;
+    v[1] += y * y;
+  }
+  block_partials<2>(v, pb);
+}
+
+__global__ void __launch_bounds__(RB) k_fin_step(double* sc, const double* pb_dir, const double* pb_q, double lam0,
+                                                 double lam1, int coupled) {
+  const double pl0 = sum_partials(pb_dir, 0), pl1 = sum_partials(pb_dir, 1);
+  const double pp0 = sum_partials(pb_dir, 2), pp1 = sum_partials(pb_dir, 3);
+  const double qq0 = sum_partials(pb_q, 0), qq1 = sum_partials(pb_q, 1);
+  if (threadIdx.x == 0) {
+    const double den0 = qq0 + (sc[S_ALPHA] + lam0) * pp0;
+    const double den1 = qq1 + (sc[S_ALPHA + 1] + lam1) * pp1;
+    double s0, s1;
+    if (coupled) {
+      s0 = s1 = (pl0 + pl1) / (den0 + den1);
+    } else {
+      s0 = pl0 / den0;
+      s1 = pl1 / den1;
+    }
+    sc[S_STEP] = s0;
+    sc[S_STEP + 1] = s1;
+    sc[S_PL] = pl0; sc[S_PL + 1] = pl1;
+    sc[S_PP] = pp0; sc[S_PP + 1] = pp1;
+    sc[S_QQ] = qq0; sc[S_QQ + 1] = qq1;
+    sc[S_LPREV] = sc[S_L];
+    sc[S_LPREV + 1] = sc[S_L + 1];
+    if (!isfinite(s0) || !isfinite(s1)) sc[S_NONFIN] = 1.0;
+  }
+}
+
+// m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w); r~ <- r~ - s q; Gramian partials
+// of the new m (on m or on w m).
+template <typename T>
+__global__ void __launch_bounds__(RB) k_update(long long n, long long nd, T* m0, T* m1, const T* p0, const T* p1,
+                                               const T* w0, const T* w1, T* r0, T* r1, const T* q0, const T* q1,
+                                               const double* sc, int gram_w, double* pb) {
+  const double s0 = sc[S_STEP], s1 = sc[S_STEP + 1];
+  double v[3] = {0.0, 0.0, 0.0};
+  const long long top = n > nd ? n : nd;
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < top; j += (long long)RGRID * RB) {
+    if (j < n) {
+      const double W0 = w0[j], W1 = w1[j];
+      const T a = (T)((W0 * (double)m0[j] - s0 * (double)p0[j]) / W0);
+      const T b = (T)((W1 * (double)m1[j] - s1 * (double)p1[j]) / W1);
+      m0[j] = a;
+      m1[j] = b;
+      const double u0 = gram_w ? W0 * (double)a : (double)a, u1 = gram_w ? W1 * (double)b : (double)b;
+      v[0] += u0 * u0;
+      v[1] += u1 * u1;
+      v[2] += u0 * u1;
+    }
+    if (j < nd) {
+      r0[j] = (T)((double)r0[j] - s0 * (double)q0[j]);
+      r1[j] = (T)((double)r1[j] - s1 * (double)q1[j]);
+    }
+  }
+  block_partials<3>(v, pb);
+}
+
+// m <- clip(m, lo, hi); Gramian partials of the projected m (original space).
+template <typename T>
+__global__ void __launch_bounds__(RB) k_clip(long long n, T* m0, T* m1, double lo0, double hi0, double lo1,
+                                             double hi1, double* pb) {
+  double v[3] = {0.0, 0.0, 0.0};
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
+    const double a = fmin(fmax((double)m0[j], lo0), hi0);
+    const double b = fmin(fmax((double)m1[j], lo1), hi1);
+    const T at = (T)a, bt = (T)b;
+    m0[j] = at;
+    m1[j] = bt;
+    v[0] += (double)at * (double)at;
+    v[1] += (double)bt * (double)bt;
+    v[2] += (double)at * (double)bt;
+  }
+  block_partials<3>(v, pb);
+}
+
+// r~ = W_d (A m - d) (A m already in r); partials ||r~_i||^2.
+template <typename T>
+__global__ void __launch_bounds__(RB) k_resid(long long nd, T* r0, T* r1, const T* d0, const T* d1, const T* wd0,
+                                              const T* wd1, double* pb) {
+  double v[2] = {0.0, 0.0};
+  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < nd; j += (long long)RGRID * RB) {
+    const T a = (T)((double)wd0[j] * ((double)r0[j] - (double)d0[j]));
+    const T b = (T)((double)wd1[j] * ((double)r1[j] - (double)d1[j]));
+    r0[j] = a;
+    r1[j] = b;
+    v[0] += (double)a * (double)a;
+    v[1] += (double)b * (double)b;
+  }
+  block_partials<2>(v, pb);
+}
+
+// Phi, S_G, and (advance = 1) the chi^2 test, freeze flags and alpha schedule.
+__global__ void __launch_bounds__(RB) k_fin_outer(double* sc, const double* pb_gram, const double* pb_res,
+                                                  double q0, double q1, double amin0, double amin1, int advance) {
+  const double g11 = sum_partials(pb_gram, 0), g22 = sum_partials(pb_gram, 1), g12 = sum_partials(pb_gram, 2);
+  const double f0 = sum_partials(pb_res, 0), f1 = sum_partials(pb_res, 1);
+  if (threadIdx.x == 0) {
+    sc[S_PHI] = f0;
+    sc[S_PHI + 1] = f1;
+    sc[S_GRAM] = g11 * g22 - g12 * g12;
+    if (!isfinite(f0) || !isfinite(f1) || !isfinite(g11) || !isfinite(g22)) sc[S_NONFIN] = 1.0;
+    if (advance) {
+      const double thr = sc[S_THR];
+      const bool p0 = f0 <= thr, p1 = f1 <= thr;
+      const bool fr0 = sc[S_FROZEN] != 0.0 || p0, fr1 = sc[S_FROZEN + 1] != 0.0 || p1;
+      sc[S_FROZEN] = fr0 ? 1.0 : 0.0;
+      sc[S_FROZEN + 1] = fr1 ? 1.0 : 0.0;
+      sc[S_CONV] = (p0 && p1) ? 1.0 : 0.0;
+      if (!fr0) sc[S_ALPHA] = fmax(q0 * sc[S_ALPHA], amin0);
+      if (!fr1) sc[S_ALPHA + 1] = fmax(q1 * sc[S_ALPHA + 1], amin1);
+      sc[S_K] += 1.0;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------
+template <typename T>
+static int outer_update(Rrcg* h, hipStream_t s, int advance) {
+  T** m = reinterpret_cast<T**>(h->m);
+  T** rt = reinterpret_cast<T**>(h->rt);
+  double* pbg = h->pb;
+  double* pbr = h->pb + NSLOT * RGRID;
+  if (advance) {
+    hipLaunchKernelGGL(k_clip<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1], h->lo[0], h->hi[0], h->lo[1],
+                       h->hi[1], pbg);
+  } else {
+    // Gramian partials only (no projection): clip to +-inf
+    hipLaunchKernelGGL(k_clip<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1], -HUGE_VAL, HUGE_VAL, -HUGE_VAL,
+                       HUGE_VAL, pbg);
+  }
+  BTTB_LAUNCHED("k_clip");
+  for (int i = 0; i < 2; ++i) {
+    int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, m[i], 0, rt[i], 0, nullptr, nullptr, s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_resid<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, rt[0], rt[1],
+                     static_cast<const T*>(h->dobs[0]), static_cast<const T*>(h->dobs[1]),
+                     static_cast<const T*>(h->wd[0]), static_cast<const T*>(h->wd[1]), pbr);
+  BTTB_LAUNCHED("k_resid");
+  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(RB), 0, s, h->sc, pbg, pbr, h->q[0], h->q[1], h->amin[0],
+                     h->amin[1], advance);
+  BTTB_LAUNCHED("k_fin_outer");
+  return BTTB_OK;
+}
+
+template <typename T>
+static int step_impl(Rrcg* h, int n_inner, hipStream_t s) {
+  T** m = reinterpret_cast<T**>(h->m);
+  T** p = reinterpret_cast<T**>(h->p);
+  T** l = reinterpret_cast<T**>(h->l);
+  T** w = reinterpret_cast<T**>(h->w);
+  T** wi = reinterpret_cast<T**>(h->winv);
+  T** rt = reinterpret_cast<T**>(h->rt);
+  T** qv = reinterpret_cast<T**>(h->qv);
+  const T* ma0 = static_cast<const T*>(h->mapr[0]);
+  const T* ma1 = static_cast<const T*>(h->mapr[1]);
+  double* pb0 = h->pb;
+  double* pb1 = h->pb + NSLOT * RGRID;
+  double* pb2 = h->pb + 2 * NSLOT * RGRID;
+  double* pb3 = h->pb + 3 * NSLOT * RGRID;
+  hipLaunchKernelGGL(k_weights<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1], ma0, ma1,
+                     static_cast<const T*>(h->wdepth[0]), static_cast<const T*>(h->wdepth[1]),
+                     static_cast<const T*>(h->whard[0]), static_cast<const T*>(h->whard[1]), h->eps2, h->p_norm,
+                     h->gram_w, w[0], w[1], wi[0], wi[1], pb0);
+  BTTB_LAUNCHED("k_weights");
+  hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, pb0);
+  BTTB_LAUNCHED("k_fin_gram");
+  for (int j = 0; j < n_inner; ++j) {
+    for (int i = 0; i < 2; ++i) {
+      int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i],
+                             static_cast<const T*>(h->wd[i]), s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_grad<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], m[0], m[1], w[0], w[1], ma0, ma1,
+                       h->sc, h->lam[0], h->lam[1], h->gram_w, pb1);
+    BTTB_LAUNCHED("k_grad");
+    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(RB), 0, s, h->sc, pb1, (j == 0 && h->restart) ? 1 : 0,
+                       h->coupled);
+    BTTB_LAUNCHED("k_fin_beta");
+    hipLaunchKernelGGL(k_dir<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], p[0], p[1], h->sc, pb2);
+    BTTB_LAUNCHED("k_dir");
+    for (int i = 0; i < 2; ++i) {
+      int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i],
+                             static_cast<const T*>(h->wd[i]), s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_sumsq2<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, qv[0], qv[1], pb3);
+    BTTB_LAUNCHED("k_sumsq2");
+    hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(RB), 0, s, h->sc, pb2, pb3, h->lam[0], h->lam[1], h->coupled);
+    BTTB_LAUNCHED("k_fin_step");
+    hipLaunchKernelGGL(k_update<T>, dim3(RGRID), dim3(RB), 0, s, h->n, h->nd, m[0], m[1], p[0], p[1], w[0], w[1],
+                       rt[0], rt[1], qv[0], qv[1], h->sc, h->gram_w, pb0);
+    BTTB_LAUNCHED("k_update");
+    hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, pb0);
+    BTTB_LAUNCHED("k_fin_gram");
+  }
+  return outer_update<T>(h, s, 1);
+}
+
+static void free_rrcg(Rrcg* h) {
+  for (int i = 0; i < 2; ++i) {
+    dfree(h->l[i]); dfree(h->w[i]); dfree(h->winv[i]); dfree(h->qv[i]);
+  }
+  dfree(h->sc);
+  dfree(h->pb);
+  delete h;
+}
+
+}  // namespace bttb
+
+using namespace bttb;
+
+extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
+  if (!d || !out) return fail(BTTB_EINVAL, "rrcg_create: NULL argument");
+  *out = nullptr;
+  Plan* P0 = reinterpret_cast<Plan*>(d->plan[0]);
+  Plan* P1 = reinterpret_cast<Plan*>(d->plan[1]);
+  if (!P0 || !P1) return fail(BTTB_EINVAL, "rrcg_create: NULL plan");
+  if (P0->sx != P1->sx || P0->sy != P1->sy || P0->nx != P1->nx || P0->ny != P1->ny || P0->nz != P1->nz ||
+      P0->precision != P1->precision)
+    return fail(BTTB_ESTATE, "rrcg_create: the two plans differ in grid or precision");
+  const size_t es = P0->precision == BTTB_F64 ? 8 : 4;
+  for (int i = 0; i < 2; ++i) {
+    if (!d->m[i] || !d->p[i] || !d->resid[i] || !d->dobs[i] || !d->wd[i] || !d->wdepth[i])
+      return fail(BTTB_EINVAL, "rrcg_create: NULL vector");
+    const void* vs[8] = {d->m[i], d->p[i], d->resid[i], d->dobs[i], d->wd[i], d->wdepth[i], d->whard[i],
+                         d->mapr[i]};
+    for (const void* v : vs)
+      if (v && !aligned(v, es)) return fail(BTTB_EINVAL, "rrcg_create: misaligned vector");
+    if (!(d->lo[i] <= d->hi[i])) return fail(BTTB_EINVAL, "rrcg_create: lo > hi");
+    if (!(d->alpha0[i] >= 0) || !(d->q[i] > 0) || !(d->lambda[i] >= 0) || !(d->alpha_min[i] >= 0))
+      return fail(BTTB_EINVAL, "rrcg_create: alpha0, alpha_min, lambda must be >= 0 and q > 0");
+  }
+  if (!(d->eps2 > 0)) return fail(BTTB_EINVAL, "rrcg_create: eps2 must be > 0");
+  if (d->p_norm != 1 && d->p_norm != 2) return fail(BTTB_EINVAL, "rrcg_create: p_norm must be 1 or 2");
+  Rrcg* h = new (std::nothrow) Rrcg{};
+  if (!h) return fail(BTTB_ENOMEM, "rrcg_create: host allocation failed");
+  h->P[0] = P0;
+  h->P[1] = P1;
+  h->precision = P0->precision;
+  h->n = (long long)P0->nx * P0->ny * P0->nz;
+  h->nd = (long long)P0->sx * P0->sy;
+  for (int i = 0; i < 2; ++i) {
+    h->m[i] = d->m[i]; h->p[i] = d->p[i]; h->rt[i] = d->resid[i];
+    h->dobs[i] = d->dobs[i]; h->wd[i] = d->wd[i]; h->wdepth[i] = d->wdepth[i];
+    h->whard[i] = d->whard[i]; h->mapr[i] = d->mapr[i];
+    h->lo[i] = d->lo[i]; h->hi[i] = d->hi[i]; h->alpha0[i] = d->alpha0[i]; h->q[i] = d->q[i];
+    h->amin[i] = d->alpha_min[i]; h->lam[i] = d->lambda[i];
+  }
+  h->eps2 = d->eps2;
+  h->coupled = d->coupled ? 1 : 0;
+  h->restart = d->restart ? 1 : 0;
+  h->p_norm = d->p_norm;
+  h->gram_w = d->gramian_weighted ? 1 : 0;
+  const size_t nb = (size_t)h->n * es, db = (size_t)h->nd * es;
+  bool ok = true;
+  for (int i = 0; i < 2 && ok; ++i) {
+    ok = hipMalloc(&h->l[i], nb) == hipSuccess && hipMalloc(&h->w[i], nb) == hipSuccess &&
+         hipMalloc(&h->winv[i], nb) == hipSuccess && hipMalloc(&h->qv[i], db) == hipSuccess;
+  }
+  ok = ok && hipMalloc((void**)&h->sc, S_COUNT * sizeof(double)) == hipSuccess &&
+       hipMalloc((void**)&h->pb, 4 * NSLOT * RGRID * sizeof(double)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_rrcg(h);
+    return fail(BTTB_ENOMEM, "rrcg_create: device allocation failed");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc = BTTB_OK;
+  double sc[S_COUNT] = {0};
+  sc[S_ALPHA] = d->alpha0[0];
+  sc[S_ALPHA + 1] = d->alpha0[1];
+  sc[S_THR] = (double)h->nd + std::sqrt(2.0 * (double)h->nd);
+  if (rc == BTTB_OK && hipMemcpyAsync(h->sc, sc, sizeof(sc), hipMemcpyHostToDevice, s) != hipSuccess)
+    rc = fail(BTTB_EHIP, "rrcg_create: scalar upload");
+  if (rc == BTTB_OK)
+    rc = h->precision == BTTB_F64 ? outer_update<double>(h, s, 0) : outer_update<float>(h, s, 0);
+  if (rc == BTTB_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(BTTB_EHIP, "rrcg_create: synchronize");
+  if (rc != BTTB_OK) {
+    free_rrcg(h);
+    return rc;
+  }
+  *out = reinterpret_cast<rrcg_handle>(h);
+  return BTTB_OK;
+}
+
+extern "C" int rrcg_step(rrcg_handle hh, int n_inner, void* stream) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_step: NULL handle");
+  if (n_inner < 1) return fail(BTTB_EINVAL, "rrcg_step: n_inner must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->precision == BTTB_F64 ? step_impl<double>(h, n_inner, s) : step_impl<float>(h, n_inner, s);
+}
+
+extern "C" int rrcg_refresh(rrcg_handle hh, void* stream) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_refresh: NULL handle");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->precision == BTTB_F64 ? outer_update<double>(h, s, 0) : outer_update<float>(h, s, 0);
+}
+
+extern "C" int rrcg_read_scalars(rrcg_handle hh, rrcg_scalars* out, void* stream) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h || !out) return fail(BTTB_EINVAL, "rrcg_read_scalars: NULL argument");
+  double sc[S_COUNT];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BTTB_HIP(hipMemcpyAsync(sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+  BTTB_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < 2; ++i) {
+    out->alpha[i] = sc[S_ALPHA + i];
+    out->L_prev[i] = sc[S_LPREV + i];
+    out->phi[i] = sc[S_PHI + i];
+    out->beta[i] = sc[S_BETA + i];
+    out->step[i] = sc[S_STEP + i];
+    out->frozen[i] = sc[S_FROZEN + i] != 0.0;
+  }
+  out->threshold = sc[S_THR];
+  out->gramian = sc[S_GRAM];
+  out->k = (int)sc[S_K];
+  out->converged = sc[S_CONV] != 0.0;
+  out->nonfinite = sc[S_NONFIN] != 0.0;
+  return BTTB_OK;
+}
+
+extern "C" int rrcg_write_scalars(rrcg_handle hh, const rrcg_scalars* in, void* stream) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h || !in) return fail(BTTB_EINVAL, "rrcg_write_scalars: NULL argument");
+  double sc[S_COUNT];
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BTTB_HIP(hipMemcpyAsync(sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+  BTTB_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < 2; ++i) {
+    sc[S_ALPHA + i] = in->alpha[i];
+    sc[S_LPREV + i] = in->L_prev[i];
+    sc[S_PHI + i] = in->phi[i];
+    sc[S_BETA + i] = in->beta[i];
+    sc[S_STEP + i] = in->step[i];
+    sc[S_FROZEN + i] = in->frozen[i] ? 1.0 : 0.0;
+  }
+  sc[S_GRAM] = in->gramian;
+  sc[S_K] = (double)in->k;
+  sc[S_CONV] = in->converged ? 1.0 : 0.0;
+  sc[S_NONFIN] = in->nonfinite ? 1.0 : 0.0;
+  BTTB_HIP(hipMemcpyAsync(h->sc, sc, sizeof(sc), hipMemcpyHostToDevice, s));
+  BTTB_HIP(hipStreamSynchronize(s));
+  return BTTB_OK;
+}
+
+extern "C" int rrcg_destroy(rrcg_handle hh) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (h) free_rrcg(h);
+  return BTTB_OK;
+}

@@ -1,0 +1,187 @@
+"""GPU BTTB sensitivity operators (Sec. 2.7.1) behind the C ABI.
+
+Every product runs in the HIP library; this module only checks tensors and passes
+pointers and the current HIP stream.  Device memory comes from PyTorch.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+GRAVITY = L.BTTB_GRAVITY
+MAGNETIC = L.BTTB_MAGNETIC
+_DT = {torch.float64: L.BTTB_F64, torch.float32: L.BTTB_F32}
+
+
+def _stream(device: torch.device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _geometry(g) -> L.Geometry:
+    get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
+    return L.Geometry(int(get("sx")), int(get("sy")), int(get("nx")), int(get("ny")), int(get("nz")),
+                      float(get("dx")), float(get("dy")), float(get("dz")), float(get("h")),
+                      float(get("top")), float(get("incl")), float(get("decl")), float(get("field")))
+
+
+def prism_kernels(kind: int, geometry, device="cuda") -> torch.Tensor:
+    """Kernel array T [nz][sx+nx-1][sy+ny-1] (FP64) of the gravity or magnetic operator,
+    evaluated on the GPU from the closed-form prism responses (Sec. 2.1).  `geometry`
+    has sx, sy, nx, ny, nz, dx, dy, dz, h, top, incl, decl, field."""
+    g = _geometry(geometry)
+    dev = torch.device(device)
+    out = torch.empty((g.nz, g.sx + g.nx - 1, g.sy + g.ny - 1), dtype=torch.float64, device=dev)
+    L.check(L.lib().bttb_prism_kernels(int(kind), C.byref(g), _ptr(out), C.c_void_p(_stream(dev))),
+            "bttb_prism_kernels")
+    return out
+
+
+class Operator:
+    """y = A x and z = A^T r for one data set (gravity or magnetic) on one GPU.
+
+    kernels: FP64 tensor [nz][sx+nx-1][sy+ny-1] (host or device), T_(r) of Sec. 2.7.1.
+    stations: (sx, sy); the prism grid follows from the kernel array's shape.
+    dtype: torch.float64 (plain FP64 path) or torch.float32 (FFTs and products in FP32,
+    eigenvalues computed in FP64 and rounded).
+    """
+
+    def __init__(self, kernels: torch.Tensor, stations: Sequence[int], dtype=torch.float64,
+                 max_batch: int = 1, device="cuda"):
+        if dtype not in _DT:
+            raise TypeError("dtype must be torch.float32 or torch.float64")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        k = torch.as_tensor(kernels).to(device=self.device, dtype=torch.float64).contiguous()
+        if k.dim() != 3:
+            raise ValueError("kernels must be [nz][sx+nx-1][sy+ny-1]")
+        sx, sy = int(stations[0]), int(stations[1])
+        nz, Lx, Ly = k.shape
+        nx, ny = Lx - sx + 1, Ly - sy + 1
+        if nx < 1 or ny < 1:
+            raise ValueError("kernel array smaller than the station grid")
+        self.sx, self.sy, self.nx, self.ny, self.nz = sx, sy, nx, ny, nz
+        self.dtype = dtype
+        self.max_batch = int(max_batch)
+        self._plan = C.c_void_p()
+        L.check(L.lib().bttb_setup(_ptr(k), sx, sy, nx, ny, nz, _DT[dtype], self.max_batch,
+                                   C.c_void_p(_stream(self.device)), C.byref(self._plan)), "bttb_setup")
+
+    @classmethod
+    def from_geometry(cls, kind: int, geometry, dtype=torch.float64, max_batch: int = 1, device="cuda"):
+        T = prism_kernels(kind, geometry, device)
+        g = _geometry(geometry)
+        return cls(T, (g.sx, g.sy), dtype=dtype, max_batch=max_batch, device=device)
+
+    # ------------------------------------------------------------------------------
+    @property
+    def plan(self) -> C.c_void_p:
+        if not self._plan:
+            raise RuntimeError("operator is closed")
+        return self._plan
+
+    @property
+    def model_shape(self):
+        return (self.nz, self.nx, self.ny)
+
+    @property
+    def data_shape(self):
+        return (self.sx, self.sy)
+
+    def info(self) -> dict:
+        d = L.PlanDesc()
+        L.check(L.lib().bttb_plan_info(self.plan, C.byref(d)), "bttb_plan_info")
+        return {f: getattr(d, f) for f, _ in L.PlanDesc._fields_}
+
+    def set_launch(self, col_fft_per_block: int = 0, row_fft_per_block: int = 0, layer_chunks: int = 0):
+        L.check(L.lib().bttb_set_launch(self.plan, col_fft_per_block, row_fft_per_block, layer_chunks),
+                "bttb_set_launch")
+
+    def timing_enable(self, max_launches: int) -> None:
+        """Record HIP events around each product kernel (max_launches kernels)."""
+        L.check(L.lib().bttb_timing_enable(self.plan, int(max_launches)), "bttb_timing_enable")
+
+    def timing_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last read; synchronises."""
+        tot = (C.c_double * L.NKERNELS)()
+        cnt = (C.c_int * L.NKERNELS)()
+        L.check(L.lib().bttb_timing_read(self.plan, tot, cnt), "bttb_timing_read")
+        return {L.KERNEL_NAMES[k]: (tot[k], cnt[k]) for k in range(L.NKERNELS)}
+
+    def eigenvalues(self) -> torch.Tensor:
+        """Copy of the stored eigenvalues, complex [nz][Py/2+1][Px], scaled by 1/(Px Py)."""
+        info = self.info()
+        K2 = info["Py"] // 2 + 1
+        out = torch.empty(self.nz * K2 * info["Px"] * 2, dtype=self.dtype, device=self.device)
+        L.check(L.lib().bttb_plan_eigenvalues(self.plan, _ptr(out), C.c_void_p(_stream(self.device))),
+                "bttb_plan_eigenvalues")
+        cplx = torch.complex128 if self.dtype == torch.float64 else torch.complex64
+        return out.view(cplx).view(self.nz, K2, info["Px"])
+
+    # ------------------------------------------------------------------------------
+    def _check_vec(self, t: torch.Tensor, tail, name: str) -> int:
+        if not isinstance(t, torch.Tensor) or t.device != self.device or t.dtype != self.dtype:
+            raise TypeError(f"{name} must be a {self.dtype} tensor on {self.device}")
+        if tuple(t.shape[-len(tail):]) != tuple(tail):
+            raise ValueError(f"{name} must end with shape {tuple(tail)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        b = 1
+        for s in t.shape[:-len(tail)]:
+            b *= int(s)
+        return b
+
+    def apply(self, op: int, x: torch.Tensor, winv: Optional[torch.Tensor] = None,
+              wd: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        tin, tout = ((self.model_shape, self.data_shape) if op == L.BTTB_OP_FORWARD
+                     else (self.data_shape, self.model_shape))
+        batch = self._check_vec(x, tin, "input")
+        if winv is not None:
+            self._check_vec(winv, self.model_shape, "winv")
+        if wd is not None:
+            self._check_vec(wd, self.data_shape, "wd")
+        lead = tuple(x.shape[:-len(tin)])
+        if out is None:
+            out = torch.empty(lead + tuple(tout), dtype=self.dtype, device=self.device)
+        elif self._check_vec(out, tout, "out") != batch:
+            raise ValueError("out batch does not match the input batch")
+        nin = 1
+        for s in tin:
+            nin *= s
+        nout = 1
+        for s in tout:
+            nout *= s
+        if batch > 0:
+            L.check(L.lib().bttb_apply(self.plan, op, batch, _ptr(x), nin, _ptr(out), nout, _ptr(winv),
+                                       _ptr(wd), C.c_void_p(_stream(self.device))), "bttb_apply")
+        return out
+
+    def matvec(self, x, winv=None, wd=None, out=None):
+        """A x (or W_d A (winv . x)); x [..., nz, nx, ny] -> [..., sx, sy]."""
+        return self.apply(L.BTTB_OP_FORWARD, x, winv, wd, out)
+
+    def rmatvec(self, r, winv=None, wd=None, out=None):
+        """A^T r (or winv . A^T (W_d . r)); r [..., sx, sy] -> [..., nz, nx, ny]."""
+        return self.apply(L.BTTB_OP_ADJOINT, r, winv, wd, out)
+
+    def close(self):
+        if self._plan:
+            torch.cuda.synchronize(self.device)
+            L.lib().bttb_destroy(self._plan)
+            self._plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None):
+                L.lib().bttb_destroy(self._plan)
+                self._plan = C.c_void_p()
+        except Exception:
+            pass

@@ -1,0 +1,158 @@
+"""Joint RRCG solver (Sec. 2.4-2.8) behind the C ABI.
+
+The solver state vectors m, p and the residual are PyTorch tensors owned here; every
+step runs in the HIP library (rrcg_step) with all scalars kept on the device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+from .operator import Operator, _ptr, _stream
+
+
+def _pair(v):
+    if isinstance(v, (list, tuple)):
+        return (float(v[0]), float(v[1]))
+    return (float(v), float(v))
+
+
+class JointRRCG:
+    """Joint gravity-magnetic inversion with L1 reweighting and the Gramian constraint.
+
+    ops: (gravity operator, magnetic operator) with the same grids and dtype.
+    dobs, wd: [sx][sy] tensors per data set (wd = 1/sigma); wdepth (and optional whard,
+    mapr): [nz][nx][ny].  m0: starting models (default m_apr, or zeros).
+    """
+
+    def __init__(self, ops: Sequence[Operator], dobs, wd, wdepth, whard=None, mapr=None, *,
+                 lo=-math.inf, hi=math.inf, alpha0=20000.0, q=0.95, alpha_min=0.0, lam=0.0,
+                 eps2=1e-9, coupled=True, restart=True, p_norm=1, gramian="original", m0=None):
+        self.ops = tuple(ops)
+        o = self.ops[0]
+        self.dtype, self.device = o.dtype, o.device
+        conv = lambda t: None if t is None else torch.as_tensor(t).to(self.device, self.dtype).contiguous()
+        self.dobs = [conv(x) for x in dobs]
+        self.wd = [conv(x) for x in wd]
+        self.wdepth = [conv(x) for x in wdepth]
+        self.whard = [conv(x) for x in whard] if whard is not None else [None, None]
+        self.mapr = [conv(x) for x in mapr] if mapr is not None else [None, None]
+        shape = o.model_shape
+        if m0 is not None:
+            self.m = [conv(x).clone() for x in m0]
+        elif mapr is not None:
+            self.m = [x.clone() for x in self.mapr]
+        else:
+            self.m = [torch.zeros(shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.p = [torch.zeros(shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.resid = [torch.empty(o.data_shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        for t in self.dobs + self.wd + self.resid:
+            if tuple(t.shape) != tuple(o.data_shape):
+                raise ValueError("data vectors must be [sx][sy]")
+        for t in self.wdepth + [x for x in self.whard + self.mapr if x is not None] + self.m:
+            if tuple(t.shape) != tuple(shape):
+                raise ValueError("model vectors must be [nz][nx][ny]")
+        d = L.RrcgDesc()
+        for i in range(2):
+            d.plan[i] = self.ops[i].plan.value
+            d.m[i] = self.m[i].data_ptr()
+            d.p[i] = self.p[i].data_ptr()
+            d.resid[i] = self.resid[i].data_ptr()
+            d.dobs[i] = self.dobs[i].data_ptr()
+            d.wd[i] = self.wd[i].data_ptr()
+            d.wdepth[i] = self.wdepth[i].data_ptr()
+            d.whard[i] = self.whard[i].data_ptr() if self.whard[i] is not None else None
+            d.mapr[i] = self.mapr[i].data_ptr() if self.mapr[i] is not None else None
+        d.lo[:] = _pair(lo)
+        d.hi[:] = _pair(hi)
+        d.alpha0[:] = _pair(alpha0)
+        d.q[:] = _pair(q)
+        d.alpha_min[:] = _pair(alpha_min)
+        d.lambda_[:] = _pair(lam)
+        d.eps2 = float(eps2)
+        d.coupled = int(bool(coupled))
+        d.restart = int(bool(restart))
+        d.p_norm = int(p_norm)
+        d.gramian_weighted = 1 if gramian == "weighted" else 0
+        self._h = C.c_void_p()
+        L.check(L.lib().rrcg_create(C.byref(d), C.c_void_p(self._stream()), C.byref(self._h)), "rrcg_create")
+
+    def _stream(self) -> int:
+        return _stream(self.device)
+
+    def step(self, n_inner: int = 1) -> None:
+        """One outer step (asynchronous)."""
+        L.check(L.lib().rrcg_step(self._h, int(n_inner), C.c_void_p(self._stream())), "rrcg_step")
+
+    def scalars(self) -> dict:
+        s = L.RrcgScalars()
+        L.check(L.lib().rrcg_read_scalars(self._h, C.byref(s), C.c_void_p(self._stream())), "rrcg_read_scalars")
+        return dict(alpha=list(s.alpha), L_prev=list(s.L_prev), phi=list(s.phi), threshold=s.threshold,
+                    beta=list(s.beta), step=list(s.step), gramian=s.gramian, frozen=[bool(x) for x in s.frozen],
+                    k=s.k, converged=bool(s.converged), nonfinite=bool(s.nonfinite))
+
+    def set_scalars(self, **kw) -> None:
+        s = L.RrcgScalars()
+        L.check(L.lib().rrcg_read_scalars(self._h, C.byref(s), C.c_void_p(self._stream())), "rrcg_read_scalars")
+        for k, v in kw.items():
+            if k in ("alpha", "L_prev", "phi", "beta", "step"):
+                getattr(s, k)[:] = [float(x) for x in v]
+            elif k == "frozen":
+                s.frozen[:] = [int(bool(x)) for x in v]
+            elif k in ("k", "converged", "nonfinite"):
+                setattr(s, k, int(v))
+            elif k == "gramian":
+                s.gramian = float(v)
+            else:
+                raise KeyError(k)
+        L.check(L.lib().rrcg_write_scalars(self._h, C.byref(s), C.c_void_p(self._stream())), "rrcg_write_scalars")
+
+    def refresh(self) -> None:
+        L.check(L.lib().rrcg_refresh(self._h, C.c_void_p(self._stream())), "rrcg_refresh")
+
+    def run(self, n_outer: int, n_inner: int = 1, stop_on_chi2: bool = False, log=None):
+        """n_outer outer steps.  With stop_on_chi2 (or a log callback) the scalars are read
+        once per outer step; otherwise the whole run is enqueued without host reads."""
+        for _ in range(n_outer):
+            self.step(n_inner)
+            if stop_on_chi2 or log is not None:
+                sc = self.scalars()
+                if log is not None:
+                    log(sc)
+                if sc["nonfinite"]:
+                    raise L.BTTBError(L.BTTB_ENAN, "JointRRCG.run", "non-finite value in a reduction")
+                if stop_on_chi2 and sc["converged"]:
+                    break
+        return self.m
+
+    def state_dict(self) -> dict:
+        return dict(m=[x.clone() for x in self.m], p=[x.clone() for x in self.p], scalars=self.scalars())
+
+    def load_state_dict(self, st: dict) -> None:
+        for i in range(2):
+            self.m[i].copy_(st["m"][i])
+            self.p[i].copy_(st["p"][i])
+        sc = dict(st["scalars"])
+        sc.pop("threshold", None)
+        self.set_scalars(**sc)
+        self.refresh()
+        # keep the recorded Phi / S_G of the checkpoint
+        self.set_scalars(phi=st["scalars"]["phi"], gramian=st["scalars"]["gramian"])
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize(self.device)
+            L.lib().rrcg_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                L.lib().rrcg_destroy(self._h)
+                self._h = C.c_void_p()
+        except Exception:
+            pass

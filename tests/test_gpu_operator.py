@@ -1,0 +1,250 @@
+"""GPU BTTB products through the C ABI vs the FP64 oracle (run on an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bttb as obttb
+from oracle import dft as odft
+from oracle import prism as oprism
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2112_15562_amd as pk
+    assert torch.cuda.is_available()
+    return pk
+
+
+def relerr(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def ogeom(g: synth.Grid) -> oprism.Geometry:
+    return oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+RAGGED = synth.Grid(7, 9, 11, 5, 3, 40.0, 30.0, 25.0, decl=20.0)
+TINY = synth.Grid(1, 1, 1, 1, 1, 50.0, 50.0, 50.0)
+ODD = synth.Grid(3, 5, 2, 7, 2, 30.0, 20.0, 10.0, h=2.0, top=5.0, incl=40.0, decl=-30.0)
+
+
+# ------------------------------------------------------------------------------------
+# setup transform: eigenvalues = brute-force DFT2 of the circular kernel array
+# ------------------------------------------------------------------------------------
+@pytest.mark.parametrize("L", [(24, 24), (17, 40), (45, 48), (80, 33), (120, 200), (250, 300)])
+def test_eigenvalues_equal_bruteforce_dft(pk, L):
+    Lx, Ly = L
+    sx, sy = (Lx + 1) // 2, (Ly + 1) // 2
+    nx, ny = Lx - sx + 1, Ly - sy + 1
+    nz = 2
+    rng = np.random.default_rng(Lx * 1000 + Ly)
+    T = rng.standard_normal((nz, Lx, Ly))
+    op = pk.Operator(dev(T), (sx, sy), dtype=torch.float64)
+    info = op.info()
+    Px, Py = info["Px"], info["Py"]
+    assert Px % 8 == 0 and Py % 8 == 0 and Px >= Lx and Py >= Ly
+    eig = op.eigenvalues().cpu().numpy()
+    for r in range(nz):
+        C = np.zeros((Px, Py))
+        for i in range(Lx):
+            for j in range(Ly):
+                C[(i - (nx - 1)) % Px, (j - (ny - 1)) % Py] = T[r, i, j]
+        ref = odft.dft2(C)[:, : Py // 2 + 1] / (Px * Py)   # [Px][K2]
+        got = eig[r].T                                    # stored [K2][Px]
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    op.close()
+
+
+# ------------------------------------------------------------------------------------
+# prism kernel generator vs the oracle's closed forms
+# ------------------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, synth.MID])
+def test_prism_kernels_match_oracle(pk, g):
+    for kind in (pk.GRAVITY, pk.MAGNETIC):
+        got = host(pk.prism_kernels(kind, g))
+        ref = obttb.kernel_array(kind, ogeom(g))
+        assert got.shape == ref.shape
+        # the 8-corner sums cancel for distant and deep cells, leaving rounding of the size
+        # of the corner terms: the bound is relative to the array's largest (near) entry
+        assert np.abs(got - ref).max() <= 4e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------------------------
+# products vs the dense oracle (small grids, GPU-generated kernels end to end)
+# ------------------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, TINY])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_products_match_dense_oracle(pk, g, dtype):
+    og = ogeom(g)
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    rho, kap = synth.uniform_models(g, 1, 0)
+    rough = synth.normal_like(g.data_shape, 1, 1)
+    for kind, m in ((pk.GRAVITY, rho), (pk.MAGNETIC, kap)):
+        A = oprism.dense_matrix(kind, og)
+        op = pk.Operator.from_geometry(kind, g, dtype=dtype)
+        y = host(op.matvec(dev(m, dtype)))
+        y_ref = (A @ m.ravel()).reshape(g.data_shape)
+        assert relerr(y, y_ref) <= tol
+        # transpose on a smooth (data-like) and a rough residual
+        for r in (y_ref / np.abs(y_ref).max(), rough):
+            z = host(op.rmatvec(dev(r, dtype)))
+            z_ref = (A.T @ r.ravel()).reshape(g.model_shape)
+            assert relerr(z, z_ref) <= tol
+        op.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_weighted_and_batched_products(pk, dtype):
+    g = synth.SMALL
+    og = ogeom(g)
+    tol = F64_TOL if dtype == torch.float64 else F32_TOL
+    r = synth.rng(1, 7)
+    B = 3
+    x = r.uniform(0, 1, (B,) + g.model_shape)
+    v = r.standard_normal((B,) + g.data_shape)
+    winv = r.uniform(0.5, 2.0, g.model_shape)
+    wd = r.uniform(0.5, 2.0, g.data_shape)
+    for kind in (pk.GRAVITY, pk.MAGNETIC):
+        A = oprism.dense_matrix(kind, og)
+        At = np.diag(wd.ravel()) @ A @ np.diag(winv.ravel())
+        op = pk.Operator.from_geometry(kind, g, dtype=dtype, max_batch=2)   # batch 3 runs in 2 slices
+        y = host(op.matvec(dev(x, dtype), winv=dev(winv, dtype), wd=dev(wd, dtype)))
+        z = host(op.rmatvec(dev(v, dtype), winv=dev(winv, dtype), wd=dev(wd, dtype)))
+        for b in range(B):
+            assert relerr(y[b], (At @ x[b].ravel()).reshape(g.data_shape)) <= tol
+            assert relerr(z[b], (At.T @ v[b].ravel()).reshape(g.model_shape)) <= tol
+            # a batch member is computed exactly as a single call
+            ys = host(op.matvec(dev(x[b], dtype), winv=dev(winv, dtype), wd=dev(wd, dtype)))
+            assert np.array_equal(ys, y[b])
+        op.close()
+
+
+# ------------------------------------------------------------------------------------
+# larger grids vs the oracle's FFT2 products (oracle kernels fed to the GPU setup)
+# ------------------------------------------------------------------------------------
+_REF_CACHE = {}
+
+
+def _fft_refs(g, kind, m, rough):
+    """Oracle kernel array and FFT2 products, computed once per grid and kind."""
+    key = (g, kind)
+    if key not in _REF_CACHE:
+        T = obttb.kernel_array(kind, ogeom(g))
+        y = obttb.fft_matvec(T, m, g.sx, g.sy, workers=8)
+        smooth = y / np.abs(y).max()
+        zr = obttb.fft_rmatvec(T, rough, g.sx, g.sy, workers=8)
+        zs = obttb.fft_rmatvec(T, smooth, g.sx, g.sy, workers=8)
+        _REF_CACHE[key] = (T, y, smooth, zr, zs)
+    return _REF_CACHE[key]
+
+
+def _fft_case(pk, g, models, dtype, tol):
+    rough = synth.normal_like(g.data_shape, 3, 9)
+    for kind, m in zip((pk.GRAVITY, pk.MAGNETIC), models):
+        T, y_ref, smooth, zr_ref, zs_ref = _fft_refs(g, kind, m, rough)
+        op = pk.Operator(dev(T), (g.sx, g.sy), dtype=dtype)
+        print(f"grid {g.sx}x{g.sy}x{g.nz} kind {kind} {dtype}", flush=True)
+        assert relerr(host(op.matvec(dev(m, dtype))), y_ref) <= tol
+        assert relerr(host(op.rmatvec(dev(rough, dtype))), zr_ref) <= tol
+        assert relerr(host(op.rmatvec(dev(smooth, dtype))), zs_ref) <= tol
+        op.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_mid_grid_matches_fft_oracle(pk, dtype):
+    g = synth.MID
+    _fft_case(pk, g, synth.random_boxes(g), dtype, F64_TOL if dtype == torch.float64 else F32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_large_grid_matches_fft_oracle(pk, dtype):
+    g = synth.LARGE
+    _fft_case(pk, g, synth.dyke_and_block(g), dtype, F64_TOL if dtype == torch.float64 else F32_TOL)
+
+
+# ------------------------------------------------------------------------------------
+# structural properties
+# ------------------------------------------------------------------------------------
+def test_adjoint_identity_fp64(pk):
+    for g in (synth.SMALL, RAGGED, synth.MID):
+        r = synth.rng(4, g.nx)
+        x = r.standard_normal(g.model_shape)
+        v = r.standard_normal(g.data_shape)
+        for kind in (pk.GRAVITY, pk.MAGNETIC):
+            op = pk.Operator.from_geometry(kind, g, dtype=torch.float64)
+            y = host(op.matvec(dev(x)))
+            z = host(op.rmatvec(dev(v)))
+            assert abs(np.sum(y * v) - np.sum(x * z)) <= 1e-12 * np.linalg.norm(y) * np.linalg.norm(v)
+            op.close()
+
+
+def test_impulse_response_is_dense_column(pk):
+    g = RAGGED
+    A = oprism.dense_matrix(oprism.MAGNETIC, ogeom(g))
+    op = pk.Operator.from_geometry(pk.MAGNETIC, g, dtype=torch.float64)
+    for (a, b, rr) in [(0, 0, 0), (g.nx - 1, g.ny - 1, g.nz - 1), (5, 2, 1)]:
+        e = np.zeros(g.model_shape)
+        e[rr, a, b] = 1.0
+        y = host(op.matvec(dev(e)))
+        col = A[:, (rr * g.nx + a) * g.ny + b].reshape(g.data_shape)
+        assert np.abs(y - col).max() <= 1e-12 * np.abs(col).max()
+    op.close()
+
+
+def test_launch_shape_and_repeatability(pk):
+    g = synth.MID
+    x, _ = synth.random_boxes(g)
+    v = synth.normal_like(g.data_shape, 2, 3)
+    op = pk.Operator.from_geometry(pk.GRAVITY, g, dtype=torch.float64)
+    y0 = host(op.matvec(dev(x)))
+    z0 = host(op.rmatvec(dev(v)))
+    assert np.array_equal(y0, host(op.matvec(dev(x))))           # repeatable
+    assert np.array_equal(z0, host(op.rmatvec(dev(v))))
+    info = op.info()
+    op.set_launch(col_fft_per_block=1, row_fft_per_block=1)          # same arithmetic
+    assert np.array_equal(y0, host(op.matvec(dev(x))))
+    assert np.array_equal(z0, host(op.rmatvec(dev(v))))
+    op.set_launch(layer_chunks=1)                                    # different layer grouping
+    assert relerr(host(op.matvec(dev(x))), y0) <= 1e-14
+    op.set_launch(col_fft_per_block=info["col_fft_per_block"], row_fft_per_block=info["row_fft_per_block"],
+                  layer_chunks=info["layer_chunks"])
+    op.close()
+
+
+def test_error_paths(pk):
+    from paper_2112_15562_amd import _lib as L
+    with pytest.raises(L.BTTBError) as e:
+        pk.Operator(torch.zeros((1, 2049, 3), dtype=torch.float64, device="cuda"), (1, 1))
+    assert e.value.status == L.BTTB_ESIZE
+    op = pk.Operator.from_geometry(pk.GRAVITY, synth.SUB, dtype=torch.float64)
+    with pytest.raises(TypeError):
+        op.matvec(torch.zeros(synth.SUB.model_shape, dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        op.matvec(torch.zeros((6, 12, 11), dtype=torch.float64, device="cuda"))
+    with pytest.raises(L.BTTBError) as e:
+        op.set_launch(row_fft_per_block=3)
+    assert e.value.status == L.BTTB_EINVAL
+    # misaligned pointer
+    buf = torch.zeros(synth.SUB.nz * 144 + 1, dtype=torch.float64, device="cuda")
+    out = torch.zeros(144, dtype=torch.float64, device="cuda")
+    import ctypes as C
+    rc = L.lib().bttb_matvec(op.plan, C.c_void_p(buf.data_ptr() + 4), C.c_void_p(out.data_ptr()), None)
+    assert rc == L.BTTB_EINVAL
+    op.close()
