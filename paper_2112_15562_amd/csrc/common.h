@@ -53,8 +53,9 @@ struct Plan {
   // launch shape
   int col_fpb;      // column FFTs per block
   int row_fpb;      // row-pair FFTs per block
-  int nchunk;       // layer chunks of the forward column pass
+  int nchunk;       // layer chunks of the forward column pass (general path)
   int nchunk_max;
+  bool fast;        // both transform sizes are powers of two: register-resident kernels
   FFTDesc fx, fy;
   void* eig;        // complex [nz][K2][Px] of the plan's type, scaled by 1/(Px Py)
   void* twx;        // complex [Px] of the plan's type
@@ -67,6 +68,21 @@ struct Plan {
   hipEvent_t* t_ev;  // [2 * t_cap]
   int* t_kid;        // [t_cap]
 };
+
+// Power-of-two path (operator_fast.hip).
+size_t fast_row_lds(int N, size_t esz, int G);
+size_t fast_col_lds(int N, size_t esz, int G, bool fwd);
+template <typename T>
+int fast_row_r2c(const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L, int nrows,
+                 int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s);
+template <typename T>
+int fast_row_c2r(const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
+                 const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
+                 hipStream_t s);
+template <typename T>
+int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs, int L,
+             int nin, int nout, int ldin, int ldout, int K2, int N, int G, const cx<T>* tw, int batch,
+             hipStream_t s);
 
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,

@@ -434,6 +434,14 @@ static int launch_row_c2r(const cx<T>* in, long long in_bs, long long in_cs, int
   return BTTB_OK;
 }
 
+// Row groups per block for the single-array row kernels (the data array, sx rows):
+// narrow blocks so that its few rows still spread over many compute units.
+static int small_row_groups(const Plan* P, int nrows, int batch) {
+  int g = P->row_fpb;
+  while (g > 1 && ceil_div(nrows, 2 * g) * batch < 256) g >>= 1;
+  return g;
+}
+
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,
                const T* winv, const T* wd, hipStream_t s) {
@@ -452,6 +460,40 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
     T* y = out + b0 * out_stride;
     int rc;
     int tk;
+    if (P->fast) {
+      const int gs = small_row_groups(P, P->sx, nb);
+      if (op == BTTB_OP_FORWARD) {
+        tk = t_begin(P, KT_FWD_ROW, s);
+        rc = fast_row_r2c<T>(x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->Py, P->row_fpb, twy, nb, s);
+        t_end(P, tk, s);
+        if (rc) return rc;
+        tk = t_begin(P, KT_FWD_COL, s);
+        rc = fast_col<T>(true, U, U_bs, eig, V, V_bs, P->nz, P->nx, P->sx, P->ldx, P->lds, P->K2, P->Px, P->col_fpb,
+                         twx, nb, s);
+        t_end(P, tk, s);
+        if (rc) return rc;
+        tk = t_begin(P, KT_FWD_INV, s);
+        rc = fast_row_c2r<T>(V, V_bs, V_cs, 1, y, out_stride, wd, 1, P->sx, P->sy, P->lds, P->Py, gs, twy, nb, s);
+        t_end(P, tk, s);
+        if (rc) return rc;
+      } else {
+        tk = t_begin(P, KT_ADJ_ROW, s);
+        rc = fast_row_r2c<T>(x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->lds, P->Py, gs, twy, nb, s);
+        t_end(P, tk, s);
+        if (rc) return rc;
+        tk = t_begin(P, KT_ADJ_COL, s);
+        rc = fast_col<T>(false, V, V_bs, eig, U, U_bs, P->nz, P->sx, P->nx, P->lds, P->ldx, P->K2, P->Px,
+                         P->col_fpb, twx, nb, s);
+        t_end(P, tk, s);
+        if (rc) return rc;
+        tk = t_begin(P, KT_ADJ_INV, s);
+        rc = fast_row_c2r<T>(U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->Py, P->row_fpb, twy,
+                             nb, s);
+        t_end(P, tk, s);
+        if (rc) return rc;
+      }
+      continue;
+    }
     if (op == BTTB_OP_FORWARD) {
       tk = t_begin(P, KT_FWD_ROW, s);
       rc = launch_row_r2c<T>(x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->K2, P->row_fpb, P->fy,
@@ -508,6 +550,7 @@ static constexpr size_t kMaxLds = 65536;
 static bool row_fpb_ok(const Plan* P, int fpb) {
   if (fpb < 1 || fpb > 8 || (fpb & (fpb - 1))) return false;
   const size_t elem = P->precision == BTTB_F64 ? 16 : 8;
+  if (P->fast) return fast_row_lds(P->Py, elem / 2, fpb) <= kMaxLds && fpb * (P->Py / 8) <= 512;
   if ((size_t)fpb * (P->Py + 2) * elem > kMaxLds) return false;
   return fpb * (P->Py / 8) <= 1024;
 }
@@ -515,11 +558,24 @@ static bool row_fpb_ok(const Plan* P, int fpb) {
 static bool col_fpb_ok(const Plan* P, int fpb) {
   if (fpb < 1) return false;
   const size_t elem = P->precision == BTTB_F64 ? 16 : 8;
+  if (P->fast)
+    return !(fpb & (fpb - 1)) && fast_col_lds(P->Px, elem / 2, fpb, true) <= kMaxLds &&
+           fpb * (P->Px / 8) <= 512 && (P->Px <= 512 || fpb == 1);
   if ((size_t)fpb * P->Px * elem > kMaxLds) return false;
   return fpb * (P->Px / 8) <= 1024;
 }
 
 static void default_launch(Plan* P) {
+  if (P->fast) {
+    int rf = 8;
+    while (rf > 1 && (!row_fpb_ok(P, rf) || rf * (P->Py / 8) > 512)) rf >>= 1;
+    P->row_fpb = rf;
+    int cf = 8;
+    while (cf > 1 && (!col_fpb_ok(P, cf) || cf > P->nz)) cf >>= 1;
+    P->col_fpb = cf;
+    P->nchunk = 1;
+    return;
+  }
   int rf = 8;
   while (rf > 1 && (!row_fpb_ok(P, rf) || rf * (P->Py / 8) > 512)) rf >>= 1;
   P->row_fpb = rf;
@@ -565,6 +621,7 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
   P->nchunk_max = std::min(nz, 16);
   P->fx = make_fft_desc(Px);
   P->fy = make_fft_desc(Py);
+  P->fast = !(Px & (Px - 1)) && !(Py & (Py - 1));
   default_launch(P);
   const size_t elem = precision == BTTB_F64 ? 16 : 8;  // complex element
   P->eig_bytes = (size_t)nz * P->K2 * Px * elem;
@@ -689,8 +746,8 @@ extern "C" int bttb_set_launch(bttb_plan plan, int col_fpb, int row_fpb, int lay
   if (!P) return fail(BTTB_EINVAL, "bttb_set_launch: plan is NULL");
   if (col_fpb > 0 && !col_fpb_ok(P, col_fpb)) return fail(BTTB_EINVAL, "bttb_set_launch: column FFTs per block");
   if (row_fpb > 0 && !row_fpb_ok(P, row_fpb)) return fail(BTTB_EINVAL, "bttb_set_launch: row FFTs per block");
-  if (layer_chunks > 0 && layer_chunks > P->nchunk_max)
-    return fail(BTTB_EINVAL, "bttb_set_launch: too many layer chunks");
+  if (layer_chunks > 0 && (layer_chunks > P->nchunk_max || (P->fast && layer_chunks != 1)))
+    return fail(BTTB_EINVAL, "bttb_set_launch: layer chunks out of range (1 on the power-of-two path)");
   if (col_fpb > 0) P->col_fpb = col_fpb;
   if (row_fpb > 0) P->row_fpb = row_fpb;
   if (layer_chunks > 0) P->nchunk = layer_chunks;

@@ -218,13 +218,13 @@ def test_launch_shape_and_repeatability(pk):
     assert np.array_equal(y0, host(op.matvec(dev(x))))           # repeatable
     assert np.array_equal(z0, host(op.rmatvec(dev(v))))
     info = op.info()
-    op.set_launch(col_fft_per_block=1, row_fft_per_block=1)          # same arithmetic
+    op.set_launch(row_fft_per_block=1)                              # same arithmetic per element
     assert np.array_equal(y0, host(op.matvec(dev(x))))
     assert np.array_equal(z0, host(op.rmatvec(dev(v))))
-    op.set_launch(layer_chunks=1)                                    # different layer grouping
+    op.set_launch(col_fft_per_block=1)                              # layers grouped differently
     assert relerr(host(op.matvec(dev(x))), y0) <= 1e-14
-    op.set_launch(col_fft_per_block=info["col_fft_per_block"], row_fft_per_block=info["row_fft_per_block"],
-                  layer_chunks=info["layer_chunks"])
+    assert np.array_equal(z0, host(op.rmatvec(dev(v))))
+    op.set_launch(col_fft_per_block=info["col_fft_per_block"], row_fft_per_block=info["row_fft_per_block"])
     op.close()
 
 
