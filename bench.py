@@ -65,9 +65,10 @@ def make_inputs(pk, torch, g):
     return (rho, kap), dobs, wd, wdepth
 
 
-def solver(pk, torch, ops, dobs, wd, wdepth):
+def solver(pk, torch, ops, dobs, wd, wdepth, use_graph=True):
     return pk.JointRRCG(ops, dobs, wd, wdepth, lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0),
-                        q=(0.95, 0.95), lam=(2.0, 100.0), eps2=1e-9, coupled=True, restart=True, p_norm=1)
+                        q=(0.95, 0.95), lam=(2.0, 100.0), eps2=1e-9, coupled=True, restart=True, p_norm=1,
+                        use_graph=use_graph)
 
 
 def product_rate(torch, ops, pairs):
@@ -175,9 +176,6 @@ def main():
     torch.cuda.synchronize()
     s32.close()
     s32 = solver(pk, torch, ops32, dobs, wd, wdepth)   # fresh start for the timed solve
-    launches = args.steps * (N_INNER * 3 + 3) + 16
-    for op in ops32:
-        op.timing_enable(launches)
     torch.cuda.synchronize()
     log("bench: fp32 timed solve")
     t0 = time.perf_counter()
@@ -186,12 +184,25 @@ def main():
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
     sc32 = s32.scalars()
-    timings = [op.timing_read() for op in ops32]
-    for op in ops32:
-        op.timing_enable(0)
+    s32.close()
     info32 = ops32[0].info()
     pairs = 2 * N_INNER * args.steps
     value = pairs / t32
+
+    # per-kernel HIP-event timing in the same solve, launched kernel by kernel (graphs
+    # hold no timing events); two outer steps
+    log("bench: fp32 per-kernel timing")
+    se = solver(pk, torch, ops32, dobs, wd, wdepth, use_graph=False)
+    launches = 2 * (N_INNER * 3 + 3) + 16
+    for op in ops32:
+        op.timing_enable(launches)
+    for _ in range(2):
+        se.step(N_INNER)
+    torch.cuda.synchronize()
+    timings = [op.timing_read() for op in ops32]
+    for op in ops32:
+        op.timing_enable(0)
+    se.close()
 
     # dominant kernel and its roofline
     tot = {}
@@ -211,7 +222,6 @@ def main():
     # ---------------- product throughput ----------------
     log("bench: product rates")
     rate32 = product_rate(torch, ops32, args.pairs)
-    s32.close()
     for op in ops32:
         op.close()
     ops64 = [pk.Operator.from_geometry(k, g, dtype=torch.float64) for k in (pk.GRAVITY, pk.MAGNETIC)]

@@ -195,6 +195,8 @@ typedef struct {
   double alpha0[2], q[2], alpha_min[2], lambda[2];
   double eps2;
   int coupled, restart, p_norm, gramian_weighted;
+  int use_graph;  /* 1: the step's kernel sequences are captured once into HIP graphs at creation
+                     and replayed by rrcg_step (fewer launches); 0: launched one by one */
 } rrcg_desc;
 
 /* Scalar state (FP64) of a handle. */

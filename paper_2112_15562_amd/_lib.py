@@ -54,7 +54,7 @@ class RrcgDesc(C.Structure):
                 ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("alpha0", C.c_double * 2),
                 ("q", C.c_double * 2), ("alpha_min", C.c_double * 2), ("lambda_", C.c_double * 2),
                 ("eps2", C.c_double), ("coupled", C.c_int), ("restart", C.c_int), ("p_norm", C.c_int),
-                ("gramian_weighted", C.c_int)]
+                ("gramian_weighted", C.c_int), ("use_graph", C.c_int)]
 
 
 class RrcgScalars(C.Structure):

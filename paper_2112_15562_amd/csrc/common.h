@@ -48,6 +48,7 @@ struct Plan {
   int sx, sy, nx, ny, nz;
   int Px, Py, K2;   // K2 = Py/2 + 1 (half spectrum along y)
   int ldx, lds;     // padded row counts of the column-major intermediates (multiples of 16)
+  int ldk;          // padded K2: row stride of the row-major data-array spectra (power-of-two path)
   int precision;
   int max_batch;
   // launch shape
@@ -65,6 +66,7 @@ struct Plan {
   size_t eig_bytes, scratch_bytes;
   // optional per-kernel event timing
   int t_cap, t_used;
+  int t_suspend;     // > 0 while kernels are being captured into a graph
   hipEvent_t* t_ev;  // [2 * t_cap]
   int* t_kid;        // [t_cap]
 };
@@ -73,16 +75,16 @@ struct Plan {
 size_t fast_row_lds(int N, size_t esz, int G);
 size_t fast_col_lds(int N, size_t esz, int G, bool fwd);
 template <typename T>
-int fast_row_r2c(const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L, int nrows,
+int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L, int nrows,
                  int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s);
 template <typename T>
-int fast_row_c2r(const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
+int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
                  const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
                  hipStream_t s);
 template <typename T>
-int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs, int L,
-             int nin, int nout, int ldin, int ldout, int K2, int N, int G, const cx<T>* tw, int batch,
-             hipStream_t s);
+int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs,
+             long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
+             const cx<T>* tw, int batch, hipStream_t s);
 
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,

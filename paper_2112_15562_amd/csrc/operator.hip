@@ -398,7 +398,7 @@ enum { KT_FWD_ROW = 0, KT_FWD_COL, KT_FWD_INV, KT_ADJ_ROW, KT_ADJ_COL, KT_ADJ_IN
 
 // Event pair around one kernel launch when timing is enabled (returns the slot or -1).
 static int t_begin(Plan* P, int kid, hipStream_t s) {
-  if (!P->t_ev || P->t_used >= P->t_cap) return -1;
+  if (!P->t_ev || P->t_suspend > 0 || P->t_used >= P->t_cap) return -1;
   const int k = P->t_used++;
   P->t_kid[k] = kid;
   (void)hipEventRecord(P->t_ev[2 * k], s);
@@ -452,7 +452,8 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
   cx<T>* V = static_cast<cx<T>*>(P->V);
   const long long U_bs = (long long)P->nz * P->K2 * P->ldx;
   const long long V_cs = (long long)P->K2 * P->lds;
-  const long long V_bs = (long long)P->nchunk_max * V_cs;
+  const long long V_fcs = (long long)P->lds * P->ldk;  // power-of-two path: one row-major partial
+  const long long V_bs = std::max((long long)P->nchunk_max * V_cs, (long long)P->nchunk_max * V_fcs);
   const int TPFx = P->Px / 8;
   for (int b0 = 0; b0 < batch; b0 += P->max_batch) {
     const int nb = std::min(P->max_batch, batch - b0);
@@ -464,31 +465,33 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
       const int gs = small_row_groups(P, P->sx, nb);
       if (op == BTTB_OP_FORWARD) {
         tk = t_begin(P, KT_FWD_ROW, s);
-        rc = fast_row_r2c<T>(x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->Py, P->row_fpb, twy, nb, s);
+        rc = fast_row_r2c<T>(false, x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->Py, P->row_fpb, twy,
+                             nb, s);
         t_end(P, tk, s);
         if (rc) return rc;
         tk = t_begin(P, KT_FWD_COL, s);
-        rc = fast_col<T>(true, U, U_bs, eig, V, V_bs, P->nz, P->nx, P->sx, P->ldx, P->lds, P->K2, P->Px, P->col_fpb,
-                         twx, nb, s);
+        rc = fast_col<T>(true, U, U_bs, eig, V, V_bs, V_fcs, P->nz, P->nx, P->sx, P->ldx, P->ldk, P->K2, P->Px,
+                         P->col_fpb, P->nchunk, twx, nb, s);
         t_end(P, tk, s);
         if (rc) return rc;
         tk = t_begin(P, KT_FWD_INV, s);
-        rc = fast_row_c2r<T>(V, V_bs, V_cs, 1, y, out_stride, wd, 1, P->sx, P->sy, P->lds, P->Py, gs, twy, nb, s);
+        rc = fast_row_c2r<T>(true, V, V_bs, V_fcs, P->nchunk, y, out_stride, wd, 1, P->sx, P->sy, P->ldk, P->Py, gs,
+                             twy, nb, s);
         t_end(P, tk, s);
         if (rc) return rc;
       } else {
         tk = t_begin(P, KT_ADJ_ROW, s);
-        rc = fast_row_r2c<T>(x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->lds, P->Py, gs, twy, nb, s);
+        rc = fast_row_r2c<T>(true, x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->ldk, P->Py, gs, twy, nb, s);
         t_end(P, tk, s);
         if (rc) return rc;
         tk = t_begin(P, KT_ADJ_COL, s);
-        rc = fast_col<T>(false, V, V_bs, eig, U, U_bs, P->nz, P->sx, P->nx, P->lds, P->ldx, P->K2, P->Px,
-                         P->col_fpb, twx, nb, s);
+        rc = fast_col<T>(false, V, V_bs, eig, U, U_bs, 0, P->nz, P->sx, P->nx, P->ldk, P->ldx, P->K2, P->Px,
+                         P->col_fpb, P->nchunk, twx, nb, s);
         t_end(P, tk, s);
         if (rc) return rc;
         tk = t_begin(P, KT_ADJ_INV, s);
-        rc = fast_row_c2r<T>(U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->Py, P->row_fpb, twy,
-                             nb, s);
+        rc = fast_row_c2r<T>(false, U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->Py,
+                             P->row_fpb, twy, nb, s);
         t_end(P, tk, s);
         if (rc) return rc;
       }
@@ -560,7 +563,7 @@ static bool col_fpb_ok(const Plan* P, int fpb) {
   const size_t elem = P->precision == BTTB_F64 ? 16 : 8;
   if (P->fast)
     return !(fpb & (fpb - 1)) && fast_col_lds(P->Px, elem / 2, fpb, true) <= kMaxLds &&
-           fpb * (P->Px / 8) <= 512 && (P->Px <= 512 || fpb == 1);
+           fpb * (P->Px / 8) <= (P->precision == BTTB_F64 ? 256 : 512) && (P->Px <= 512 || fpb == 1);
   if ((size_t)fpb * P->Px * elem > kMaxLds) return false;
   return fpb * (P->Px / 8) <= 1024;
 }
@@ -570,10 +573,14 @@ static void default_launch(Plan* P) {
     int rf = 8;
     while (rf > 1 && (!row_fpb_ok(P, rf) || rf * (P->Py / 8) > 512)) rf >>= 1;
     P->row_fpb = rf;
+    // column jobs = Py/2; enough layer chunks for >= 256 blocks, up to 8 groups per block
+    const int jobs = P->Py / 2;
+    int nc = 1;
+    while (jobs * nc * P->max_batch < 256 && nc * 2 <= std::min(P->nz, P->nchunk_max)) nc *= 2;
+    P->nchunk = nc;
     int cf = 8;
-    while (cf > 1 && (!col_fpb_ok(P, cf) || cf > P->nz)) cf >>= 1;
+    while (cf > 1 && (!col_fpb_ok(P, cf) || cf * nc > P->nz)) cf >>= 1;
     P->col_fpb = cf;
-    P->nchunk = 1;
     return;
   }
   int rf = 8;
@@ -616,6 +623,7 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
   P->Px = Px; P->Py = Py; P->K2 = Py / 2 + 1;
   P->ldx = round_up(nx, 16);
   P->lds = round_up(sx, 16);
+  P->ldk = round_up(Py / 2 + 1, 8);
   P->precision = precision;
   P->max_batch = max_batch;
   P->nchunk_max = std::min(nz, 16);
@@ -626,7 +634,8 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
   const size_t elem = precision == BTTB_F64 ? 16 : 8;  // complex element
   P->eig_bytes = (size_t)nz * P->K2 * Px * elem;
   const size_t Ub = (size_t)max_batch * nz * P->K2 * P->ldx * elem;
-  const size_t Vb = (size_t)max_batch * P->nchunk_max * P->K2 * P->lds * elem;
+  const size_t Vb =
+      (size_t)max_batch * P->nchunk_max * std::max((size_t)P->K2 * P->lds, (size_t)P->lds * P->ldk) * elem;
   P->scratch_bytes = Ub + Vb;
 
   auto cleanup = [&](int rc) {
@@ -746,8 +755,8 @@ extern "C" int bttb_set_launch(bttb_plan plan, int col_fpb, int row_fpb, int lay
   if (!P) return fail(BTTB_EINVAL, "bttb_set_launch: plan is NULL");
   if (col_fpb > 0 && !col_fpb_ok(P, col_fpb)) return fail(BTTB_EINVAL, "bttb_set_launch: column FFTs per block");
   if (row_fpb > 0 && !row_fpb_ok(P, row_fpb)) return fail(BTTB_EINVAL, "bttb_set_launch: row FFTs per block");
-  if (layer_chunks > 0 && (layer_chunks > P->nchunk_max || (P->fast && layer_chunks != 1)))
-    return fail(BTTB_EINVAL, "bttb_set_launch: layer chunks out of range (1 on the power-of-two path)");
+  if (layer_chunks > 0 && layer_chunks > std::min(P->nchunk_max, P->nz))
+    return fail(BTTB_EINVAL, "bttb_set_launch: layer chunks out of range");
   if (col_fpb > 0) P->col_fpb = col_fpb;
   if (row_fpb > 0) P->row_fpb = row_fpb;
   if (layer_chunks > 0) P->nchunk = layer_chunks;

@@ -53,7 +53,9 @@ struct FRowArgs {
   const cx<T>* tw;
 };
 
-template <typename T, int N>
+// ROWOUT = false: half spectra stored column-major out[l][k2][row] (ld = padded rows) through an
+// LDS transpose; ROWOUT = true: row-major out[l][row][k2] (ld = padded K2) straight from registers.
+template <typename T, int N, bool ROWOUT>
 __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
@@ -101,6 +103,18 @@ __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a) {
       xb[i] = cx<T>{h * (A.im + C.im), h * (C.re - A.re)};
     }
   }
+  if constexpr (ROWOUT) {
+    cx<T>* dst = a.out + b * a.out_bs + ((long long)l * a.nrows + r0) * a.ld;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      const int k = t + i * TPF;
+      if (k <= N / 2) {
+        if (ra) dst[k] = xa[i];
+        if (rb) dst[a.ld + k] = xb[i];
+      }
+    }
+    return;
+  }
   gsync();
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -118,7 +132,10 @@ __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a) {
   }
 }
 
-template <typename T, int N>
+// ROWIN = false: half spectra read column-major in[c][l][k2][row] (ld = padded rows), summed over
+// nsum partials, through an LDS transpose; ROWIN = true: row-major in[l][row][k2] (ld = padded
+// K2, nsum = 1) read straight into the strided layout.
+template <typename T, int N, bool ROWIN>
 __global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
@@ -132,48 +149,81 @@ __global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a) {
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
   F.init(a.tw, t);
-  // here `in` is complex [nsum][L][K2][ld] and `out` real [L][nrows][ncols]
-  const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + (long long)l * K2 * a.ld + tile * RT;
-  for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
-    const int k2 = idx / RT, rr = idx - k2 * RT;
-    const int row = tile * RT + rr;
-    cx<T> hv{T(0), T(0)};
-    if (row < a.nrows) {
-      if (a.nsum == 1) {
-        hv = src[(long long)k2 * a.ld + rr];
-      } else {
-        double hr = 0.0, hi = 0.0;
-        for (int c = 0; c < a.nsum; ++c) {
-          const cx<T> u = src[c * a.in_cs + (long long)k2 * a.ld + rr];
-          hr += (double)u.re;
-          hi += (double)u.im;
-        }
-        hv = cx<T>{(T)hr, (T)hi};
+  const int r0 = tile * RT + 2 * f;
+  const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
+  cx<T> v[8];
+  if constexpr (ROWIN) {
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + ((long long)l * a.nrows + r0) * a.ld;
+    cx<T> ha[8], hb[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = t + i * TPF;
+      const int kk = k <= N / 2 ? k : N - k;
+      ha[i] = ra ? src[kk] : cx<T>{T(0), T(0)};
+      hb[i] = rb ? src[a.ld + kk] : cx<T>{T(0), T(0)};
+    }
+    for (int c = 1; c < a.nsum; ++c) {  // partials of the layer chunks, summed in order
+      const cx<T>* sc = src + c * a.in_cs;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = t + i * TPF;
+        const int kk = k <= N / 2 ? k : N - k;
+        if (ra) ha[i] = cadd(ha[i], sc[kk]);
+        if (rb) hb[i] = cadd(hb[i], sc[a.ld + kk]);
       }
     }
-    if (k2 == 0 || k2 == K2 - 1) hv.im = T(0);  // DC and Nyquist of a real row are real
-    smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv;
-  }
-  __syncthreads();
-  cx<T> v[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int k = t + i * TPF;
-    if (k <= N / 2) {
-      const cx<T> ha = buf[k], hb = buf[K2 + k];
-      v[i] = cx<T>{ha.re - hb.im, ha.im + hb.re};
-    } else {
-      const cx<T> ha = buf[N - k], hb = buf[K2 + N - k];
-      v[i] = cx<T>{ha.re + hb.im, hb.re - ha.im};
+    for (int i = 0; i < 8; ++i) {
+      const int k = t + i * TPF;
+      const int kk = k <= N / 2 ? k : N - k;
+      if (kk == 0 || kk == N / 2) {  // DC and Nyquist of a real row are real
+        ha[i].im = T(0);
+        hb[i].im = T(0);
+      }
+      v[i] = k <= N / 2 ? cx<T>{ha[i].re - hb[i].im, ha[i].im + hb[i].re}
+                        : cx<T>{ha[i].re + hb[i].im, hb[i].re - ha[i].im};
+    }
+  } else {
+    // `in` is complex [nsum][L][K2][ld], summed over the nsum partials
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + (long long)l * K2 * a.ld + tile * RT;
+    for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
+      const int k2 = idx / RT, rr = idx - k2 * RT;
+      const int row = tile * RT + rr;
+      cx<T> hv{T(0), T(0)};
+      if (row < a.nrows) {
+        if (a.nsum == 1) {
+          hv = src[(long long)k2 * a.ld + rr];
+        } else {
+          double hr = 0.0, hi = 0.0;
+          for (int c = 0; c < a.nsum; ++c) {
+            const cx<T> u = src[c * a.in_cs + (long long)k2 * a.ld + rr];
+            hr += (double)u.re;
+            hi += (double)u.im;
+          }
+          hv = cx<T>{(T)hr, (T)hi};
+        }
+      }
+      if (k2 == 0 || k2 == K2 - 1) hv.im = T(0);  // DC and Nyquist of a real row are real
+      smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = t + i * TPF;
+      if (k <= N / 2) {
+        const cx<T> ha = buf[k], hb = buf[K2 + k];
+        v[i] = cx<T>{ha.re - hb.im, ha.im + hb.re};
+      } else {
+        const cx<T> ha = buf[N - k], hb = buf[K2 + N - k];
+        v[i] = cx<T>{ha.re + hb.im, hb.re - ha.im};
+      }
     }
   }
   gsync();
   F.template run<true>(v, buf, t, gsync);
-  const int r0 = tile * RT + 2 * f;
   const long long lofs = (long long)l * a.nrows * a.ncols;
   T* dst = reinterpret_cast<T*>(a.out) + b * a.out_bs + lofs;
   const T* sc = a.scale ? a.scale + lofs : nullptr;
-  const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int q = t + i * TPF;
@@ -195,20 +245,114 @@ struct FColArgs {
   const cx<T>* eig;
   cx<T>* out;
   long long out_bs;
-  int L, nin, nout, ldin, ldout, K2, fpb;
+  long long out_cs;  // forward: stride between layer-chunk partials
+  int L, nin, nout, ldin, ldout, K2, fpb, nchunk;
   const cx<T>* tw;
 };
 
-// Forward: per column k2, sum over layers of eig_l . FFT_x(U_l column), inverse FFT_x.
+// Column jobs: job j in [1, Py/2) is column k2 = j; job 0 carries the two columns whose
+// row spectra are real, k2 = 0 and k2 = Py/2 (= K2-1), packed as one complex transform
+// c0 + i cN.  Their column transforms are recovered as X0[k] = (Z[k] + conj Z[-k]) / 2,
+// XN[k] = (Z[k] - conj Z[-k]) / (2i); products with eigenvalue columns of a real array
+// stay Hermitian, so the inverse of S0 + i SN returns s0 in its real and sN in its
+// imaginary part.  This gives Py/2 equal jobs.
+
+// Layer loop of the forward column pass for one group: acc += eig_l . FFT_x(column_l)
+// (PACKED: eig0 . X0 + i eigN . XN from the packed pair of real columns).  The next
+// layer's eigenvalues (and in FP32 its column) are loaded while the current one is
+// transformed; FP64 keeps the column load in place to stay within 256 registers.
+template <typename T, int N, bool PACKED>
+__device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
+                                           int G, int k2, int l0, int l1, int b, double (&ar)[8],
+                                           double (&ai)[8]) {
+  constexpr int TPF = N / 8;
+  constexpr bool PF_IN = sizeof(T) == 4;
+  GroupSync<TPF> gsync;
+  const int kN = a.K2 - 1;
+  const cx<T>* src = a.in + b * a.in_bs + (long long)k2 * a.ldin;
+  const cx<T>* srcN = a.in + b * a.in_bs + (long long)kN * a.ldin;
+  const cx<T>* eg = a.eig + (long long)k2 * N;
+  const cx<T>* egN = a.eig + (long long)kN * N;
+  const long long lstride_in = (long long)a.K2 * a.ldin, lstride_e = (long long)a.K2 * N;
+  const int nit = (l1 - l0 + G - 1) / G;
+  cx<T> un[PF_IN ? 8 : 1], en[8], enN[PACKED ? 8 : 1];
+  auto load_col = [&](int l, int i) -> cx<T> {
+    const int n = t + i * TPF;
+    if (l >= l1 || n >= a.nin) return cx<T>{T(0), T(0)};
+    if constexpr (PACKED) return cx<T>{src[l * lstride_in + n].re, srcN[l * lstride_in + n].re};
+    return src[l * lstride_in + n];
+  };
+  auto fetch = [&](int l) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if constexpr (PF_IN) un[i] = load_col(l, i);
+      en[i] = l < l1 ? eg[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
+      if constexpr (PACKED) enN[i] = l < l1 ? egN[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
+    }
+  };
+  fetch(l0 + f);
+  for (int it = 0; it < nit; ++it) {
+    const int l = l0 + it * G + f;
+    const bool act = l < l1;
+    cx<T> v[8], e[8], eN[PACKED ? 8 : 1];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      if constexpr (PF_IN) v[i] = un[i];
+      else v[i] = load_col(l, i);
+      e[i] = en[i];
+      if constexpr (PACKED) eN[i] = enN[i];
+    }
+    if (it + 1 < nit) fetch(l + G);
+    F.template run<false>(v, buf, t, gsync);
+    if constexpr (PACKED) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) buf[lds_pad(t + i * TPF)] = v[i];
+      gsync();
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = t + i * TPF;
+        const cx<T> A = v[i], C = buf[lds_pad((N - k) & (N - 1))];
+        const double x0r = 0.5 * ((double)A.re + C.re), x0i = 0.5 * ((double)A.im - C.im);
+        const double xnr = 0.5 * ((double)A.im + C.im), xni = 0.5 * ((double)C.re - A.re);
+        const double pr = (double)e[i].re * x0r - (double)e[i].im * x0i;
+        const double pi = (double)e[i].re * x0i + (double)e[i].im * x0r;
+        const double qr = (double)eN[i].re * xnr - (double)eN[i].im * xni;
+        const double qi = (double)eN[i].re * xni + (double)eN[i].im * xnr;
+        if (act) {
+          ar[i] += pr - qi;
+          ai[i] += pi + qr;
+        }
+      }
+      gsync();
+    } else if (act) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const double xr = v[i].re, xi = v[i].im, wr = e[i].re, wi = e[i].im;
+        ar[i] += wr * xr - wi * xi;
+        ai[i] += wr * xi + wi * xr;
+      }
+    }
+  }
+}
+
+// Forward: partial over the layers of chunk c of sum_l eig_l . FFT_x(U_l column), then the
+// inverse FFT_x; rows p < nout are written row-major to out[c][p][k2] (ldout = padded K2).
+// FP64 column blocks are limited to 256 threads so that the registers beyond 256 per lane
+// (the accumulation registers) can hold what does not fit, instead of scratch memory.
+constexpr int col_threads(int esz) { return esz == 4 ? 512 : 256; }
+
 template <typename T, int N>
-__global__ void __launch_bounds__(512) k_fcol_fwd(FColArgs<T> a) {
+__global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_fwd(FColArgs<T> a) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
   const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
   const int G = a.fpb;
-  const int k2 = blockIdx.x, b = blockIdx.y;
+  const int job = blockIdx.x, c = blockIdx.y, b = blockIdx.z;
+  const bool packed = job == 0;
+  const int k2 = job, kN = a.K2 - 1;
+  const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
   cx<T>* buf = smem + f * P::BUF;
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
@@ -216,30 +360,8 @@ __global__ void __launch_bounds__(512) k_fcol_fwd(FColArgs<T> a) {
   double ar[8], ai[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) ar[i] = ai[i] = 0.0;
-  const cx<T>* src = a.in + b * a.in_bs + (long long)k2 * a.ldin;
-  const cx<T>* eg = a.eig + (long long)k2 * N;
-  const long long lstride_in = (long long)a.K2 * a.ldin, lstride_e = (long long)a.K2 * N;
-  const int nit = (a.L + G - 1) / G;
-  for (int it = 0; it < nit; ++it) {
-    const int l = it * G + f;
-    const bool act = l < a.L;
-    cx<T> v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      v[i] = (act && n < a.nin) ? src[l * lstride_in + n] : cx<T>{T(0), T(0)};
-    }
-    F.template run<false>(v, buf, t, gsync);
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const cx<T> w = eg[l * lstride_e + t + i * TPF];
-        const double xr = v[i].re, xi = v[i].im, wr = w.re, wi = w.im;
-        ar[i] += wr * xr - wi * xi;
-        ai[i] += wr * xi + wi * xr;
-      }
-    }
-  }
+  if (packed) fwd_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+  else fwd_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
   // tree reduction of the groups' accumulators (G is a power of two)
   double2* red = reinterpret_cast<double2*>(smem_raw);
   for (int half = G >> 1; half >= 1; half >>= 1) {
@@ -265,59 +387,130 @@ __global__ void __launch_bounds__(512) k_fcol_fwd(FColArgs<T> a) {
     for (int i = 0; i < 8; ++i) v[i] = cx<T>{(T)ar[i], (T)ai[i]};
     F.template run<true>(v, buf, t, gsync);
     if (f == 0) {
-      cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
+      cx<T>* dst = a.out + b * a.out_bs + c * a.out_cs;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int p = t + i * TPF;
-        if (p < a.nout) dst[p] = v[i];
+        if (p < a.nout) {
+          if (packed) {
+            dst[(long long)p * a.ldout] = cx<T>{v[i].re, T(0)};
+            dst[(long long)p * a.ldout + kN] = cx<T>{v[i].im, T(0)};
+          } else {
+            dst[(long long)p * a.ldout + k2] = v[i];
+          }
+        }
       }
     }
   }
 }
 
-// Transpose: per column k2, R = FFT_x(Rrow column) once, then per layer conj(eig_l) R
-// and the inverse FFT_x; rows a < nout are written.
+// Layer loop of the transpose column pass for one group: per layer conj(eig_l) R (PACKED:
+// conj(eig0) R0 + i conj(eigN) RN), inverse FFT_x, rows a < nout stored.
+template <typename T, int N, bool PACKED>
+__device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
+                                           int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8],
+                                           const cx<T> (&Rm)[8]) {
+  constexpr int TPF = N / 8;
+  GroupSync<TPF> gsync;
+  const int kN = a.K2 - 1;
+  const cx<T>* eg = a.eig + (long long)k2 * N;
+  const cx<T>* egN = a.eig + (long long)kN * N;
+  cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
+  cx<T>* dstN = a.out + b * a.out_bs + (long long)kN * a.ldout;
+  const long long lstride_out = (long long)a.K2 * a.ldout, lstride_e = (long long)a.K2 * N;
+  const int nit = (l1 - l0 + G - 1) / G;
+  cx<T> en[8], enN[PACKED ? 8 : 1];
+  auto fetch = [&](int l) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      en[i] = l < l1 ? eg[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
+      if constexpr (PACKED) enN[i] = l < l1 ? egN[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
+    }
+  };
+  fetch(l0 + f);
+  for (int it = 0; it < nit; ++it) {
+    const int l = l0 + it * G + f;
+    const bool act = l < l1;
+    cx<T> v[8];
+    if constexpr (PACKED) {
+      // conj(eig0) . R0 + i conj(eigN) . RN with R0, RN split from the packed spectrum
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const cx<T> A = R[i], C = Rm[i];
+        const T h = T(0.5);
+        const cx<T> r0{h * (A.re + C.re), h * (A.im - C.im)};
+        const cx<T> rn{h * (A.im + C.im), h * (C.re - A.re)};
+        const cx<T> p0 = cmulc(r0, en[i]), pn = cmulc(rn, enN[i]);
+        v[i] = cx<T>{p0.re - pn.im, p0.im + pn.re};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], en[i]);
+    }
+    if (it + 1 < nit) fetch(l + G);
+    F.template run<true>(v, buf, t, gsync);
+    if (act) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int p = t + i * TPF;
+        if (p < a.nout) {
+          if constexpr (PACKED) {
+            dst[l * lstride_out + p] = cx<T>{v[i].re, T(0)};
+            dstN[l * lstride_out + p] = cx<T>{v[i].im, T(0)};
+          } else {
+            dst[l * lstride_out + p] = v[i];
+          }
+        }
+      }
+    }
+  }
+}
+
+// Transpose: R = FFT_x(Rrow column) once per block (group 0, shared through LDS), then for
+// each layer of chunk c, conj(eig_l) R and the inverse FFT_x; rows a < nout are written
+// to out[l][k2][a] (ldout = padded rows).  Rrow is row-major Rrow[p][k2] (ldin = padded K2).
 template <typename T, int N>
-__global__ void __launch_bounds__(512) k_fcol_adj(FColArgs<T> a) {
+__global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_adj(FColArgs<T> a) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
   const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
   const int G = a.fpb;
-  const int k2 = blockIdx.x, b = blockIdx.y;
+  const int job = blockIdx.x, c = blockIdx.y, b = blockIdx.z;
+  const bool packed = job == 0;
+  const int k2 = job, kN = a.K2 - 1;
+  const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
   cx<T>* buf = smem + f * P::BUF;
+  cx<T>* Rs = smem + G * P::BUF;  // the shared column spectrum, N values
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
   F.init(a.tw, t);
-  const cx<T>* col = a.in + b * a.in_bs + (long long)k2 * a.ldin;
-  cx<T> R[8];
+  const cx<T>* col = a.in + b * a.in_bs;
+  if (TPF > 64 || f == 0) {
+    cx<T> R[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int n = t + i * TPF;
-    R[i] = n < a.nin ? col[n] : cx<T>{T(0), T(0)};
-  }
-  F.template run<false>(R, buf, t, gsync);
-  const cx<T>* eg = a.eig + (long long)k2 * N;
-  cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
-  const long long lstride_out = (long long)a.K2 * a.ldout, lstride_e = (long long)a.K2 * N;
-  const int nit = (a.L + G - 1) / G;
-  for (int it = 0; it < nit; ++it) {
-    const int l = it * G + f;
-    const bool act = l < a.L;
-    cx<T> v[8];
+    for (int i = 0; i < 8; ++i) {
+      const int n = t + i * TPF;
+      const long long o = (long long)n * a.ldin;
+      R[i] = n >= a.nin ? cx<T>{T(0), T(0)} : (packed ? cx<T>{col[o].re, col[o + kN].re} : col[o + k2]);
+    }
+    F.template run<false>(R, buf, t, gsync);
+    if (f == 0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      v[i] = act ? cmulc(R[i], eg[l * lstride_e + t + i * TPF]) : cx<T>{T(0), T(0)};
-    F.template run<true>(v, buf, t, gsync);
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int p = t + i * TPF;
-        if (p < a.nout) dst[l * lstride_out + p] = v[i];
-      }
+      for (int i = 0; i < 8; ++i) Rs[t + i * TPF] = R[i];
     }
   }
+  __syncthreads();
+  cx<T> R[8], Rm[8];  // Rm: the mirrored values Z[-k] of the packed job
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = t + i * TPF;
+    R[i] = Rs[k];
+    if (packed) Rm[i] = Rs[(N - k) & (N - 1)];
+  }
+  if (packed) adj_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
+  else adj_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
 }
 
 // ------------------------------------------------------------------------------------
@@ -344,45 +537,57 @@ size_t fast_row_lds(int N, size_t esz, int G) {
 }
 
 size_t fast_col_lds(int N, size_t esz, int G, bool fwd) {
-  const size_t ex = (size_t)G * (N + N / 8) * 2 * esz;
+  const size_t ex = (size_t)G * (N + N / 8) * 2 * esz + (fwd ? 0 : (size_t)N * 2 * esz);
   const size_t red = fwd ? (size_t)(G / 2) * N * 16 : 0;
   return ex > red ? ex : red;
 }
 
 template <typename T>
-int fast_row_r2c(const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L, int nrows,
-                 int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s) {
+int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L,
+                 int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s) {
   FRowArgs<T> a{in, in_bs, scale, out, out_bs, 0, 1, L, nrows, ncols, ld, N / 2 + 1, G, ceil_div(nrows, 2 * G), tw};
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN>), grid, block, sh, s, a)
-  BTTB_POW2_SWITCH(N, BTTB_L)
+  if (rowout) {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, true>), grid, block, sh, s, a)
+    BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
+  } else {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, false>), grid, block, sh, s, a)
+    BTTB_POW2_SWITCH(N, BTTB_L)
+#undef BTTB_L
+  }
   BTTB_LAUNCHED("k_frow_r2c");
   return BTTB_OK;
 }
 
 template <typename T>
-int fast_row_c2r(const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
+int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
                  const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
                  hipStream_t s) {
   FRowArgs<T> a{reinterpret_cast<const T*>(in), in_bs, scale, reinterpret_cast<cx<T>*>(out), out_bs, in_cs,
                 nsum, L, nrows, ncols, ld, N / 2 + 1, G, ceil_div(nrows, 2 * G), tw};
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN>), grid, block, sh, s, a)
-  BTTB_POW2_SWITCH(N, BTTB_L)
+  if (rowin) {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true>), grid, block, sh, s, a)
+    BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
+  } else {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, false>), grid, block, sh, s, a)
+    BTTB_POW2_SWITCH(N, BTTB_L)
+#undef BTTB_L
+  }
   BTTB_LAUNCHED("k_frow_c2r");
   return BTTB_OK;
 }
 
 template <typename T>
-int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs, int L,
-             int nin, int nout, int ldin, int ldout, int K2, int N, int G, const cx<T>* tw, int batch,
-             hipStream_t s) {
-  FColArgs<T> a{in, in_bs, eig, out, out_bs, L, nin, nout, ldin, ldout, K2, G, tw};
-  dim3 grid(K2, batch), block(G * (N / 8));
+int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs,
+             long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
+             const cx<T>* tw, int batch, hipStream_t s) {
+  FColArgs<T> a{in, in_bs, eig, out, out_bs, out_cs, L, nin, nout, ldin, ldout, K2, G, nchunk, tw};
+  dim3 grid(K2 - 1, nchunk, batch), block(G * (N / 8));
   const size_t sh = fast_col_lds(N, sizeof(T), G, fwd);
   if (fwd) {
 #define BTTB_L(NN) hipLaunchKernelGGL((k_fcol_fwd<T, NN>), grid, block, sh, s, a)
@@ -398,17 +603,18 @@ int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>
   return BTTB_OK;
 }
 
-template int fast_row_r2c<float>(const float*, long long, const float*, cx<float>*, long long, int, int, int, int,
+template int fast_row_r2c<float>(bool, const float*, long long, const float*, cx<float>*, long long, int, int, int, int,
                                  int, int, const cx<float>*, int, hipStream_t);
-template int fast_row_r2c<double>(const double*, long long, const double*, cx<double>*, long long, int, int, int,
+template int fast_row_r2c<double>(bool, const double*, long long, const double*, cx<double>*, long long, int, int, int,
                                   int, int, int, const cx<double>*, int, hipStream_t);
-template int fast_row_c2r<float>(const cx<float>*, long long, long long, int, float*, long long, const float*, int,
+template int fast_row_c2r<float>(bool, const cx<float>*, long long, long long, int, float*, long long, const float*, int,
                                  int, int, int, int, int, const cx<float>*, int, hipStream_t);
-template int fast_row_c2r<double>(const cx<double>*, long long, long long, int, double*, long long, const double*,
+template int fast_row_c2r<double>(bool, const cx<double>*, long long, long long, int, double*, long long, const double*,
                                   int, int, int, int, int, int, const cx<double>*, int, hipStream_t);
-template int fast_col<float>(bool, const cx<float>*, long long, const cx<float>*, cx<float>*, long long, int, int,
-                             int, int, int, int, int, int, const cx<float>*, int, hipStream_t);
-template int fast_col<double>(bool, const cx<double>*, long long, const cx<double>*, cx<double>*, long long, int,
-                              int, int, int, int, int, int, int, const cx<double>*, int, hipStream_t);
+template int fast_col<float>(bool, const cx<float>*, long long, const cx<float>*, cx<float>*, long long, long long,
+                             int, int, int, int, int, int, int, int, int, const cx<float>*, int, hipStream_t);
+template int fast_col<double>(bool, const cx<double>*, long long, const cx<double>*, cx<double>*, long long,
+                              long long, int, int, int, int, int, int, int, int, int, const cx<double>*, int,
+                              hipStream_t);
 
 }  // namespace bttb

@@ -60,6 +60,10 @@ struct Rrcg {
   void* qv[2];
   double* sc;  // [S_COUNT]
   double* pb;  // [4][NSLOT][RGRID] partial sums (four independent reductions)
+  // HIP graphs of the step's phases (captured once at creation on a private stream)
+  int use_graph;
+  hipStream_t cap;
+  hipGraphExec_t g_weights, g_inner_restart, g_inner, g_outer;
 };
 
 // Sum of v over the block, written to out[slot * RGRID + blockIdx.x] for each slot.
@@ -361,8 +365,26 @@ static int outer_update(Rrcg* h, hipStream_t s, int advance) {
   return BTTB_OK;
 }
 
+// Phase 1 of an outer step: w, winv from m and the Gramian scalars.
 template <typename T>
-static int step_impl(Rrcg* h, int n_inner, hipStream_t s) {
+static int phase_weights(Rrcg* h, hipStream_t s) {
+  T** m = reinterpret_cast<T**>(h->m);
+  T** w = reinterpret_cast<T**>(h->w);
+  T** wi = reinterpret_cast<T**>(h->winv);
+  hipLaunchKernelGGL(k_weights<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1],
+                     static_cast<const T*>(h->mapr[0]), static_cast<const T*>(h->mapr[1]),
+                     static_cast<const T*>(h->wdepth[0]), static_cast<const T*>(h->wdepth[1]),
+                     static_cast<const T*>(h->whard[0]), static_cast<const T*>(h->whard[1]), h->eps2, h->p_norm,
+                     h->gram_w, w[0], w[1], wi[0], wi[1], h->pb);
+  BTTB_LAUNCHED("k_weights");
+  hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, h->pb);
+  BTTB_LAUNCHED("k_fin_gram");
+  return BTTB_OK;
+}
+
+// One CG step (RRCG:2-7) at the outer step's W and alpha; restart_now sets beta = 0.
+template <typename T>
+static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
   T** m = reinterpret_cast<T**>(h->m);
   T** p = reinterpret_cast<T**>(h->p);
   T** l = reinterpret_cast<T**>(h->l);
@@ -376,46 +398,83 @@ static int step_impl(Rrcg* h, int n_inner, hipStream_t s) {
   double* pb1 = h->pb + NSLOT * RGRID;
   double* pb2 = h->pb + 2 * NSLOT * RGRID;
   double* pb3 = h->pb + 3 * NSLOT * RGRID;
-  hipLaunchKernelGGL(k_weights<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1], ma0, ma1,
-                     static_cast<const T*>(h->wdepth[0]), static_cast<const T*>(h->wdepth[1]),
-                     static_cast<const T*>(h->whard[0]), static_cast<const T*>(h->whard[1]), h->eps2, h->p_norm,
-                     h->gram_w, w[0], w[1], wi[0], wi[1], pb0);
-  BTTB_LAUNCHED("k_weights");
+  for (int i = 0; i < 2; ++i) {
+    int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i], static_cast<const T*>(h->wd[i]), s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_grad<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], m[0], m[1], w[0], w[1], ma0, ma1,
+                     h->sc, h->lam[0], h->lam[1], h->gram_w, pb1);
+  BTTB_LAUNCHED("k_grad");
+  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(RB), 0, s, h->sc, pb1, restart_now, h->coupled);
+  BTTB_LAUNCHED("k_fin_beta");
+  hipLaunchKernelGGL(k_dir<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], p[0], p[1], h->sc, pb2);
+  BTTB_LAUNCHED("k_dir");
+  for (int i = 0; i < 2; ++i) {
+    int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i], static_cast<const T*>(h->wd[i]), s);
+    if (rc) return rc;
+  }
+  hipLaunchKernelGGL(k_sumsq2<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, qv[0], qv[1], pb3);
+  BTTB_LAUNCHED("k_sumsq2");
+  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(RB), 0, s, h->sc, pb2, pb3, h->lam[0], h->lam[1], h->coupled);
+  BTTB_LAUNCHED("k_fin_step");
+  hipLaunchKernelGGL(k_update<T>, dim3(RGRID), dim3(RB), 0, s, h->n, h->nd, m[0], m[1], p[0], p[1], w[0], w[1],
+                     rt[0], rt[1], qv[0], qv[1], h->sc, h->gram_w, pb0);
+  BTTB_LAUNCHED("k_update");
   hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, pb0);
   BTTB_LAUNCHED("k_fin_gram");
-  for (int j = 0; j < n_inner; ++j) {
-    for (int i = 0; i < 2; ++i) {
-      int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i],
-                             static_cast<const T*>(h->wd[i]), s);
-      if (rc) return rc;
-    }
-    hipLaunchKernelGGL(k_grad<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], m[0], m[1], w[0], w[1], ma0, ma1,
-                       h->sc, h->lam[0], h->lam[1], h->gram_w, pb1);
-    BTTB_LAUNCHED("k_grad");
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(RB), 0, s, h->sc, pb1, (j == 0 && h->restart) ? 1 : 0,
-                       h->coupled);
-    BTTB_LAUNCHED("k_fin_beta");
-    hipLaunchKernelGGL(k_dir<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], p[0], p[1], h->sc, pb2);
-    BTTB_LAUNCHED("k_dir");
-    for (int i = 0; i < 2; ++i) {
-      int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i],
-                             static_cast<const T*>(h->wd[i]), s);
-      if (rc) return rc;
-    }
-    hipLaunchKernelGGL(k_sumsq2<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, qv[0], qv[1], pb3);
-    BTTB_LAUNCHED("k_sumsq2");
-    hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(RB), 0, s, h->sc, pb2, pb3, h->lam[0], h->lam[1], h->coupled);
-    BTTB_LAUNCHED("k_fin_step");
-    hipLaunchKernelGGL(k_update<T>, dim3(RGRID), dim3(RB), 0, s, h->n, h->nd, m[0], m[1], p[0], p[1], w[0], w[1],
-                       rt[0], rt[1], qv[0], qv[1], h->sc, h->gram_w, pb0);
-    BTTB_LAUNCHED("k_update");
-    hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, pb0);
-    BTTB_LAUNCHED("k_fin_gram");
+  return BTTB_OK;
+}
+
+template <typename T>
+static int step_impl(Rrcg* h, int n_inner, hipStream_t s) {
+  if (h->use_graph) {
+    BTTB_HIP(hipGraphLaunch(h->g_weights, s));
+    for (int j = 0; j < n_inner; ++j)
+      BTTB_HIP(hipGraphLaunch((j == 0 && h->restart) ? h->g_inner_restart : h->g_inner, s));
+    BTTB_HIP(hipGraphLaunch(h->g_outer, s));
+    return BTTB_OK;
   }
-  return outer_update<T>(h, s, 1);
+  int rc = phase_weights<T>(h, s);
+  for (int j = 0; j < n_inner && rc == BTTB_OK; ++j) rc = phase_inner<T>(h, (j == 0 && h->restart) ? 1 : 0, s);
+  return rc == BTTB_OK ? outer_update<T>(h, s, 1) : rc;
+}
+
+// Captures one phase on the private stream into an executable graph.
+template <typename Fn>
+static int capture(Rrcg* h, Fn fn, hipGraphExec_t* out) {
+  for (int i = 0; i < 2; ++i) h->P[i]->t_suspend += 1;  // no timing events inside graphs
+  int rc = BTTB_OK;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    rc = hip_fail(e, "rrcg: hipStreamBeginCapture");
+  } else {
+    rc = fn(h->cap);
+    e = hipStreamEndCapture(h->cap, &g);
+    if (rc == BTTB_OK && e != hipSuccess) rc = hip_fail(e, "rrcg: hipStreamEndCapture");
+    if (rc == BTTB_OK) {
+      e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) rc = hip_fail(e, "rrcg: hipGraphInstantiate");
+    }
+    if (g) (void)hipGraphDestroy(g);
+  }
+  for (int i = 0; i < 2; ++i) h->P[i]->t_suspend -= 1;
+  return rc;
+}
+
+template <typename T>
+static int build_graphs(Rrcg* h) {
+  int rc = capture(h, [&](hipStream_t s) { return phase_weights<T>(h, s); }, &h->g_weights);
+  if (rc == BTTB_OK) rc = capture(h, [&](hipStream_t s) { return phase_inner<T>(h, 1, s); }, &h->g_inner_restart);
+  if (rc == BTTB_OK) rc = capture(h, [&](hipStream_t s) { return phase_inner<T>(h, 0, s); }, &h->g_inner);
+  if (rc == BTTB_OK) rc = capture(h, [&](hipStream_t s) { return outer_update<T>(h, s, 1); }, &h->g_outer);
+  return rc;
 }
 
 static void free_rrcg(Rrcg* h) {
+  for (hipGraphExec_t g : {h->g_weights, h->g_inner_restart, h->g_inner, h->g_outer})
+    if (g) (void)hipGraphExecDestroy(g);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   for (int i = 0; i < 2; ++i) {
     dfree(h->l[i]); dfree(h->w[i]); dfree(h->winv[i]); dfree(h->qv[i]);
   }
@@ -470,6 +529,7 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   h->restart = d->restart ? 1 : 0;
   h->p_norm = d->p_norm;
   h->gram_w = d->gramian_weighted ? 1 : 0;
+  h->use_graph = d->use_graph ? 1 : 0;
   const size_t nb = (size_t)h->n * es, db = (size_t)h->nd * es;
   bool ok = true;
   for (int i = 0; i < 2 && ok; ++i) {
@@ -494,6 +554,12 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   if (rc == BTTB_OK)
     rc = h->precision == BTTB_F64 ? outer_update<double>(h, s, 0) : outer_update<float>(h, s, 0);
   if (rc == BTTB_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(BTTB_EHIP, "rrcg_create: synchronize");
+  if (rc == BTTB_OK && h->use_graph) {
+    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
+      rc = fail(BTTB_EHIP, "rrcg_create: capture stream");
+    else
+      rc = h->precision == BTTB_F64 ? build_graphs<double>(h) : build_graphs<float>(h);
+  }
   if (rc != BTTB_OK) {
     free_rrcg(h);
     return rc;

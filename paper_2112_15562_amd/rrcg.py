@@ -31,7 +31,8 @@ class JointRRCG:
 
     def __init__(self, ops: Sequence[Operator], dobs, wd, wdepth, whard=None, mapr=None, *,
                  lo=-math.inf, hi=math.inf, alpha0=20000.0, q=0.95, alpha_min=0.0, lam=0.0,
-                 eps2=1e-9, coupled=True, restart=True, p_norm=1, gramian="original", m0=None):
+                 eps2=1e-9, coupled=True, restart=True, p_norm=1, gramian="original", m0=None,
+                 use_graph=True):
         self.ops = tuple(ops)
         o = self.ops[0]
         self.dtype, self.device = o.dtype, o.device
@@ -78,6 +79,7 @@ class JointRRCG:
         d.restart = int(bool(restart))
         d.p_norm = int(p_norm)
         d.gramian_weighted = 1 if gramian == "weighted" else 0
+        d.use_graph = int(bool(use_graph))
         self._h = C.c_void_p()
         L.check(L.lib().rrcg_create(C.byref(d), C.c_void_p(self._stream()), C.byref(self._h)), "rrcg_create")
 

@@ -64,12 +64,12 @@ def problem(g, dense: bool):
     return _PROBLEMS[key]
 
 
-def gpu_solver(pk, g, T, data, prm, dtype, state=None):
+def gpu_solver(pk, g, T, data, prm, dtype, state=None, use_graph=True):
     ops = [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=dtype) for i in range(2)]
     m0 = state.m if state is not None else None
     s = pk.JointRRCG(ops, data.dobs, data.wd, data.wdepth, lo=prm.lo, hi=prm.hi, alpha0=prm.alpha0, q=prm.q,
                      alpha_min=prm.alpha_min, lam=prm.lam, eps2=prm.eps2, coupled=prm.coupled,
-                     restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian, m0=m0)
+                     restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian, m0=m0, use_graph=use_graph)
     if state is not None:
         for i in range(2):
             s.p[i].copy_(torch.as_tensor(state.p[i], dtype=dtype, device="cuda"))
@@ -200,3 +200,28 @@ def test_nonfinite_flag_from_host_data(pk):
     with pytest.raises(BTTBError):
         s.run(1, 1, stop_on_chi2=True)
     s.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_graph_replay_equals_eager(pk, dtype):
+    # the captured step graphs are replayed many times, with eager kernels and host
+    # synchronisations in between; every outer step must match the eager launches bitwise
+    g = synth.SMALL
+    _, T, data, _ = problem(g, dense=True)
+    prm = orrcg.Params(**dict(BASE, restart=True))
+    sg, ops = gpu_solver(pk, g, T, data, prm, dtype, use_graph=True)
+    se, _ = gpu_solver(pk, g, T, data, prm, dtype, use_graph=False)
+    x = torch.rand(g.model_shape, dtype=dtype, device="cuda")
+    for k in range(5):
+        sg.step(4)
+        ops[0].matvec(x)            # unrelated eager work between replays
+        torch.cuda.synchronize()
+        se.step(4)
+        for i in range(2):
+            assert np.array_equal(host(sg.m[i]), host(se.m[i]))
+            assert np.array_equal(host(sg.p[i]), host(se.p[i]))
+            assert np.array_equal(host(sg.resid[i]), host(se.resid[i]))
+        a, b = sg.scalars(), se.scalars()
+        assert a["phi"] == b["phi"] and a["alpha"] == b["alpha"] and a["k"] == b["k"] == k + 1
+    sg.close()
+    se.close()
