@@ -19,6 +19,7 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,6 +34,16 @@ if ROOT not in sys.path:
 METRIC = "G+G^T matvec pairs/s & HBM GB/s at 256x256x32; RRCG solve s, FP32 vs FP64"
 HBM_PEAK_GBS = 8000.0
 N_INNER = 50
+COPY_BYTES = 256 << 20   # one side of the calibration copy
+TIMING_REPEAT = 10
+
+# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 0 --no-cpu --no-f64 --pairs 4` (FETCH_SIZE, then WRITE_SIZE),
+# each scaled by the same counter's reading for the calibration copy (COPY_BYTES read,
+# COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
+# paper_2112_15562_amd/csrc must match, else traffic is reported as null.
+TRAFFIC = {"kernel": "fwd_col_eig_sum", "fetch_bytes": 50737938, "write_bytes": 2105344,
+           "csrc_sha256": "96f4a8a0ae6b908248dc76624f12f2e0c950bbacc456d702ba96927864891746"}
 
 
 def parse():
@@ -95,22 +106,63 @@ def product_rate(torch, ops, pairs):
     return n / (e0.elapsed_time(e1) / 1e3)
 
 
-def kernel_bytes(info, esz):
+def copy_probe(torch):
+    """A plain elementwise copy (dst = -src, fp32) of COPY_BYTES: its achieved bandwidth is the
+    practical HBM ceiling, and its counter readings calibrate FETCH_SIZE / WRITE_SIZE."""
+    n = COPY_BYTES // 4
+    src = torch.rand(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    e1.record()
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return {"bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES, "avg_us": 1e6 * dt,
+            "GBps": 2 * COPY_BYTES / dt / 1e9}
+
+
+def kernel_source_digest():
+    d = os.path.join(ROOT, "paper_2112_15562_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_for(kernel):
+    if TRAFFIC is None or TRAFFIC["csrc_sha256"] != kernel_source_digest() or TRAFFIC["kernel"] != kernel:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
+
+def kernel_bytes(info, esz, weighted=True):
     """Bytes each product kernel must move per launch (batch 1): its inputs once and its
-    outputs once.  Complex values are 2 esz bytes."""
+    outputs once, including the diagonal weights the weighted products (the solve's) read.
+    Complex values are 2 esz bytes."""
     nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
     Px, Py = info["Px"], info["Py"]
     K2 = Py // 2 + 1
     c = 2 * esz
     nch = info["layer_chunks"]
     eig = nz * K2 * Px * c
+    w = 2 if weighted else 1
     return {
-        "fwd_row_r2c": nz * nx * ny * esz + nz * K2 * nx * c,
+        "fwd_row_r2c": w * nz * nx * ny * esz + nz * K2 * nx * c,
         "fwd_col_eig_sum": eig + nz * K2 * nx * c + nch * K2 * sx * c,
-        "fwd_row_c2r": nch * K2 * sx * c + sx * sy * esz,
-        "adj_row_r2c": sx * sy * esz + K2 * sx * c,
+        "fwd_row_c2r": nch * K2 * sx * c + w * sx * sy * esz,
+        "adj_row_r2c": w * sx * sy * esz + K2 * sx * c,
         "adj_col_conj_eig": eig + K2 * sx * c + nz * K2 * nx * c,
-        "adj_row_c2r": nz * K2 * nx * c + nz * nx * ny * esz,
+        "adj_row_c2r": nz * K2 * nx * c + w * nz * nx * ny * esz,
     }
 
 
@@ -190,12 +242,14 @@ def main():
     value = pairs / t32
 
     # per-kernel HIP-event timing in the same solve, launched kernel by kernel (graphs
-    # hold no timing events); two outer steps
+    # hold no timing events); two outer steps, each product kernel launched TIMING_REPEAT
+    # times back to back between its events (idempotent: every kernel reads one buffer
+    # and writes another)
     log("bench: fp32 per-kernel timing")
     se = solver(pk, torch, ops32, dobs, wd, wdepth, use_graph=False)
     launches = 2 * (N_INNER * 3 + 3) + 16
     for op in ops32:
-        op.timing_enable(launches)
+        op.timing_enable(launches, TIMING_REPEAT)
     for _ in range(2):
         se.step(N_INNER)
     torch.cuda.synchronize()
@@ -218,6 +272,9 @@ def main():
     kernel_table = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1),
                         "GBps": kernel_bytes(info32, 4)[k] / (ms / max(n, 1) * 1e-3) / 1e9 if n else None}
                     for k, (ms, n) in tot.items()}
+
+    log("bench: copy calibration")
+    copy = copy_probe(torch)
 
     # ---------------- product throughput ----------------
     log("bench: product rates")
@@ -278,8 +335,9 @@ def main():
                              "bytes_per_pair": {"f32": b32, "f64": b64}},
         "final_chi2": {"phi": sc32["phi"], "threshold": sc32["threshold"], "alpha": sc32["alpha"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": kb,
-                     "avg_launch_us": 1e3 * avg_ms},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom), "bytes_per_launch": kb,
+                     "avg_launch_us": 1e3 * avg_ms, "csrc_sha256": kernel_source_digest()[:16]},
+        "copy_probe": copy,
         "kernels": kernel_table,
         "cpu_baseline": cpu,
     }

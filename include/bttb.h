@@ -142,16 +142,20 @@ BTTB_API int bttb_plan_eigenvalues(bttb_plan plan, void* out, void* stream);
 BTTB_API int bttb_destroy(bttb_plan plan);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around each kernel
- * of the products, for measurement.  bttb_timing_enable(plan, n) allocates n event
- * pairs (n = 0 disables and frees them; not to be called during stream capture);
- * launches beyond n are not timed.  bttb_timing_read synchronises on the events, adds
- * the elapsed milliseconds and launch counts of every timed kernel into
- * total_ms[BTTB_NKERNELS] and count[BTTB_NKERNELS] (overwritten), and starts over.
+ * of the products, for measurement.  bttb_timing_enable(plan, n, repeat) allocates n
+ * event pairs (n = 0 disables and frees them; not to be called during stream capture);
+ * launches beyond n are not timed.  While timing is on, each timed kernel is launched
+ * `repeat` (>= 1) times back to back between its two events; every kernel reads one
+ * buffer and writes another, so the repeats leave the results unchanged and the
+ * per-launch time excludes the event overhead.  bttb_timing_read synchronises on the
+ * events, adds the elapsed milliseconds and launch counts (repeats included) of every
+ * timed kernel into total_ms[BTTB_NKERNELS] and count[BTTB_NKERNELS] (overwritten),
+ * and starts over.
  * Kernel ids: 0 forward row transform, 1 forward column pass (eigenvalue multiply and
  * layer sum), 2 forward inverse row transform, 3 transpose row transform, 4 transpose
  * column pass (conjugate eigenvalue multiply), 5 transpose inverse row transform. */
 #define BTTB_NKERNELS 6
-BTTB_API int bttb_timing_enable(bttb_plan plan, int max_launches);
+BTTB_API int bttb_timing_enable(bttb_plan plan, int max_launches, int repeat);
 BTTB_API int bttb_timing_read(bttb_plan plan, double* total_ms, int* count);
 
 /* ---------------------------------------------------------------------------------- */

@@ -92,7 +92,7 @@ def lib() -> C.CDLL:
         "rrcg_write_scalars": [vp, C.POINTER(RrcgScalars), vp],
         "rrcg_refresh": [vp, vp],
         "rrcg_destroy": [vp],
-        "bttb_timing_enable": [vp, i],
+        "bttb_timing_enable": [vp, i, i],
         "bttb_timing_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)],
     }
     for name, args in sig.items():

@@ -66,6 +66,7 @@ struct Plan {
   size_t eig_bytes, scratch_bytes;
   // optional per-kernel event timing
   int t_cap, t_used;
+  int t_repeat;      // launches of each timed kernel between its two events
   int t_suspend;     // > 0 while kernels are being captured into a graph
   hipEvent_t* t_ev;  // [2 * t_cap]
   int* t_kid;        // [t_cap]

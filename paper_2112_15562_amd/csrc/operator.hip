@@ -455,85 +455,99 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
   const long long V_fcs = (long long)P->lds * P->ldk;  // power-of-two path: one row-major partial
   const long long V_bs = std::max((long long)P->nchunk_max * V_cs, (long long)P->nchunk_max * V_fcs);
   const int TPFx = P->Px / 8;
+  // One stage: its kernel launch, bracketed by timing events when timing is on.
+  auto stage = [&](int kid, auto&& launch) -> int {
+    const int tk = t_begin(P, kid, s);
+    const int n = tk >= 0 ? P->t_repeat : 1;
+    for (int i = 0; i < n; ++i) {
+      const int rc = launch();
+      if (rc) return rc;
+    }
+    t_end(P, tk, s);
+    return BTTB_OK;
+  };
   for (int b0 = 0; b0 < batch; b0 += P->max_batch) {
     const int nb = std::min(P->max_batch, batch - b0);
     const T* x = in + b0 * in_stride;
     T* y = out + b0 * out_stride;
     int rc;
-    int tk;
     if (P->fast) {
       const int gs = small_row_groups(P, P->sx, nb);
       if (op == BTTB_OP_FORWARD) {
-        tk = t_begin(P, KT_FWD_ROW, s);
-        rc = fast_row_r2c<T>(false, x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->Py, P->row_fpb, twy,
-                             nb, s);
-        t_end(P, tk, s);
+        rc = stage(KT_FWD_ROW, [&]() -> int {
+          return fast_row_r2c<T>(false, x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->Py,
+                                 P->row_fpb, twy, nb, s);
+        });
         if (rc) return rc;
-        tk = t_begin(P, KT_FWD_COL, s);
-        rc = fast_col<T>(true, U, U_bs, eig, V, V_bs, V_fcs, P->nz, P->nx, P->sx, P->ldx, P->ldk, P->K2, P->Px,
-                         P->col_fpb, P->nchunk, twx, nb, s);
-        t_end(P, tk, s);
+        rc = stage(KT_FWD_COL, [&]() -> int {
+          return fast_col<T>(true, U, U_bs, eig, V, V_bs, V_fcs, P->nz, P->nx, P->sx, P->ldx, P->ldk, P->K2, P->Px,
+                             P->col_fpb, P->nchunk, twx, nb, s);
+        });
         if (rc) return rc;
-        tk = t_begin(P, KT_FWD_INV, s);
-        rc = fast_row_c2r<T>(true, V, V_bs, V_fcs, P->nchunk, y, out_stride, wd, 1, P->sx, P->sy, P->ldk, P->Py, gs,
-                             twy, nb, s);
-        t_end(P, tk, s);
+        rc = stage(KT_FWD_INV, [&]() -> int {
+          return fast_row_c2r<T>(true, V, V_bs, V_fcs, P->nchunk, y, out_stride, wd, 1, P->sx, P->sy, P->ldk,
+                                 P->Py, gs, twy, nb, s);
+        });
         if (rc) return rc;
       } else {
-        tk = t_begin(P, KT_ADJ_ROW, s);
-        rc = fast_row_r2c<T>(true, x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->ldk, P->Py, gs, twy, nb, s);
-        t_end(P, tk, s);
+        rc = stage(KT_ADJ_ROW, [&]() -> int {
+          return fast_row_r2c<T>(true, x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->ldk, P->Py, gs, twy, nb, s);
+        });
         if (rc) return rc;
-        tk = t_begin(P, KT_ADJ_COL, s);
-        rc = fast_col<T>(false, V, V_bs, eig, U, U_bs, 0, P->nz, P->sx, P->nx, P->ldk, P->ldx, P->K2, P->Px,
-                         P->col_fpb, P->nchunk, twx, nb, s);
-        t_end(P, tk, s);
+        rc = stage(KT_ADJ_COL, [&]() -> int {
+          return fast_col<T>(false, V, V_bs, eig, U, U_bs, 0, P->nz, P->sx, P->nx, P->ldk, P->ldx, P->K2, P->Px,
+                             P->col_fpb, P->nchunk, twx, nb, s);
+        });
         if (rc) return rc;
-        tk = t_begin(P, KT_ADJ_INV, s);
-        rc = fast_row_c2r<T>(false, U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->Py,
-                             P->row_fpb, twy, nb, s);
-        t_end(P, tk, s);
+        rc = stage(KT_ADJ_INV, [&]() -> int {
+          return fast_row_c2r<T>(false, U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->Py,
+                                 P->row_fpb, twy, nb, s);
+        });
         if (rc) return rc;
       }
       continue;
     }
     if (op == BTTB_OP_FORWARD) {
-      tk = t_begin(P, KT_FWD_ROW, s);
-      rc = launch_row_r2c<T>(x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->K2, P->row_fpb, P->fy,
-                             twy, nb, s);
-      t_end(P, tk, s);
+      rc = stage(KT_FWD_ROW, [&]() -> int {
+        return launch_row_r2c<T>(x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->K2, P->row_fpb,
+                                 P->fy, twy, nb, s);
+      });
       if (rc) return rc;
-      ColFwdArgs<T> a{U, U_bs, eig, V, V_bs, V_cs, P->nz, P->nx, P->sx, P->ldx, P->lds, P->K2, P->col_fpb,
-                      P->nchunk, P->fx, twx};
-      dim3 grid(ceil_div(P->K2, P->col_fpb), P->nchunk, nb);
-      tk = t_begin(P, KT_FWD_COL, s);
-      hipLaunchKernelGGL(k_col_fwd<T>, grid, dim3(P->col_fpb * TPFx), (size_t)P->col_fpb * P->Px * sizeof(cx<T>),
-                         s, a);
-      t_end(P, tk, s);
-      BTTB_LAUNCHED("k_col_fwd");
-      tk = t_begin(P, KT_FWD_INV, s);
-      rc = launch_row_c2r<T>(V, V_bs, V_cs, P->nchunk, y, out_stride, wd, 1, P->sx, P->sy, P->lds, P->K2,
-                             P->row_fpb, P->fy, twy, nb, s);
-      t_end(P, tk, s);
+      rc = stage(KT_FWD_COL, [&]() -> int {
+        ColFwdArgs<T> a{U, U_bs, eig, V, V_bs, V_cs, P->nz, P->nx, P->sx, P->ldx, P->lds, P->K2, P->col_fpb,
+                        P->nchunk, P->fx, twx};
+        dim3 grid(ceil_div(P->K2, P->col_fpb), P->nchunk, nb);
+        hipLaunchKernelGGL(k_col_fwd<T>, grid, dim3(P->col_fpb * TPFx),
+                           (size_t)P->col_fpb * P->Px * sizeof(cx<T>), s, a);
+        BTTB_LAUNCHED("k_col_fwd");
+        return BTTB_OK;
+      });
+      if (rc) return rc;
+      rc = stage(KT_FWD_INV, [&]() -> int {
+        return launch_row_c2r<T>(V, V_bs, V_cs, P->nchunk, y, out_stride, wd, 1, P->sx, P->sy, P->lds, P->K2,
+                                 P->row_fpb, P->fy, twy, nb, s);
+      });
       if (rc) return rc;
     } else {
-      tk = t_begin(P, KT_ADJ_ROW, s);
-      rc = launch_row_r2c<T>(x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->lds, P->K2, P->row_fpb, P->fy, twy,
-                             nb, s);
-      t_end(P, tk, s);
+      rc = stage(KT_ADJ_ROW, [&]() -> int {
+        return launch_row_r2c<T>(x, in_stride, wd, V, V_bs, 1, P->sx, P->sy, P->lds, P->K2, P->row_fpb, P->fy,
+                                 twy, nb, s);
+      });
       if (rc) return rc;
-      ColAdjArgs<T> a{V, V_bs, eig, U, U_bs, P->nz, P->sx, P->nx, P->lds, P->ldx, P->K2, P->col_fpb,
-                      P->nchunk, P->fx, twx};
-      dim3 grid(ceil_div(P->K2, P->col_fpb), P->nchunk, nb);
-      tk = t_begin(P, KT_ADJ_COL, s);
-      hipLaunchKernelGGL(k_col_adj<T>, grid, dim3(P->col_fpb * TPFx), (size_t)P->col_fpb * P->Px * sizeof(cx<T>),
-                         s, a);
-      t_end(P, tk, s);
-      BTTB_LAUNCHED("k_col_adj");
-      tk = t_begin(P, KT_ADJ_INV, s);
-      rc = launch_row_c2r<T>(U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->K2, P->row_fpb,
-                             P->fy, twy, nb, s);
-      t_end(P, tk, s);
+      rc = stage(KT_ADJ_COL, [&]() -> int {
+        ColAdjArgs<T> a{V, V_bs, eig, U, U_bs, P->nz, P->sx, P->nx, P->lds, P->ldx, P->K2, P->col_fpb,
+                        P->nchunk, P->fx, twx};
+        dim3 grid(ceil_div(P->K2, P->col_fpb), P->nchunk, nb);
+        hipLaunchKernelGGL(k_col_adj<T>, grid, dim3(P->col_fpb * TPFx),
+                           (size_t)P->col_fpb * P->Px * sizeof(cx<T>), s, a);
+        BTTB_LAUNCHED("k_col_adj");
+        return BTTB_OK;
+      });
+      if (rc) return rc;
+      rc = stage(KT_ADJ_INV, [&]() -> int {
+        return launch_row_c2r<T>(U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->K2,
+                                 P->row_fpb, P->fy, twy, nb, s);
+      });
       if (rc) return rc;
     }
   }
@@ -792,10 +806,12 @@ static void timing_free(Plan* P) {
   P->t_cap = P->t_used = 0;
 }
 
-extern "C" int bttb_timing_enable(bttb_plan plan, int max_launches) {
+extern "C" int bttb_timing_enable(bttb_plan plan, int max_launches, int repeat) {
   Plan* P = as_plan(plan);
-  if (!P || max_launches < 0) return fail(BTTB_EINVAL, "bttb_timing_enable: bad argument");
+  if (!P || max_launches < 0 || repeat < 1 || repeat > 1000)
+    return fail(BTTB_EINVAL, "bttb_timing_enable: bad argument");
   timing_free(P);
+  P->t_repeat = repeat;
   if (max_launches == 0) return BTTB_OK;
   P->t_ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches]();
   P->t_kid = new (std::nothrow) int[max_launches];
@@ -828,7 +844,7 @@ extern "C" int bttb_timing_read(bttb_plan plan, double* total_ms, int* count) {
     float ms = 0.0f;
     BTTB_HIP(hipEventElapsedTime(&ms, P->t_ev[2 * i], P->t_ev[2 * i + 1]));
     total_ms[P->t_kid[i]] += ms;
-    count[P->t_kid[i]] += 1;
+    count[P->t_kid[i]] += P->t_repeat;
   }
   P->t_used = 0;
   return BTTB_OK;

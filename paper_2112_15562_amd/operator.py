@@ -105,9 +105,10 @@ class Operator:
         L.check(L.lib().bttb_set_launch(self.plan, col_fft_per_block, row_fft_per_block, layer_chunks),
                 "bttb_set_launch")
 
-    def timing_enable(self, max_launches: int) -> None:
-        """Record HIP events around each product kernel (max_launches kernels)."""
-        L.check(L.lib().bttb_timing_enable(self.plan, int(max_launches)), "bttb_timing_enable")
+    def timing_enable(self, max_launches: int, repeat: int = 1) -> None:
+        """Record HIP events around each product kernel (max_launches kernels), each kernel
+        launched `repeat` times back to back between its events."""
+        L.check(L.lib().bttb_timing_enable(self.plan, int(max_launches), int(repeat)), "bttb_timing_enable")
 
     def timing_read(self) -> dict:
         """{kernel name: (total ms, launches)} since the last read; synchronises."""

@@ -228,6 +228,25 @@ def test_launch_shape_and_repeatability(pk):
     op.close()
 
 
+@pytest.mark.parametrize("g", [synth.MID, synth.SUB])
+def test_timing_with_repeats_leaves_results_unchanged(pk, g):
+    # power-of-two (register FFT) and radix-3 (generic) paths
+    x, _ = synth.random_boxes(g)
+    v = synth.normal_like(g.data_shape, 2, 3)
+    op = pk.Operator.from_geometry(pk.MAGNETIC, g, dtype=torch.float32)
+    y0 = host(op.matvec(dev(x, torch.float32)))
+    z0 = host(op.rmatvec(dev(v, torch.float32)))
+    op.timing_enable(64, repeat=3)
+    assert np.array_equal(y0, host(op.matvec(dev(x, torch.float32))))
+    assert np.array_equal(z0, host(op.rmatvec(dev(v, torch.float32))))
+    t = op.timing_read()
+    assert all(n == 3 for ms, n in t.values()), t
+    assert all(ms > 0 for ms, n in t.values()), t
+    op.timing_enable(0)
+    assert all(n == 0 for ms, n in op.timing_read().values())
+    op.close()
+
+
 def test_error_paths(pk):
     from paper_2112_15562_amd import _lib as L
     with pytest.raises(L.BTTBError) as e:
