@@ -13,6 +13,7 @@
 
 #include "common.h"
 #include "fft_reg.h"
+#include "rrcg_fuse.h"
 
 namespace bttb {
 
@@ -55,8 +56,12 @@ struct FRowArgs {
 
 // ROWOUT = false: half spectra stored column-major out[l][k2][row] (ld = padded rows) through an
 // LDS transpose; ROWOUT = true: row-major out[l][row][k2] (ld = padded K2) straight from registers.
-template <typename T, int N, bool ROWOUT>
-__global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a) {
+// MODE = FUSE_DIR (ROWOUT = false, the forward product inside the CG step): beta is summed from
+// the partials of ||l||^2 at the start, the input is the new direction p = l + beta p (RRCG:5),
+// written back, and the block partials of (p, l) and ||p||^2 are stored for the step length.
+template <typename T, int N, bool ROWOUT, int MODE>
+__global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
+  static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT), "fused form");
   using P = Pow2<N>;
   constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -75,16 +80,45 @@ __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a) {
   const T* sc = a.scale ? a.scale + lofs : nullptr;
   const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
   cx<T> v[8];
+  double acc[2] = {0.0, 0.0};
+  if constexpr (MODE == FUSE_DIR) {
+    double bt[2], L[2];
+    beta_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.restart, fz.coupled, bt, L);
+    if (fz.lead && flat_block() == 0 && threadIdx.x == 0) record_beta(fz.sc, bt, L);
+    const double beta = bt[fz.self];
+    const T* lv = fz.l + lofs;
+    T* pv = fz.p + lofs;
+    auto dir = [&](long long o) -> T {
+      const double lo = lv[o];
+      const T pn = (T)(lo + beta * (double)pv[o]);
+      pv[o] = pn;
+      acc[0] += (double)pn * lo;
+      acc[1] += (double)pn * (double)pn;
+      return pn * sc[o];
+    };
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int n = t + i * TPF;
-    T xa = T(0), xb = T(0);
-    if (n < a.ncols) {
-      const long long oa = (long long)r0 * a.ncols + n;
-      if (ra) xa = sc ? src[oa] * sc[oa] : src[oa];
-      if (rb) xb = sc ? src[oa + a.ncols] * sc[oa + a.ncols] : src[oa + a.ncols];
+    for (int i = 0; i < 8; ++i) {
+      const int n = t + i * TPF;
+      T xa = T(0), xb = T(0);
+      if (n < a.ncols) {
+        const long long oa = (long long)r0 * a.ncols + n;
+        if (ra) xa = dir(oa);
+        if (rb) xb = dir(oa + a.ncols);
+      }
+      v[i] = cx<T>{xa, xb};
     }
-    v[i] = cx<T>{xa, xb};
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int n = t + i * TPF;
+      T xa = T(0), xb = T(0);
+      if (n < a.ncols) {
+        const long long oa = (long long)r0 * a.ncols + n;
+        if (ra) xa = sc ? src[oa] * sc[oa] : src[oa];
+        if (rb) xb = sc ? src[oa + a.ncols] * sc[oa + a.ncols] : src[oa + a.ncols];
+      }
+      v[i] = cx<T>{xa, xb};
+    }
   }
   F.template run<false>(v, buf, t, gsync);
   // X_a[k] = (Z[k] + conj Z[N-k]) / 2,  X_b[k] = (Z[k] - conj Z[N-k]) / (2i),  k <= N/2
@@ -130,13 +164,20 @@ __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a) {
     const int k2 = idx / RT, rr = idx - k2 * RT;
     dst[(long long)k2 * a.ld + rr] = smem[(rr >> 1) * BS + (rr & 1) * K2 + k2];
   }
+  if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0);
 }
 
 // ROWIN = false: half spectra read column-major in[c][l][k2][row] (ld = padded rows), summed over
 // nsum partials, through an LDS transpose; ROWIN = true: row-major in[l][row][k2] (ld = padded
 // K2, nsum = 1) read straight into the strided layout.
-template <typename T, int N, bool ROWIN>
-__global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a) {
+// MODE = FUSE_QQ (ROWIN = true, the forward product inside the CG step): block partials of
+// ||q||^2 for the output q (for the step length of RRCG:6).
+// MODE = FUSE_GRAD (ROWIN = false, the transpose product inside the CG step): the output is the
+// gradient l of RRCG:4, from the Gramian scalars summed at the start, with its block partials
+// of ||l||^2 (for beta of RRCG:5).
+template <typename T, int N, bool ROWIN, int MODE>
+__global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a, Fuse<T> fz) {
+  static_assert(MODE == FUSE_NONE || (MODE == FUSE_QQ && ROWIN) || (MODE == FUSE_GRAD && !ROWIN), "fused form");
   using P = Pow2<N>;
   constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -149,6 +190,8 @@ __global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a) {
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
   F.init(a.tw, t);
+  double gg[3] = {0.0, 0.0, 0.0};  // Gramian scalars for the gradient form
+  if constexpr (MODE == FUSE_GRAD) gram_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lead && flat_block() == 0, gg);
   const int r0 = tile * RT + 2 * f;
   const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
   cx<T> v[8];
@@ -224,15 +267,49 @@ __global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a) {
   const long long lofs = (long long)l * a.nrows * a.ncols;
   T* dst = reinterpret_cast<T*>(a.out) + b * a.out_bs + lofs;
   const T* sc = a.scale ? a.scale + lofs : nullptr;
+  if constexpr (MODE == FUSE_GRAD) {
+    const double al = fz.sc[S_ALPHA + fz.self], lam = fz.lam[fz.self];
+    const double g11 = gg[0], g22 = gg[1], g12 = gg[2];
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = t + i * TPF;
+      if (q < a.ncols) {
+        const long long o = (long long)r0 * a.ncols + q;
+        if (ra) {
+          const T g = grad_element(fz, lofs + o, v[i].re * sc[o], al, lam, g11, g22, g12);
+          dst[o] = g;
+          acc[0] += (double)g * (double)g;
+        }
+        if (rb) {
+          const T g = grad_element(fz, lofs + o + a.ncols, v[i].im * sc[o + a.ncols], al, lam, g11, g22, g12);
+          dst[o + a.ncols] = g;
+          acc[0] += (double)g * (double)g;
+        }
+      }
+    }
+    block_partials<1>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_L1 : PB_L0);
+    return;
+  }
+  double acc[1] = {0.0};
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int q = t + i * TPF;
     if (q < a.ncols) {
       const long long o = (long long)r0 * a.ncols + q;
-      if (ra) dst[o] = sc ? v[i].re * sc[o] : v[i].re;
-      if (rb) dst[o + a.ncols] = sc ? v[i].im * sc[o + a.ncols] : v[i].im;
+      if (ra) {
+        const T y = sc ? v[i].re * sc[o] : v[i].re;
+        dst[o] = y;
+        if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
+      }
+      if (rb) {
+        const T y = sc ? v[i].im * sc[o + a.ncols] : v[i].im;
+        dst[o + a.ncols] = y;
+        if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
+      }
     }
   }
+  if constexpr (MODE == FUSE_QQ) block_partials<1>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_Q1 : PB_Q0);
 }
 
 // ------------------------------------------------------------------------------------
@@ -544,16 +621,24 @@ size_t fast_col_lds(int N, size_t esz, int G, bool fwd) {
 
 template <typename T>
 int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L,
-                 int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s) {
+                 int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s,
+                 const Fuse<T>* fz) {
   FRowArgs<T> a{in, in_bs, scale, out, out_bs, 0, 1, L, nrows, ncols, ld, N / 2 + 1, G, ceil_div(nrows, 2 * G), tw};
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
-  if (rowout) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, true>), grid, block, sh, s, a)
+  const Fuse<T> f0{};
+  if (fz) {
+    if (rowout || batch != 1 || !scale || (long long)grid.x > fz->pbs)
+      return fail(BTTB_EINVAL, "fast_row_r2c: fused form needs one column-major launch of at most pbs blocks");
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, false, FUSE_DIR>), grid, block, sh, s, a, *fz)
+    BTTB_POW2_SWITCH(N, BTTB_L)
+#undef BTTB_L
+  } else if (rowout) {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, true, FUSE_NONE>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   } else {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, false>), grid, block, sh, s, a)
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, false, FUSE_NONE>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   }
@@ -564,17 +649,28 @@ int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T
 template <typename T>
 int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
                  const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
-                 hipStream_t s) {
+                 hipStream_t s, const Fuse<T>* fz) {
   FRowArgs<T> a{reinterpret_cast<const T*>(in), in_bs, scale, reinterpret_cast<cx<T>*>(out), out_bs, in_cs,
                 nsum, L, nrows, ncols, ld, N / 2 + 1, G, ceil_div(nrows, 2 * G), tw};
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
-  if (rowin) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true>), grid, block, sh, s, a)
+  const Fuse<T> f0{};
+  if (fz && (batch != 1 || !scale || (long long)grid.x > fz->pbs))
+    return fail(BTTB_EINVAL, "fast_row_c2r: fused form needs one weighted launch of at most pbs blocks");
+  if (fz && rowin) {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_QQ>), grid, block, sh, s, a, *fz)
+    BTTB_POW2_SWITCH(N, BTTB_L)
+#undef BTTB_L
+  } else if (fz) {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, false, FUSE_GRAD>), grid, block, sh, s, a, *fz)
+    BTTB_POW2_SWITCH(N, BTTB_L)
+#undef BTTB_L
+  } else if (rowin) {
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_NONE>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   } else {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, false>), grid, block, sh, s, a)
+#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, false, FUSE_NONE>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   }
@@ -604,13 +700,14 @@ int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>
 }
 
 template int fast_row_r2c<float>(bool, const float*, long long, const float*, cx<float>*, long long, int, int, int, int,
-                                 int, int, const cx<float>*, int, hipStream_t);
+                                 int, int, const cx<float>*, int, hipStream_t, const Fuse<float>*);
 template int fast_row_r2c<double>(bool, const double*, long long, const double*, cx<double>*, long long, int, int, int,
-                                  int, int, int, const cx<double>*, int, hipStream_t);
+                                  int, int, int, const cx<double>*, int, hipStream_t, const Fuse<double>*);
 template int fast_row_c2r<float>(bool, const cx<float>*, long long, long long, int, float*, long long, const float*, int,
-                                 int, int, int, int, int, const cx<float>*, int, hipStream_t);
+                                 int, int, int, int, int, const cx<float>*, int, hipStream_t, const Fuse<float>*);
 template int fast_row_c2r<double>(bool, const cx<double>*, long long, long long, int, double*, long long, const double*,
-                                  int, int, int, int, int, int, const cx<double>*, int, hipStream_t);
+                                  int, int, int, int, int, int, const cx<double>*, int, hipStream_t,
+                                  const Fuse<double>*);
 template int fast_col<float>(bool, const cx<float>*, long long, const cx<float>*, cx<float>*, long long, long long,
                              int, int, int, int, int, int, int, int, int, const cx<float>*, int, hipStream_t);
 template int fast_col<double>(bool, const cx<double>*, long long, const cx<double>*, cx<double>*, long long,

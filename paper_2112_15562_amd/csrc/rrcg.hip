@@ -4,20 +4,23 @@
 // State per data set i: the model m (original space), the search direction p (weighted
 // space), the current weights w = W_depth W_hard W_L1 and winv = 1/w, the weighted
 // residual r~ = W_d (A m - d), and the scalars (FP64, device resident).  One outer step:
-//   w, winv from m (eq. WL, eq. W)                                        k_weights
+//   w, winv from m (eq. WL, eq. W), Gramian scalars                       k_weights
 //   repeat n_inner times:
-//     l = A~^T r~ + alpha (w m - w m_apr) + lambda l_G                    apply + k_grad
-//         l_G on m (RRCG:2-3) or on m~ = w m (steepestascenta/b)
-//     beta = sum ||l||^2 / sum ||l_prev||^2 (0 at a restart), p = l + beta p   fin_beta, k_dir
-//     q = A~ p                                                            apply
-//     s = sum (p,l) / sum (||q||^2 + (alpha + lambda) ||p||^2)            fin_step
-//     m <- m - s p / w   (m~ <- m~ - s p, RRCG:7-8);  r~ <- r~ - s q       k_update
+//     l = A~^T r~ + alpha (w m - w m_apr) + lambda l_G                    transpose product
+//         l_G on m (RRCG:2-3) or on m~ = w m (steepestascenta/b)          (+ k_grad)
+//     beta = sum ||l||^2 / sum ||l_prev||^2 (0 at a restart)
+//     p = l + beta p,  q = A~ p                                            forward product
+//     s = sum (p,l) / sum (||q||^2 + (alpha + lambda) ||p||^2)             (+ k_dir, k_sumsq2)
+//     m <- m - s p / w   (m~ <- m~ - s p, RRCG:7-8);  r~ <- r~ - s q;
+//     Gramian scalars of the new m                                         k_update
 //   m <- clip(m, lo, hi)                                                  k_clip
 //   r~ = W_d (A m - d), Phi = ||r~||^2, chi^2 test, alpha <- max(q alpha, alpha_min)
-//   unless frozen                                                         k_resid, fin_outer
-// Dot products are accumulated in FP64 per block (fixed grid) and summed in a fixed
-// order by single-block kernels, so results are bitwise repeatable; no scalar leaves
-// the device during a step.
+//   unless frozen                                                         k_resid
+// On power-of-two plans the gradient, direction and ||q||^2 are computed inside the
+// products' row transforms; otherwise by the bracketed elementwise kernels.  Dot
+// products are accumulated in FP64 per block and summed in a fixed order by the last
+// block to finish, so results are bitwise repeatable; no scalar leaves the device
+// during a step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,19 +29,12 @@
 #include <new>
 
 #include "common.h"
+#include "rrcg_fuse.h"
 
 namespace bttb {
 
 constexpr int RB = 256;     // threads per elementwise block
 constexpr int RGRID = 512;  // elementwise blocks (fixed, so reductions are repeatable)
-constexpr int NSLOT = 8;    // partial-sum slots
-
-// Scalar array layout (doubles).
-enum {
-  S_ALPHA = 0, S_LPREV = 2, S_PHI = 4, S_THR = 6, S_BETA = 7, S_STEP = 9, S_GRAM = 11, S_FROZEN = 12,
-  S_K = 14, S_CONV = 15, S_NONFIN = 16, S_G11 = 17, S_G22 = 18, S_G12 = 19, S_L = 20, S_PL = 22,
-  S_PP = 24, S_QQ = 26, S_COUNT = 32
-};
 
 struct Rrcg {
   Plan* P[2];
@@ -51,6 +47,7 @@ struct Rrcg {
   const void* mapr[2];
   double lo[2], hi[2], alpha0[2], q[2], amin[2], lam[2], eps2;
   int coupled, restart, p_norm, gram_w;
+  int fused;       // both plans on the power-of-two path: CG pieces ride on the products
   void* m[2];      // caller-owned
   void* p[2];      // caller-owned
   void* rt[2];     // caller-owned
@@ -58,61 +55,27 @@ struct Rrcg {
   void* w[2];
   void* winv[2];
   void* qv[2];
-  double* sc;  // [S_COUNT]
-  double* pb;  // [4][NSLOT][RGRID] partial sums (four independent reductions)
+  double* sc;      // [S_COUNT]
+  double* pb;      // [PB_NSLOT][pbs] partial sums
+  int* pbn;        // [PB_NSLOT]
+  int pbs;
   // HIP graphs of the step's phases (captured once at creation on a private stream)
   int use_graph;
   hipStream_t cap;
   hipGraphExec_t g_weights, g_inner_restart, g_inner, g_outer;
 };
 
-// Sum of v over the block, written to out[slot * RGRID + blockIdx.x] for each slot.
-template <int K>
-__device__ __forceinline__ void block_partials(double (&v)[K], double* out) {
-  __shared__ double sh[K][RB / 64];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double x = v[k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[k] = x;
-  }
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < RB / 64; ++w) s += sh[k][w];
-      out[k * RGRID + blockIdx.x] = s;
-    }
-  }
-}
-
-// Fixed-order sum of RGRID partials of `slot` (single block of RB threads).
-__device__ double sum_partials(const double* pb, int slot) {
-  __shared__ double sh[RB];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < RGRID; i += RB) s += pb[slot * RGRID + i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = RB / 2; w >= 1; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
+struct Red {  // where a reducing kernel puts its partials
+  double* pb;
+  int* pbn;
+  int pbs;
+};
 
 template <typename T>
 __global__ void __launch_bounds__(RB) k_weights(long long n, const T* m0, const T* m1, const T* ma0, const T* ma1,
                                                 const T* wz0, const T* wz1, const T* wh0, const T* wh1, double eps2,
-                                                int p_norm, int gram_w, T* w0, T* w1, T* wi0, T* wi1, double* pb) {
+                                                int p_norm, int gram_w, T* w0, T* w1, T* wi0, T* wi1, double* sc,
+                                                Red rd) {
   double v[3] = {0.0, 0.0, 0.0};
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
     const double a = m0[j], b = m1[j];
@@ -134,25 +97,17 @@ __global__ void __launch_bounds__(RB) k_weights(long long n, const T* m0, const 
     v[1] += u1 * u1;
     v[2] += u0 * u1;
   }
-  block_partials<3>(v, pb);
+  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11);
 }
 
-__global__ void __launch_bounds__(RB) k_fin_gram(double* sc, const double* pb) {
-  const double g11 = sum_partials(pb, 0), g22 = sum_partials(pb, 1), g12 = sum_partials(pb, 2);
-  if (threadIdx.x == 0) {
-    sc[S_G11] = g11;
-    sc[S_G22] = g22;
-    sc[S_G12] = g12;
-    if (!isfinite(g11) || !isfinite(g22) || !isfinite(g12)) sc[S_NONFIN] = 1.0;
-  }
-}
-
-// l = A~^T r~ (already in l) + alpha (w m - w m_apr) + lambda l_G;  partials ||l_i||^2.
+// l = A~^T r~ (already in l) + alpha (w m - w m_apr) + lambda l_G;  partials of ||l_i||^2.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_grad(long long n, T* l0, T* l1, const T* m0, const T* m1, const T* w0,
-                                             const T* w1, const T* ma0, const T* ma1, const double* sc,
-                                             double lam0, double lam1, int gram_w, double* pb) {
-  const double g11 = sc[S_G11], g22 = sc[S_G22], g12 = sc[S_G12];
+                                             const T* w1, const T* ma0, const T* ma1, double* sc, double lam0,
+                                             double lam1, int gram_w, Red rd) {
+  double gg[3];
+  gram_from(sc, rd.pb, rd.pbn, rd.pbs, blockIdx.x == 0, gg);
+  const double g11 = gg[0], g22 = gg[1], g12 = gg[2];
   const double al0 = sc[S_ALPHA], al1 = sc[S_ALPHA + 1];
   double v[2] = {0.0, 0.0};
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
@@ -168,35 +123,18 @@ __global__ void __launch_bounds__(RB) k_grad(long long n, T* l0, T* l1, const T*
     v[0] += (double)r0 * (double)r0;
     v[1] += (double)r1 * (double)r1;
   }
-  block_partials<2>(v, pb);
+  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_L0);
 }
 
-__global__ void __launch_bounds__(RB) k_fin_beta(double* sc, const double* pb, int restart_now, int coupled) {
-  const double L0 = sum_partials(pb, 0), L1 = sum_partials(pb, 1);
-  if (threadIdx.x == 0) {
-    const double P0 = sc[S_LPREV], P1 = sc[S_LPREV + 1];
-    double b0, b1;
-    if (coupled) {
-      const double Lp = P0 + P1;
-      b0 = b1 = (restart_now || Lp == 0.0) ? 0.0 : (L0 + L1) / Lp;
-    } else {
-      b0 = (restart_now || P0 == 0.0) ? 0.0 : L0 / P0;
-      b1 = (restart_now || P1 == 0.0) ? 0.0 : L1 / P1;
-    }
-    sc[S_L] = L0;
-    sc[S_L + 1] = L1;
-    sc[S_BETA] = b0;
-    sc[S_BETA + 1] = b1;
-    if (!isfinite(L0) || !isfinite(L1)) sc[S_NONFIN] = 1.0;
-  }
-}
-
-// p = l + beta p; partials (p, l)_i and ||p_i||^2.
+// beta from ||l||^2; p = l + beta p; partials (p, l)_i and ||p_i||^2.
 template <typename T>
-__global__ void __launch_bounds__(RB) k_dir(long long n, const T* l0, const T* l1, T* p0, T* p1, const double* sc,
-                                            double* pb) {
-  const double b0 = sc[S_BETA], b1 = sc[S_BETA + 1];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+__global__ void __launch_bounds__(RB) k_dir(long long n, const T* l0, const T* l1, T* p0, T* p1, double* sc,
+                                            int restart_now, int coupled, Red rd) {
+  double bt[2], L[2];
+  beta_from(sc, rd.pb, rd.pbn, rd.pbs, restart_now, coupled, bt, L);
+  if (blockIdx.x == 0 && threadIdx.x == 0) record_beta(sc, bt, L);
+  const double b0 = bt[0], b1 = bt[1];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // (p0,l0), ||p0||^2, (p1,l1), ||p1||^2
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
     const double la = l0[j], lb = l1[j];
     const T pa = (T)(la + b0 * (double)p0[j]);
@@ -204,57 +142,35 @@ __global__ void __launch_bounds__(RB) k_dir(long long n, const T* l0, const T* l
     p0[j] = pa;
     p1[j] = pbv;
     v[0] += (double)pa * la;
-    v[1] += (double)pbv * lb;
-    v[2] += (double)pa * (double)pa;
+    v[1] += (double)pa * (double)pa;
+    v[2] += (double)pbv * lb;
     v[3] += (double)pbv * (double)pbv;
   }
-  block_partials<4>(v, pb);
+  block_partials<4>(v, rd.pb, rd.pbn, rd.pbs, PB_PL0);
 }
 
+// partials of ||q_i||^2.
 template <typename T>
-__global__ void __launch_bounds__(RB) k_sumsq2(long long n, const T* a0, const T* a1, double* pb) {
+__global__ void __launch_bounds__(RB) k_sumsq2(long long n, const T* a0, const T* a1, Red rd) {
   double v[2] = {0.0, 0.0};
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
     const double x = a0[j], y = a1[j];
     v[0] += x * x;
     v[1] += y * y;
   }
-  block_partials<2>(v, pb);
+  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_Q0);
 }
 
-__global__ void __launch_bounds__(RB) k_fin_step(double* sc, const double* pb_dir, const double* pb_q, double lam0,
-                                                 double lam1, int coupled) {
-  const double pl0 = sum_partials(pb_dir, 0), pl1 = sum_partials(pb_dir, 1);
-  const double pp0 = sum_partials(pb_dir, 2), pp1 = sum_partials(pb_dir, 3);
-  const double qq0 = sum_partials(pb_q, 0), qq1 = sum_partials(pb_q, 1);
-  if (threadIdx.x == 0) {
-    const double den0 = qq0 + (sc[S_ALPHA] + lam0) * pp0;
-    const double den1 = qq1 + (sc[S_ALPHA + 1] + lam1) * pp1;
-    double s0, s1;
-    if (coupled) {
-      s0 = s1 = (pl0 + pl1) / (den0 + den1);
-    } else {
-      s0 = pl0 / den0;
-      s1 = pl1 / den1;
-    }
-    sc[S_STEP] = s0;
-    sc[S_STEP + 1] = s1;
-    sc[S_PL] = pl0; sc[S_PL + 1] = pl1;
-    sc[S_PP] = pp0; sc[S_PP + 1] = pp1;
-    sc[S_QQ] = qq0; sc[S_QQ + 1] = qq1;
-    sc[S_LPREV] = sc[S_L];
-    sc[S_LPREV + 1] = sc[S_L + 1];
-    if (!isfinite(s0) || !isfinite(s1)) sc[S_NONFIN] = 1.0;
-  }
-}
-
-// m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w); r~ <- r~ - s q; Gramian partials
-// of the new m (on m or on w m).
+// s from the partials (RRCG:6); m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w);
+// r~ <- r~ - s q; Gramian partials of the new m (on m or on w m).
 template <typename T>
 __global__ void __launch_bounds__(RB) k_update(long long n, long long nd, T* m0, T* m1, const T* p0, const T* p1,
                                                const T* w0, const T* w1, T* r0, T* r1, const T* q0, const T* q1,
-                                               const double* sc, int gram_w, double* pb) {
-  const double s0 = sc[S_STEP], s1 = sc[S_STEP + 1];
+                                               double* sc, double lam0, double lam1, int coupled, int gram_w,
+                                               Red rd) {
+  double st[2];
+  step_from(sc, rd.pb, rd.pbn, rd.pbs, lam0, lam1, coupled, blockIdx.x == 0, st);
+  const double s0 = st[0], s1 = st[1];
   double v[3] = {0.0, 0.0, 0.0};
   const long long top = n > nd ? n : nd;
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < top; j += (long long)RGRID * RB) {
@@ -274,13 +190,13 @@ __global__ void __launch_bounds__(RB) k_update(long long n, long long nd, T* m0,
       r1[j] = (T)((double)r1[j] - s1 * (double)q1[j]);
     }
   }
-  block_partials<3>(v, pb);
+  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11);
 }
 
 // m <- clip(m, lo, hi); Gramian partials of the projected m (original space).
 template <typename T>
 __global__ void __launch_bounds__(RB) k_clip(long long n, T* m0, T* m1, double lo0, double hi0, double lo1,
-                                             double hi1, double* pb) {
+                                             double hi1, Red rd) {
   double v[3] = {0.0, 0.0, 0.0};
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
     const double a = fmin(fmax((double)m0[j], lo0), hi0);
@@ -292,13 +208,13 @@ __global__ void __launch_bounds__(RB) k_clip(long long n, T* m0, T* m1, double l
     v[1] += (double)bt * (double)bt;
     v[2] += (double)at * (double)bt;
   }
-  block_partials<3>(v, pb);
+  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11);
 }
 
-// r~ = W_d (A m - d) (A m already in r); partials ||r~_i||^2.
+// r~ = W_d (A m - d) (A m already in r); partials of ||r~_i||^2.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_resid(long long nd, T* r0, T* r1, const T* d0, const T* d1, const T* wd0,
-                                              const T* wd1, double* pb) {
+                                              const T* wd1, Red rd) {
   double v[2] = {0.0, 0.0};
   for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < nd; j += (long long)RGRID * RB) {
     const T a = (T)((double)wd0[j] * ((double)r0[j] - (double)d0[j]));
@@ -308,14 +224,17 @@ __global__ void __launch_bounds__(RB) k_resid(long long nd, T* r0, T* r1, const 
     v[0] += (double)a * (double)a;
     v[1] += (double)b * (double)b;
   }
-  block_partials<2>(v, pb);
+  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_F0);
 }
 
-// Phi, S_G, and (advance = 1) the chi^2 test, freeze flags and alpha schedule.
-__global__ void __launch_bounds__(RB) k_fin_outer(double* sc, const double* pb_gram, const double* pb_res,
-                                                  double q0, double q1, double amin0, double amin1, int advance) {
-  const double g11 = sum_partials(pb_gram, 0), g22 = sum_partials(pb_gram, 1), g12 = sum_partials(pb_gram, 2);
-  const double f0 = sum_partials(pb_res, 0), f1 = sum_partials(pb_res, 1);
+// Phi, S_G, and (advance = 1) the chi^2 test, freeze flags and alpha schedule (Sec. 2.6, 2.8);
+// one block.
+__global__ void __launch_bounds__(RB) k_fin_outer(double* sc, Red rd, double q0, double q1, double amin0,
+                                                  double amin1, int advance) {
+  const int sl[5] = {PB_G11, PB_G22, PB_G12, PB_F0, PB_F1};
+  double t[5];
+  slot_totals<5>(rd.pb, rd.pbn, rd.pbs, sl, t);
+  const double g11 = t[0], g22 = t[1], g12 = t[2], f0 = t[3], f1 = t[4];
   if (threadIdx.x == 0) {
     sc[S_PHI] = f0;
     sc[S_PHI + 1] = f1;
@@ -335,20 +254,21 @@ __global__ void __launch_bounds__(RB) k_fin_outer(double* sc, const double* pb_g
   }
 }
 
+static Red red_of(const Rrcg* h) { return Red{h->pb, h->pbn, h->pbs}; }
+
 // ------------------------------------------------------------------------------------
 template <typename T>
 static int outer_update(Rrcg* h, hipStream_t s, int advance) {
   T** m = reinterpret_cast<T**>(h->m);
   T** rt = reinterpret_cast<T**>(h->rt);
-  double* pbg = h->pb;
-  double* pbr = h->pb + NSLOT * RGRID;
+  const Red rd = red_of(h);
   if (advance) {
     hipLaunchKernelGGL(k_clip<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1], h->lo[0], h->hi[0], h->lo[1],
-                       h->hi[1], pbg);
+                       h->hi[1], rd);
   } else {
     // Gramian partials only (no projection): clip to +-inf
     hipLaunchKernelGGL(k_clip<T>, dim3(RGRID), dim3(RB), 0, s, h->n, m[0], m[1], -HUGE_VAL, HUGE_VAL, -HUGE_VAL,
-                       HUGE_VAL, pbg);
+                       HUGE_VAL, rd);
   }
   BTTB_LAUNCHED("k_clip");
   for (int i = 0; i < 2; ++i) {
@@ -357,10 +277,10 @@ static int outer_update(Rrcg* h, hipStream_t s, int advance) {
   }
   hipLaunchKernelGGL(k_resid<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, rt[0], rt[1],
                      static_cast<const T*>(h->dobs[0]), static_cast<const T*>(h->dobs[1]),
-                     static_cast<const T*>(h->wd[0]), static_cast<const T*>(h->wd[1]), pbr);
+                     static_cast<const T*>(h->wd[0]), static_cast<const T*>(h->wd[1]), rd);
   BTTB_LAUNCHED("k_resid");
-  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(RB), 0, s, h->sc, pbg, pbr, h->q[0], h->q[1], h->amin[0],
-                     h->amin[1], advance);
+  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(RB), 0, s, h->sc, rd, h->q[0], h->q[1], h->amin[0], h->amin[1],
+                     advance);
   BTTB_LAUNCHED("k_fin_outer");
   return BTTB_OK;
 }
@@ -375,14 +295,15 @@ static int phase_weights(Rrcg* h, hipStream_t s) {
                      static_cast<const T*>(h->mapr[0]), static_cast<const T*>(h->mapr[1]),
                      static_cast<const T*>(h->wdepth[0]), static_cast<const T*>(h->wdepth[1]),
                      static_cast<const T*>(h->whard[0]), static_cast<const T*>(h->whard[1]), h->eps2, h->p_norm,
-                     h->gram_w, w[0], w[1], wi[0], wi[1], h->pb);
+                     h->gram_w, w[0], w[1], wi[0], wi[1], h->sc, red_of(h));
   BTTB_LAUNCHED("k_weights");
-  hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, h->pb);
-  BTTB_LAUNCHED("k_fin_gram");
   return BTTB_OK;
 }
 
 // One CG step (RRCG:2-7) at the outer step's W and alpha; restart_now sets beta = 0.
+// Power-of-two plans carry the gradient (RRCG:4), beta (RRCG:5), the direction update and the
+// step length (RRCG:6) inside the row transforms of the products; otherwise separate
+// elementwise kernels do the same arithmetic.
 template <typename T>
 static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
   T** m = reinterpret_cast<T**>(h->m);
@@ -394,34 +315,63 @@ static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
   T** qv = reinterpret_cast<T**>(h->qv);
   const T* ma0 = static_cast<const T*>(h->mapr[0]);
   const T* ma1 = static_cast<const T*>(h->mapr[1]);
-  double* pb0 = h->pb;
-  double* pb1 = h->pb + NSLOT * RGRID;
-  double* pb2 = h->pb + 2 * NSLOT * RGRID;
-  double* pb3 = h->pb + 3 * NSLOT * RGRID;
-  for (int i = 0; i < 2; ++i) {
-    int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i], static_cast<const T*>(h->wd[i]), s);
-    if (rc) return rc;
+  const Red rd = red_of(h);
+  if (h->fused) {
+    Fuse<T> fz[2];
+    for (int i = 0; i < 2; ++i) {
+      Fuse<T>& f = fz[i];
+      f.self = i;
+      f.lead = i == 0;
+      f.restart = restart_now;
+      f.coupled = h->coupled;
+      f.gram_w = h->gram_w;
+      f.lam[0] = h->lam[0];
+      f.lam[1] = h->lam[1];
+      f.l = l[i];
+      f.p = p[i];
+      f.m[0] = m[0];
+      f.m[1] = m[1];
+      f.w[0] = w[0];
+      f.w[1] = w[1];
+      f.ma = static_cast<const T*>(h->mapr[i]);
+      f.sc = h->sc;
+      f.pb = h->pb;
+      f.pbn = h->pbn;
+      f.pbs = h->pbs;
+    }
+    for (int i = 0; i < 2; ++i) {
+      int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i],
+                             static_cast<const T*>(h->wd[i]), s, &fz[i]);
+      if (rc) return rc;
+    }
+    for (int i = 0; i < 2; ++i) {
+      int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i],
+                             static_cast<const T*>(h->wd[i]), s, &fz[i]);
+      if (rc) return rc;
+    }
+  } else {
+    for (int i = 0; i < 2; ++i) {
+      int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i],
+                             static_cast<const T*>(h->wd[i]), s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_grad<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], m[0], m[1], w[0], w[1], ma0, ma1,
+                       h->sc, h->lam[0], h->lam[1], h->gram_w, rd);
+    BTTB_LAUNCHED("k_grad");
+    hipLaunchKernelGGL(k_dir<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], p[0], p[1], h->sc, restart_now,
+                       h->coupled, rd);
+    BTTB_LAUNCHED("k_dir");
+    for (int i = 0; i < 2; ++i) {
+      int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i],
+                             static_cast<const T*>(h->wd[i]), s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_sumsq2<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, qv[0], qv[1], rd);
+    BTTB_LAUNCHED("k_sumsq2");
   }
-  hipLaunchKernelGGL(k_grad<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], m[0], m[1], w[0], w[1], ma0, ma1,
-                     h->sc, h->lam[0], h->lam[1], h->gram_w, pb1);
-  BTTB_LAUNCHED("k_grad");
-  hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(RB), 0, s, h->sc, pb1, restart_now, h->coupled);
-  BTTB_LAUNCHED("k_fin_beta");
-  hipLaunchKernelGGL(k_dir<T>, dim3(RGRID), dim3(RB), 0, s, h->n, l[0], l[1], p[0], p[1], h->sc, pb2);
-  BTTB_LAUNCHED("k_dir");
-  for (int i = 0; i < 2; ++i) {
-    int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i], static_cast<const T*>(h->wd[i]), s);
-    if (rc) return rc;
-  }
-  hipLaunchKernelGGL(k_sumsq2<T>, dim3(RGRID), dim3(RB), 0, s, h->nd, qv[0], qv[1], pb3);
-  BTTB_LAUNCHED("k_sumsq2");
-  hipLaunchKernelGGL(k_fin_step, dim3(1), dim3(RB), 0, s, h->sc, pb2, pb3, h->lam[0], h->lam[1], h->coupled);
-  BTTB_LAUNCHED("k_fin_step");
   hipLaunchKernelGGL(k_update<T>, dim3(RGRID), dim3(RB), 0, s, h->n, h->nd, m[0], m[1], p[0], p[1], w[0], w[1],
-                     rt[0], rt[1], qv[0], qv[1], h->sc, h->gram_w, pb0);
+                     rt[0], rt[1], qv[0], qv[1], h->sc, h->lam[0], h->lam[1], h->coupled, h->gram_w, rd);
   BTTB_LAUNCHED("k_update");
-  hipLaunchKernelGGL(k_fin_gram, dim3(1), dim3(RB), 0, s, h->sc, pb0);
-  BTTB_LAUNCHED("k_fin_gram");
   return BTTB_OK;
 }
 
@@ -480,6 +430,7 @@ static void free_rrcg(Rrcg* h) {
   }
   dfree(h->sc);
   dfree(h->pb);
+  dfree(h->pbn);
   delete h;
 }
 
@@ -536,8 +487,14 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
     ok = hipMalloc(&h->l[i], nb) == hipSuccess && hipMalloc(&h->w[i], nb) == hipSuccess &&
          hipMalloc(&h->winv[i], nb) == hipSuccess && hipMalloc(&h->qv[i], db) == hipSuccess;
   }
+  // partials per slot: the elementwise grid, or the most blocks a fused row transform can
+  // have (one row pair per block)
+  const long long rows_blocks = (long long)P0->nz * ((P0->nx + 1) / 2);
+  h->pbs = (int)std::max<long long>(RGRID, std::max<long long>(rows_blocks, (P0->sx + 1) / 2));
+  h->fused = P0->fast && P1->fast;
   ok = ok && hipMalloc((void**)&h->sc, S_COUNT * sizeof(double)) == hipSuccess &&
-       hipMalloc((void**)&h->pb, 4 * NSLOT * RGRID * sizeof(double)) == hipSuccess;
+       hipMalloc((void**)&h->pb, (size_t)PB_NSLOT * h->pbs * sizeof(double)) == hipSuccess &&
+       hipMalloc((void**)&h->pbn, PB_NSLOT * sizeof(int)) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     free_rrcg(h);
@@ -551,6 +508,8 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   sc[S_THR] = (double)h->nd + std::sqrt(2.0 * (double)h->nd);
   if (rc == BTTB_OK && hipMemcpyAsync(h->sc, sc, sizeof(sc), hipMemcpyHostToDevice, s) != hipSuccess)
     rc = fail(BTTB_EHIP, "rrcg_create: scalar upload");
+  if (rc == BTTB_OK && hipMemsetAsync(h->pbn, 0, PB_NSLOT * sizeof(int), s) != hipSuccess)
+    rc = fail(BTTB_EHIP, "rrcg_create: partial counts reset");
   if (rc == BTTB_OK)
     rc = h->precision == BTTB_F64 ? outer_update<double>(h, s, 0) : outer_update<float>(h, s, 0);
   if (rc == BTTB_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(BTTB_EHIP, "rrcg_create: synchronize");

@@ -1,0 +1,216 @@
+// Pieces of the joint CG step (Sec. 2.4, eqs. RRCG:2-7) shared by the solver's own
+// kernels and the product kernels that carry them as prologues and epilogues:
+//   * the device-resident scalar layout;
+//   * block partial sums of FP64 dot products, one value per block and slot;
+//   * the finishing sums (beta of RRCG:5, the step s of RRCG:6, the Gramian scalars of
+//     RRCG:2-3), done by every block of the kernel that consumes them: the launch
+//     boundary makes the producer's partials visible without fences or atomics, and
+//     every block sums the same partials in the same order, so all blocks hold the
+//     same scalars;
+//   * Fuse<T>, the arguments of the fused forms of the row transforms.
+// The results are bitwise repeatable for a given launch configuration.
+#pragma once
+#include "common.h"
+
+namespace bttb {
+
+// Scalar array layout (doubles).
+enum {
+  S_ALPHA = 0, S_LPREV = 2, S_PHI = 4, S_THR = 6, S_BETA = 7, S_STEP = 9, S_GRAM = 11, S_FROZEN = 12,
+  S_K = 14, S_CONV = 15, S_NONFIN = 16, S_G11 = 17, S_G22 = 18, S_G12 = 19, S_L = 20, S_PL = 22,
+  S_PP = 24, S_QQ = 26, S_COUNT = 32
+};
+
+// Partial-sum slots: ||l_i||^2; (p_i, l_i) and ||p_i||^2; ||q_i||^2 (q = A~ p); the Gramian
+// sums (m1,m1), (m2,m2), (m1,m2); the misfits ||r~_i||^2.
+enum {
+  PB_L0 = 0, PB_L1, PB_PL0, PB_PP0, PB_PL1, PB_PP1, PB_Q0, PB_Q1, PB_G11, PB_G22, PB_G12, PB_F0, PB_F1,
+  PB_NSLOT = 16
+};
+// Fused forms of the row transforms.
+enum { FUSE_NONE = 0, FUSE_DIR = 1, FUSE_GRAD = 2, FUSE_QQ = 3 };
+
+template <typename T>
+struct Fuse {
+  int self;     // data set of this launch (0, 1)
+  int lead;     // 1: block 0 of this launch records the finished scalars (first data set)
+  int restart;  // beta = 0 in this step
+  int coupled;  // joint beta and s (else per data set)
+  int gram_w;   // Gramian on w m instead of m
+  double lam[2];
+  const T* l;     // DIR: gradient of this data set
+  T* p;           // DIR: direction of this data set, updated in place
+  const T* m[2];  // GRAD: models of both data sets (original space)
+  const T* w[2];  // GRAD: weights of both data sets
+  const T* ma;    // GRAD: m_apr of this data set, or NULL for zero
+  double* sc;     // scalars
+  double* pb;     // [PB_NSLOT][pbs] partials
+  int* pbn;       // [PB_NSLOT] number of partials in each slot
+  int pbs;        // partials per slot (>= blocks of any reducing launch)
+};
+
+__device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
+
+// Sum of v over the block (every thread calls; blockDim a multiple of 64 or a power of two
+// below 64, at most 1024) stored at pb[(slot0 + k) * pbs + block]; block 0 records the
+// number of blocks.
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* pbn, int pbs, int slot0) {
+  __shared__ double sh[K][16];
+  const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;  // xor partners stay among active lanes
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+    for (int off = wsz >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[k] = x;
+  }
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    const int b = flat_block();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += sh[k][w];
+      pb[(slot0 + k) * pbs + b] = s;
+      if (b == 0) pbn[slot0 + k] = gridDim.x * gridDim.y;
+    }
+  }
+}
+
+// Sums of K values over the block, left in v of every thread (blockDim a multiple of 64
+// or a power of two below 64, at most 1024).  All lanes of a wave hold the same sum after
+// the xor butterfly (each level adds the same two operands), and the waves' sums are
+// added in a fixed order.
+template <int K>
+__device__ __forceinline__ void block_allreduce(double (&v)[K]) {
+  __shared__ double sh[K][16];
+  const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+    for (int off = wsz >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[k] = x;
+  }
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+  }
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[k][w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Fixed-order totals of K slots' partials, in every thread of the block.
+template <int K>
+__device__ __forceinline__ void slot_totals(const double* pb, const int* pbn, int pbs, const int (&slot)[K],
+                                            double (&out)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int n = pbn[slot[k]];
+    const double* src = pb + (long long)slot[k] * pbs;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += src[i];
+    out[k] = s;
+  }
+  block_allreduce<K>(out);
+}
+
+// RRCG:5 from the partials of ||l_i||^2: L_i and beta (joint when coupled; 0 at a restart).
+__device__ __forceinline__ void beta_from(const double* sc, const double* pb, const int* pbn, int pbs,
+                                          int restart, int coupled, double (&beta)[2], double (&L)[2]) {
+  const int sl[2] = {PB_L0, PB_L1};
+  slot_totals<2>(pb, pbn, pbs, sl, L);
+  const double P0 = sc[S_LPREV], P1 = sc[S_LPREV + 1];
+  if (coupled) {
+    const double Lp = P0 + P1;
+    beta[0] = beta[1] = (restart || Lp == 0.0) ? 0.0 : (L[0] + L[1]) / Lp;
+  } else {
+    beta[0] = (restart || P0 == 0.0) ? 0.0 : L[0] / P0;
+    beta[1] = (restart || P1 == 0.0) ? 0.0 : L[1] / P1;
+  }
+}
+
+__device__ __forceinline__ void record_beta(double* sc, const double (&beta)[2], const double (&L)[2]) {
+  sc[S_L] = L[0];
+  sc[S_L + 1] = L[1];
+  sc[S_BETA] = beta[0];
+  sc[S_BETA + 1] = beta[1];
+  if (!isfinite(L[0]) || !isfinite(L[1])) sc[S_NONFIN] = 1.0;
+}
+
+// RRCG:6: s = sum (p,l) / sum (||A~ p||^2 + (alpha + lambda) ||p||^2), joint when coupled.
+// The block-0 thread 0 of the consumer records it (and L_prev <- L for the next beta) when
+// `record` is set.
+__device__ __forceinline__ void step_from(double* sc, const double* pb, const int* pbn, int pbs, double lam0,
+                                          double lam1, int coupled, bool record, double (&s)[2]) {
+  const int sl[6] = {PB_PL0, PB_PL1, PB_PP0, PB_PP1, PB_Q0, PB_Q1};
+  double t[6];
+  slot_totals<6>(pb, pbn, pbs, sl, t);
+  const double den0 = t[4] + (sc[S_ALPHA] + lam0) * t[2];
+  const double den1 = t[5] + (sc[S_ALPHA + 1] + lam1) * t[3];
+  if (coupled) {
+    s[0] = s[1] = (t[0] + t[1]) / (den0 + den1);
+  } else {
+    s[0] = t[0] / den0;
+    s[1] = t[1] / den1;
+  }
+  if (record && threadIdx.x == 0) {
+    sc[S_STEP] = s[0];
+    sc[S_STEP + 1] = s[1];
+    sc[S_PL] = t[0]; sc[S_PL + 1] = t[1];
+    sc[S_PP] = t[2]; sc[S_PP + 1] = t[3];
+    sc[S_QQ] = t[4]; sc[S_QQ + 1] = t[5];
+    sc[S_LPREV] = sc[S_L];
+    sc[S_LPREV + 1] = sc[S_L + 1];
+    if (!isfinite(s[0]) || !isfinite(s[1])) sc[S_NONFIN] = 1.0;
+  }
+}
+
+// RRCG:2-3 scalars (m1,m1), (m2,m2), (m1,m2) from their partials.
+__device__ __forceinline__ void gram_from(double* sc, const double* pb, const int* pbn, int pbs, bool record,
+                                          double (&g)[3]) {
+  const int sl[3] = {PB_G11, PB_G22, PB_G12};
+  slot_totals<3>(pb, pbn, pbs, sl, g);
+  if (record && threadIdx.x == 0) {
+    sc[S_G11] = g[0];
+    sc[S_G22] = g[1];
+    sc[S_G12] = g[2];
+    if (!isfinite(g[0]) || !isfinite(g[1]) || !isfinite(g[2])) sc[S_NONFIN] = 1.0;
+  }
+}
+
+// RRCG:4 for element j of data set `self`, given z~ = (A~^T r~)_j:
+//   l = z~ + alpha (w m - w m_apr) + lambda l_G,
+//   l_G = (m2,m2) m1 - (m1,m2) m2 for data set 0, (m1,m1) m2 - (m1,m2) m1 for data set 1
+// (on w m instead of m when gram_w).
+template <typename T>
+__device__ __forceinline__ T grad_element(const Fuse<T>& fz, long long j, T zt, double al, double lam, double g11,
+                                          double g22, double g12) {
+  const double a = fz.m[0][j], b = fz.m[1][j];
+  const double Ws = fz.w[fz.self][j];
+  double u0 = a, u1 = b;
+  if (fz.gram_w) {
+    const double Wo = fz.w[1 - fz.self][j];
+    u0 = fz.self == 0 ? Ws * a : Wo * a;
+    u1 = fz.self == 0 ? Wo * b : Ws * b;
+  }
+  const double lg = fz.self == 0 ? g22 * u0 - g12 * u1 : g11 * u1 - g12 * u0;
+  const double ms = fz.self == 0 ? a : b;
+  const double mt = Ws * ms, mta = fz.ma ? Ws * (double)fz.ma[j] : 0.0;
+  return (T)((double)zt + al * (mt - mta) + lam * lg);
+}
+
+}  // namespace bttb

@@ -88,9 +88,11 @@ VARIANTS = [
 ]
 
 
+# SMALL (transform 32): the CG pieces ride on the products' row transforms;
+# SUB (transform 24, radix 3): separate elementwise kernels
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB], ids=["pow2-fused", "radix3"])
 @pytest.mark.parametrize("var", range(len(VARIANTS)))
-def test_single_outer_step_parity_fp64(pk, var):
-    g = synth.SMALL
+def test_single_outer_step_parity_fp64(pk, var, g):
     ops, T, data, _ = problem(g, dense=True)
     v = dict(VARIANTS[var])
     n_inner = v.pop("n_inner")
