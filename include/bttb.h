@@ -57,6 +57,8 @@ extern "C" {
 
 typedef struct bttb_plan_s* bttb_plan;
 typedef struct rrcg_s* rrcg_handle;
+typedef struct bttb_group_s* bttb_group;
+typedef struct rrcg_group_s* rrcg_group;
 
 typedef enum {
   BTTB_OK = 0,
@@ -69,6 +71,10 @@ typedef enum {
 } bttb_status;
 
 typedef enum { BTTB_F64 = 0, BTTB_F32 = 1 } bttb_precision;
+/* Flag or-ed into bttb_setup's precision: pad to powers of two (>= 32) instead of the
+ * smallest 5-smooth multiples of 8, so that the plan takes the register-FFT kernels and
+ * can join a group. */
+#define BTTB_PAD_POW2 0x10
 typedef enum { BTTB_GRAVITY = 0, BTTB_MAGNETIC = 1 } bttb_kind;
 typedef enum { BTTB_OP_FORWARD = 0, BTTB_OP_ADJOINT = 1 } bttb_op;
 
@@ -157,6 +163,46 @@ BTTB_API int bttb_destroy(bttb_plan plan);
 #define BTTB_NKERNELS 6
 BTTB_API int bttb_timing_enable(bttb_plan plan, int max_launches, int repeat);
 BTTB_API int bttb_timing_read(bttb_plan plan, double* total_ms, int* count);
+
+/* ---------------------------------------------------------------------------------- */
+/* Groups: the products of many plans in one launch per stage                           */
+/* ---------------------------------------------------------------------------------- */
+
+/* A group runs the products (Sec. 2.7.1, eq. matrixvector) of up to 64 plans -- e.g. the
+ * gravity and magnetic operators of many inversions of uneven sizes -- as one kernel
+ * launch per stage (row transform, column pass, inverse row transform), each member
+ * with its own plan's eigenvalues and scratch.  Members must be power-of-two plans
+ * (bttb_setup with BTTB_PAD_POW2, transforms 32..2048) of one precision.  The group
+ * refers to the plans, which must outlive it and must not be used on another stream
+ * while a group product runs.  Creation allocates a small device table and
+ * synchronises `stream`. */
+BTTB_API int bttb_group_create(const bttb_plan* plans, int count, void* stream, bttb_group* out);
+
+/* For every member i: op = BTTB_OP_FORWARD: out_i = wd_i . (A_i (winv_i . in_i));
+ * op = BTTB_OP_ADJOINT: out_i = winv_i . (A_i^T (wd_i . in_i)); shapes as bttb_apply
+ * with batch 1.  in, out: DEVICE arrays of `count` device pointers (caller-owned, read
+ * by the kernels when they run, so a captured graph may be replayed with new contents
+ * of the same buffers).  winv, wd: device pointer arrays or NULL (identity for all);
+ * entries may be NULL. */
+BTTB_API int bttb_group_apply(bttb_group g, int op, const void* const* in, void* const* out,
+                              const void* const* winv, const void* const* wd, void* stream);
+
+/* Launch shape: threads per block of the model-side row transforms, the data-side row
+ * transforms and the column passes (powers of two, at least N/8 of every member, at
+ * most 512; columns at most 256 in FP64), and the layer chunks of the forward column
+ * pass (bounded per member by its plan).  Values <= 0 keep the current choice.  Only
+ * the work split changes.  Synchronises `stream`. */
+BTTB_API int bttb_group_set_launch(bttb_group g, int model_row_threads, int data_row_threads, int col_threads,
+                                   int layer_chunks, void* stream);
+
+typedef struct {
+  int count, precision;
+  int model_row_threads, data_row_threads, col_threads, layer_chunks;
+  int blocks[6]; /* blocks of each launch: forward row, column, inverse row; transpose likewise */
+} bttb_group_desc;
+
+BTTB_API int bttb_group_info(bttb_group g, bttb_group_desc* out);
+BTTB_API int bttb_group_destroy(bttb_group g);
 
 /* ---------------------------------------------------------------------------------- */
 /* Joint RRCG (Sec. 2.4 eqs. RRCG:1-8, Sec. 2.5-2.6, Sec. 2.8)                          */

@@ -16,9 +16,9 @@ from ._lib import BTTBError, MAX_TRANSFORM
 if not _os.path.exists(_lib.LIB_PATH):  # no fallback path: fail loudly without the HIP library
     raise ImportError(f"{_lib.LIB_PATH} is not built; run `python paper_2112_15562_amd/build.py`")
 
-from .operator import GRAVITY, MAGNETIC, Operator, prism_kernels  # noqa: E402
+from .operator import GRAVITY, MAGNETIC, Group, Operator, pointer_array, prism_kernels  # noqa: E402
 from .autograd import BTTBFunction, BTTBTransposeFunction, ForwardModel  # noqa: E402
 from .rrcg import JointRRCG  # noqa: E402
 
-__all__ = ["Operator", "prism_kernels", "GRAVITY", "MAGNETIC", "BTTBFunction", "BTTBTransposeFunction",
+__all__ = ["Operator", "Group", "pointer_array", "prism_kernels", "GRAVITY", "MAGNETIC", "BTTBFunction", "BTTBTransposeFunction",
            "ForwardModel", "JointRRCG", "BTTBError", "MAX_TRANSFORM"]

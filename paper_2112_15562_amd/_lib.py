@@ -15,6 +15,7 @@ BTTB_OK, BTTB_EINVAL, BTTB_ENOMEM, BTTB_EHIP, BTTB_ESIZE, BTTB_ESTATE, BTTB_ENAN
 BTTB_F64, BTTB_F32 = 0, 1
 BTTB_GRAVITY, BTTB_MAGNETIC = 0, 1
 BTTB_OP_FORWARD, BTTB_OP_ADJOINT = 0, 1
+BTTB_PAD_POW2 = 0x10
 MAX_TRANSFORM = 2048
 
 EXPORTED = [
@@ -22,6 +23,7 @@ EXPORTED = [
     "bttb_plan_info", "bttb_plan_eigenvalues", "bttb_destroy", "rrcg_create", "rrcg_step",
     "rrcg_read_scalars", "rrcg_write_scalars", "rrcg_refresh", "rrcg_destroy", "bttb_strerror",
     "bttb_last_error", "bttb_timing_enable", "bttb_timing_read",
+    "bttb_group_create", "bttb_group_apply", "bttb_group_set_launch", "bttb_group_info", "bttb_group_destroy",
 ]
 NKERNELS = 6
 KERNEL_NAMES = ["fwd_row_r2c", "fwd_col_eig_sum", "fwd_row_c2r", "adj_row_r2c", "adj_col_conj_eig", "adj_row_c2r"]
@@ -45,6 +47,12 @@ class PlanDesc(C.Structure):
                 ("Px", C.c_int), ("Py", C.c_int), ("precision", C.c_int), ("max_batch", C.c_int),
                 ("eig_bytes", C.c_size_t), ("scratch_bytes", C.c_size_t), ("col_fft_per_block", C.c_int),
                 ("row_fft_per_block", C.c_int), ("layer_chunks", C.c_int)]
+
+
+class GroupDesc(C.Structure):
+    _fields_ = [("count", C.c_int), ("precision", C.c_int), ("model_row_threads", C.c_int),
+                ("data_row_threads", C.c_int), ("col_threads", C.c_int), ("layer_chunks", C.c_int),
+                ("blocks", C.c_int * 6)]
 
 
 class RrcgDesc(C.Structure):
@@ -94,6 +102,11 @@ def lib() -> C.CDLL:
         "rrcg_destroy": [vp],
         "bttb_timing_enable": [vp, i, i],
         "bttb_timing_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)],
+        "bttb_group_create": [C.POINTER(vp), i, vp, C.POINTER(vp)],
+        "bttb_group_apply": [vp, i, vp, vp, vp, vp, vp],
+        "bttb_group_set_launch": [vp, i, i, i, i, vp],
+        "bttb_group_info": [vp, C.POINTER(GroupDesc)],
+        "bttb_group_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

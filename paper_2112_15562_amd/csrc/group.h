@@ -1,0 +1,58 @@
+// Group products (group.hip): host and kernel-side descriptions of a group of plans.
+#pragma once
+#include "common.h"
+#include "rrcg_fuse.h"
+
+namespace bttb {
+
+constexpr int GMAX = 64;  // members per group
+
+// Stages of the products: forward row / column / inverse row, transpose likewise.
+enum { GS_F1 = 0, GS_F2, GS_F3, GS_T1, GS_T2, GS_T3, GS_COUNT };
+
+// One member as the kernels see it (device table, written at creation and on a launch
+// shape change).
+template <typename T>
+struct GMember {
+  int Px, Py, K2, sx, sy, nx, ny, nz, ldx, ldk, nchunk;
+  const cx<T>* eig;
+  const cx<T>* twx;
+  const cx<T>* twy;
+  cx<T>* U;
+  cx<T>* V;
+  long long V_fcs;  // elements between layer-chunk partials of the data spectrum
+};
+
+// Arguments of one group launch (by value).
+template <typename T>
+struct GLaunch {
+  const GMember<T>* mem;
+  const Fuse<T>* fz;     // per member: the CG step's fused forms, or NULL
+  const T* const* in;    // dev arrays of one pointer per member
+  T* const* out;
+  const T* const* winv;  // nullable arrays; entries nullable
+  const T* const* wd;
+  int bt;                // threads per block
+  int count;
+  int start[GMAX + 1];   // first block of each member; start[count] = blocks of the launch
+};
+
+struct Group {
+  int count, precision;
+  Plan* P[GMAX];
+  void* mem;  // dev GMember<T>[count]
+  int bt_rm, bt_rd, bt_c;  // threads per block: model rows (F1, T3), data rows (F3, T1), columns
+  int nchunk;              // layer chunks requested for the forward column pass
+  int nch[GMAX];           // per member, bounded by its plan
+  int start[GS_COUNT][GMAX + 1];
+  size_t lds[GS_COUNT];
+};
+
+int group_create(const bttb_plan* plans, int count, void* stream, Group** out);
+void group_destroy(Group* g);
+int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s);
+template <typename T>
+int group_apply_impl(const Group* g, int op, const void* const* in, void* const* out, const void* const* winv,
+                     const void* const* wd, const Fuse<T>* fz, hipStream_t s);
+
+}  // namespace bttb

@@ -155,10 +155,12 @@ __global__ void __launch_bounds__(1024) k_row_r2c(RowR2CArgs<T> a) {
     }
   }
   __syncthreads();
+  // rows beyond nrows are not stored: a tile may be taller than the padded row count ld
   cx<T>* dst = a.out + b * a.out_bs + (long long)l * K2 * a.ld + tile * RT;
+  const int rows = min(RT, a.nrows - tile * RT);
   for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
     const int k2 = idx / RT, rr = idx - k2 * RT;
-    dst[(long long)k2 * a.ld + rr] = smem[(rr >> 1) * stride + (rr & 1) * K2 + k2];
+    if (rr < rows) dst[(long long)k2 * a.ld + rr] = smem[(rr >> 1) * stride + (rr & 1) * K2 + k2];
   }
 }
 
@@ -623,11 +625,19 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
   if (!kernels || !aligned(kernels, 8)) return fail(BTTB_EINVAL, "bttb_setup: kernels NULL or misaligned");
   if (sx < 1 || sy < 1 || nx < 1 || ny < 1 || nz < 1 || max_batch < 1)
     return fail(BTTB_EINVAL, "bttb_setup: sizes must be >= 1");
+  const bool pad_pow2 = (precision & BTTB_PAD_POW2) != 0;
+  precision &= ~BTTB_PAD_POW2;
   if (precision != BTTB_F64 && precision != BTTB_F32) return fail(BTTB_EINVAL, "bttb_setup: bad precision");
   const long long Lx = (long long)sx + nx - 1, Ly = (long long)sy + ny - 1;
   if (Lx > BTTB_MAX_TRANSFORM || Ly > BTTB_MAX_TRANSFORM)
     return fail(BTTB_ESIZE, "bttb_setup: sx+nx-1 or sy+ny-1 exceeds the maximum transform size");
-  const int Px = padded_size((int)Lx), Py = padded_size((int)Ly);
+  auto pow2_size = [](long long L) {
+    int v = 32;
+    while (v < L) v <<= 1;
+    return v;
+  };
+  const int Px = pad_pow2 ? pow2_size(Lx) : padded_size((int)Lx);
+  const int Py = pad_pow2 ? pow2_size(Ly) : padded_size((int)Ly);
   if (Px > BTTB_MAX_TRANSFORM || Py > BTTB_MAX_TRANSFORM)
     return fail(BTTB_ESIZE, "bttb_setup: padded transform size exceeds the maximum");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -12,583 +12,9 @@
 #include <algorithm>
 
 #include "common.h"
-#include "fft_reg.h"
-#include "rrcg_fuse.h"
+#include "fast_kernels.h"
 
 namespace bttb {
-
-// Orders the LDS accesses of one wave: LDS requests of a wave complete in issue order,
-// so only compiler reordering has to be prevented.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int TPF>
-struct GroupSync {
-  __device__ __forceinline__ void operator()() const {
-    if constexpr (TPF <= 64) wave_sync();
-    else __syncthreads();
-  }
-};
-
-template <int N>
-constexpr int row_buf() {  // per-group LDS elements of the row kernels (exchange and [2][K2] staging)
-  return Pow2<N>::BUF > N + 2 ? Pow2<N>::BUF : N + 2;
-}
-
-// ------------------------------------------------------------------------------------
-// Row transforms
-// ------------------------------------------------------------------------------------
-template <typename T>
-struct FRowArgs {
-  const T* in;
-  long long in_bs;
-  const T* scale;
-  cx<T>* out;
-  long long out_bs;
-  long long in_cs;  // c2r: stride between summed partials
-  int nsum;
-  int L, nrows, ncols, ld, K2, fpb, tiles;
-  const cx<T>* tw;
-};
-
-// ROWOUT = false: half spectra stored column-major out[l][k2][row] (ld = padded rows) through an
-// LDS transpose; ROWOUT = true: row-major out[l][row][k2] (ld = padded K2) straight from registers.
-// MODE = FUSE_DIR (ROWOUT = false, the forward product inside the CG step): beta is summed from
-// the partials of ||l||^2 at the start, the input is the new direction p = l + beta p (RRCG:5),
-// written back, and the block partials of (p, l) and ||p||^2 are stored for the step length.
-template <typename T, int N, bool ROWOUT, int MODE>
-__global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
-  static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT), "fused form");
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
-  const int l = blockIdx.x / a.tiles, tile = blockIdx.x - l * a.tiles;
-  const int b = blockIdx.y;
-  const int RT = 2 * a.fpb;
-  const int r0 = tile * RT + 2 * f;
-  cx<T>* buf = smem + f * BS;
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
-  F.init(a.tw, t);
-  const long long lofs = (long long)l * a.nrows * a.ncols;
-  const T* src = a.in + b * a.in_bs + lofs;
-  const T* sc = a.scale ? a.scale + lofs : nullptr;
-  const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
-  cx<T> v[8];
-  double acc[2] = {0.0, 0.0};
-  if constexpr (MODE == FUSE_DIR) {
-    double bt[2], L[2];
-    beta_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.restart, fz.coupled, bt, L);
-    if (fz.lead && flat_block() == 0 && threadIdx.x == 0) record_beta(fz.sc, bt, L);
-    const double beta = bt[fz.self];
-    const T* lv = fz.l + lofs;
-    T* pv = fz.p + lofs;
-    auto dir = [&](long long o) -> T {
-      const double lo = lv[o];
-      const T pn = (T)(lo + beta * (double)pv[o]);
-      pv[o] = pn;
-      acc[0] += (double)pn * lo;
-      acc[1] += (double)pn * (double)pn;
-      return pn * sc[o];
-    };
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      T xa = T(0), xb = T(0);
-      if (n < a.ncols) {
-        const long long oa = (long long)r0 * a.ncols + n;
-        if (ra) xa = dir(oa);
-        if (rb) xb = dir(oa + a.ncols);
-      }
-      v[i] = cx<T>{xa, xb};
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      T xa = T(0), xb = T(0);
-      if (n < a.ncols) {
-        const long long oa = (long long)r0 * a.ncols + n;
-        if (ra) xa = sc ? src[oa] * sc[oa] : src[oa];
-        if (rb) xb = sc ? src[oa + a.ncols] * sc[oa + a.ncols] : src[oa + a.ncols];
-      }
-      v[i] = cx<T>{xa, xb};
-    }
-  }
-  F.template run<false>(v, buf, t, gsync);
-  // X_a[k] = (Z[k] + conj Z[N-k]) / 2,  X_b[k] = (Z[k] - conj Z[N-k]) / (2i),  k <= N/2
-#pragma unroll
-  for (int i = 0; i < 8; ++i) buf[lds_pad(t + i * TPF)] = v[i];
-  gsync();
-  const T h = T(0.5);
-  cx<T> xa[5], xb[5];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const int k = t + i * TPF;
-    if (k <= N / 2) {
-      const cx<T> A = v[i];
-      const cx<T> C = buf[lds_pad((N - k) & (N - 1))];
-      xa[i] = cx<T>{h * (A.re + C.re), h * (A.im - C.im)};
-      xb[i] = cx<T>{h * (A.im + C.im), h * (C.re - A.re)};
-    }
-  }
-  if constexpr (ROWOUT) {
-    cx<T>* dst = a.out + b * a.out_bs + ((long long)l * a.nrows + r0) * a.ld;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-      const int k = t + i * TPF;
-      if (k <= N / 2) {
-        if (ra) dst[k] = xa[i];
-        if (rb) dst[a.ld + k] = xb[i];
-      }
-    }
-    return;
-  }
-  gsync();
-#pragma unroll
-  for (int i = 0; i < 5; ++i) {
-    const int k = t + i * TPF;
-    if (k <= N / 2) {
-      buf[k] = xa[i];
-      buf[K2 + k] = xb[i];
-    }
-  }
-  __syncthreads();
-  cx<T>* dst = a.out + b * a.out_bs + (long long)l * K2 * a.ld + tile * RT;
-  for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
-    const int k2 = idx / RT, rr = idx - k2 * RT;
-    dst[(long long)k2 * a.ld + rr] = smem[(rr >> 1) * BS + (rr & 1) * K2 + k2];
-  }
-  if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0);
-}
-
-// ROWIN = false: half spectra read column-major in[c][l][k2][row] (ld = padded rows), summed over
-// nsum partials, through an LDS transpose; ROWIN = true: row-major in[l][row][k2] (ld = padded
-// K2, nsum = 1) read straight into the strided layout.
-// MODE = FUSE_QQ (ROWIN = true, the forward product inside the CG step): block partials of
-// ||q||^2 for the output q (for the step length of RRCG:6).
-// MODE = FUSE_GRAD (ROWIN = false, the transpose product inside the CG step): the output is the
-// gradient l of RRCG:4, from the Gramian scalars summed at the start, with its block partials
-// of ||l||^2 (for beta of RRCG:5).
-template <typename T, int N, bool ROWIN, int MODE>
-__global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a, Fuse<T> fz) {
-  static_assert(MODE == FUSE_NONE || (MODE == FUSE_QQ && ROWIN) || (MODE == FUSE_GRAD && !ROWIN), "fused form");
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
-  const int l = blockIdx.x / a.tiles, tile = blockIdx.x - l * a.tiles;
-  const int b = blockIdx.y;
-  const int RT = 2 * a.fpb;
-  cx<T>* buf = smem + f * BS;
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
-  F.init(a.tw, t);
-  double gg[3] = {0.0, 0.0, 0.0};  // Gramian scalars for the gradient form
-  if constexpr (MODE == FUSE_GRAD) gram_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lead && flat_block() == 0, gg);
-  const int r0 = tile * RT + 2 * f;
-  const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
-  cx<T> v[8];
-  if constexpr (ROWIN) {
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + ((long long)l * a.nrows + r0) * a.ld;
-    cx<T> ha[8], hb[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = t + i * TPF;
-      const int kk = k <= N / 2 ? k : N - k;
-      ha[i] = ra ? src[kk] : cx<T>{T(0), T(0)};
-      hb[i] = rb ? src[a.ld + kk] : cx<T>{T(0), T(0)};
-    }
-    for (int c = 1; c < a.nsum; ++c) {  // partials of the layer chunks, summed in order
-      const cx<T>* sc = src + c * a.in_cs;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = t + i * TPF;
-        const int kk = k <= N / 2 ? k : N - k;
-        if (ra) ha[i] = cadd(ha[i], sc[kk]);
-        if (rb) hb[i] = cadd(hb[i], sc[a.ld + kk]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = t + i * TPF;
-      const int kk = k <= N / 2 ? k : N - k;
-      if (kk == 0 || kk == N / 2) {  // DC and Nyquist of a real row are real
-        ha[i].im = T(0);
-        hb[i].im = T(0);
-      }
-      v[i] = k <= N / 2 ? cx<T>{ha[i].re - hb[i].im, ha[i].im + hb[i].re}
-                        : cx<T>{ha[i].re + hb[i].im, hb[i].re - ha[i].im};
-    }
-  } else {
-    // `in` is complex [nsum][L][K2][ld], summed over the nsum partials
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + (long long)l * K2 * a.ld + tile * RT;
-    for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
-      const int k2 = idx / RT, rr = idx - k2 * RT;
-      const int row = tile * RT + rr;
-      cx<T> hv{T(0), T(0)};
-      if (row < a.nrows) {
-        if (a.nsum == 1) {
-          hv = src[(long long)k2 * a.ld + rr];
-        } else {
-          double hr = 0.0, hi = 0.0;
-          for (int c = 0; c < a.nsum; ++c) {
-            const cx<T> u = src[c * a.in_cs + (long long)k2 * a.ld + rr];
-            hr += (double)u.re;
-            hi += (double)u.im;
-          }
-          hv = cx<T>{(T)hr, (T)hi};
-        }
-      }
-      if (k2 == 0 || k2 == K2 - 1) hv.im = T(0);  // DC and Nyquist of a real row are real
-      smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int k = t + i * TPF;
-      if (k <= N / 2) {
-        const cx<T> ha = buf[k], hb = buf[K2 + k];
-        v[i] = cx<T>{ha.re - hb.im, ha.im + hb.re};
-      } else {
-        const cx<T> ha = buf[N - k], hb = buf[K2 + N - k];
-        v[i] = cx<T>{ha.re + hb.im, hb.re - ha.im};
-      }
-    }
-  }
-  gsync();
-  F.template run<true>(v, buf, t, gsync);
-  const long long lofs = (long long)l * a.nrows * a.ncols;
-  T* dst = reinterpret_cast<T*>(a.out) + b * a.out_bs + lofs;
-  const T* sc = a.scale ? a.scale + lofs : nullptr;
-  if constexpr (MODE == FUSE_GRAD) {
-    const double al = fz.sc[S_ALPHA + fz.self], lam = fz.lam[fz.self];
-    const double g11 = gg[0], g22 = gg[1], g12 = gg[2];
-    double acc[1] = {0.0};
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int q = t + i * TPF;
-      if (q < a.ncols) {
-        const long long o = (long long)r0 * a.ncols + q;
-        if (ra) {
-          const T g = grad_element(fz, lofs + o, v[i].re * sc[o], al, lam, g11, g22, g12);
-          dst[o] = g;
-          acc[0] += (double)g * (double)g;
-        }
-        if (rb) {
-          const T g = grad_element(fz, lofs + o + a.ncols, v[i].im * sc[o + a.ncols], al, lam, g11, g22, g12);
-          dst[o + a.ncols] = g;
-          acc[0] += (double)g * (double)g;
-        }
-      }
-    }
-    block_partials<1>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_L1 : PB_L0);
-    return;
-  }
-  double acc[1] = {0.0};
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int q = t + i * TPF;
-    if (q < a.ncols) {
-      const long long o = (long long)r0 * a.ncols + q;
-      if (ra) {
-        const T y = sc ? v[i].re * sc[o] : v[i].re;
-        dst[o] = y;
-        if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
-      }
-      if (rb) {
-        const T y = sc ? v[i].im * sc[o + a.ncols] : v[i].im;
-        dst[o + a.ncols] = y;
-        if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
-      }
-    }
-  }
-  if constexpr (MODE == FUSE_QQ) block_partials<1>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_Q1 : PB_Q0);
-}
-
-// ------------------------------------------------------------------------------------
-// Column passes
-// ------------------------------------------------------------------------------------
-template <typename T>
-struct FColArgs {
-  const cx<T>* in;
-  long long in_bs;
-  const cx<T>* eig;
-  cx<T>* out;
-  long long out_bs;
-  long long out_cs;  // forward: stride between layer-chunk partials
-  int L, nin, nout, ldin, ldout, K2, fpb, nchunk;
-  const cx<T>* tw;
-};
-
-// Column jobs: job j in [1, Py/2) is column k2 = j; job 0 carries the two columns whose
-// row spectra are real, k2 = 0 and k2 = Py/2 (= K2-1), packed as one complex transform
-// c0 + i cN.  Their column transforms are recovered as X0[k] = (Z[k] + conj Z[-k]) / 2,
-// XN[k] = (Z[k] - conj Z[-k]) / (2i); products with eigenvalue columns of a real array
-// stay Hermitian, so the inverse of S0 + i SN returns s0 in its real and sN in its
-// imaginary part.  This gives Py/2 equal jobs.
-
-// Layer loop of the forward column pass for one group: acc += eig_l . FFT_x(column_l)
-// (PACKED: eig0 . X0 + i eigN . XN from the packed pair of real columns).  The next
-// layer's eigenvalues (and in FP32 its column) are loaded while the current one is
-// transformed; FP64 keeps the column load in place to stay within 256 registers.
-template <typename T, int N, bool PACKED>
-__device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
-                                           int G, int k2, int l0, int l1, int b, double (&ar)[8],
-                                           double (&ai)[8]) {
-  constexpr int TPF = N / 8;
-  constexpr bool PF_IN = sizeof(T) == 4;
-  GroupSync<TPF> gsync;
-  const int kN = a.K2 - 1;
-  const cx<T>* src = a.in + b * a.in_bs + (long long)k2 * a.ldin;
-  const cx<T>* srcN = a.in + b * a.in_bs + (long long)kN * a.ldin;
-  const cx<T>* eg = a.eig + (long long)k2 * N;
-  const cx<T>* egN = a.eig + (long long)kN * N;
-  const long long lstride_in = (long long)a.K2 * a.ldin, lstride_e = (long long)a.K2 * N;
-  const int nit = (l1 - l0 + G - 1) / G;
-  cx<T> un[PF_IN ? 8 : 1], en[8], enN[PACKED ? 8 : 1];
-  auto load_col = [&](int l, int i) -> cx<T> {
-    const int n = t + i * TPF;
-    if (l >= l1 || n >= a.nin) return cx<T>{T(0), T(0)};
-    if constexpr (PACKED) return cx<T>{src[l * lstride_in + n].re, srcN[l * lstride_in + n].re};
-    return src[l * lstride_in + n];
-  };
-  auto fetch = [&](int l) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if constexpr (PF_IN) un[i] = load_col(l, i);
-      en[i] = l < l1 ? eg[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
-      if constexpr (PACKED) enN[i] = l < l1 ? egN[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
-    }
-  };
-  fetch(l0 + f);
-  for (int it = 0; it < nit; ++it) {
-    const int l = l0 + it * G + f;
-    const bool act = l < l1;
-    cx<T> v[8], e[8], eN[PACKED ? 8 : 1];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if constexpr (PF_IN) v[i] = un[i];
-      else v[i] = load_col(l, i);
-      e[i] = en[i];
-      if constexpr (PACKED) eN[i] = enN[i];
-    }
-    if (it + 1 < nit) fetch(l + G);
-    F.template run<false>(v, buf, t, gsync);
-    if constexpr (PACKED) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) buf[lds_pad(t + i * TPF)] = v[i];
-      gsync();
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = t + i * TPF;
-        const cx<T> A = v[i], C = buf[lds_pad((N - k) & (N - 1))];
-        const double x0r = 0.5 * ((double)A.re + C.re), x0i = 0.5 * ((double)A.im - C.im);
-        const double xnr = 0.5 * ((double)A.im + C.im), xni = 0.5 * ((double)C.re - A.re);
-        const double pr = (double)e[i].re * x0r - (double)e[i].im * x0i;
-        const double pi = (double)e[i].re * x0i + (double)e[i].im * x0r;
-        const double qr = (double)eN[i].re * xnr - (double)eN[i].im * xni;
-        const double qi = (double)eN[i].re * xni + (double)eN[i].im * xnr;
-        if (act) {
-          ar[i] += pr - qi;
-          ai[i] += pi + qr;
-        }
-      }
-      gsync();
-    } else if (act) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const double xr = v[i].re, xi = v[i].im, wr = e[i].re, wi = e[i].im;
-        ar[i] += wr * xr - wi * xi;
-        ai[i] += wr * xi + wi * xr;
-      }
-    }
-  }
-}
-
-// Forward: partial over the layers of chunk c of sum_l eig_l . FFT_x(U_l column), then the
-// inverse FFT_x; rows p < nout are written row-major to out[c][p][k2] (ldout = padded K2).
-// FP64 column blocks are limited to 256 threads so that the registers beyond 256 per lane
-// (the accumulation registers) can hold what does not fit, instead of scratch memory.
-constexpr int col_threads(int esz) { return esz == 4 ? 512 : 256; }
-
-template <typename T, int N>
-__global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_fwd(FColArgs<T> a) {
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
-  const int G = a.fpb;
-  const int job = blockIdx.x, c = blockIdx.y, b = blockIdx.z;
-  const bool packed = job == 0;
-  const int k2 = job, kN = a.K2 - 1;
-  const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
-  cx<T>* buf = smem + f * P::BUF;
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
-  F.init(a.tw, t);
-  double ar[8], ai[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) ar[i] = ai[i] = 0.0;
-  if (packed) fwd_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-  else fwd_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-  // tree reduction of the groups' accumulators (G is a power of two)
-  double2* red = reinterpret_cast<double2*>(smem_raw);
-  for (int half = G >> 1; half >= 1; half >>= 1) {
-    __syncthreads();
-    if (f >= half && f < 2 * half) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) red[(f - half) * N + t + i * TPF] = make_double2(ar[i], ai[i]);
-    }
-    __syncthreads();
-    if (f < half) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const double2 u = red[f * N + t + i * TPF];
-        ar[i] += u.x;
-        ai[i] += u.y;
-      }
-    }
-  }
-  __syncthreads();
-  if (TPF > 64 || f == 0) {  // groups wider than a wave run the transform together
-    cx<T> v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = cx<T>{(T)ar[i], (T)ai[i]};
-    F.template run<true>(v, buf, t, gsync);
-    if (f == 0) {
-      cx<T>* dst = a.out + b * a.out_bs + c * a.out_cs;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int p = t + i * TPF;
-        if (p < a.nout) {
-          if (packed) {
-            dst[(long long)p * a.ldout] = cx<T>{v[i].re, T(0)};
-            dst[(long long)p * a.ldout + kN] = cx<T>{v[i].im, T(0)};
-          } else {
-            dst[(long long)p * a.ldout + k2] = v[i];
-          }
-        }
-      }
-    }
-  }
-}
-
-// Layer loop of the transpose column pass for one group: per layer conj(eig_l) R (PACKED:
-// conj(eig0) R0 + i conj(eigN) RN), inverse FFT_x, rows a < nout stored.
-template <typename T, int N, bool PACKED>
-__device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
-                                           int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8],
-                                           const cx<T> (&Rm)[8]) {
-  constexpr int TPF = N / 8;
-  GroupSync<TPF> gsync;
-  const int kN = a.K2 - 1;
-  const cx<T>* eg = a.eig + (long long)k2 * N;
-  const cx<T>* egN = a.eig + (long long)kN * N;
-  cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
-  cx<T>* dstN = a.out + b * a.out_bs + (long long)kN * a.ldout;
-  const long long lstride_out = (long long)a.K2 * a.ldout, lstride_e = (long long)a.K2 * N;
-  const int nit = (l1 - l0 + G - 1) / G;
-  cx<T> en[8], enN[PACKED ? 8 : 1];
-  auto fetch = [&](int l) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      en[i] = l < l1 ? eg[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
-      if constexpr (PACKED) enN[i] = l < l1 ? egN[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
-    }
-  };
-  fetch(l0 + f);
-  for (int it = 0; it < nit; ++it) {
-    const int l = l0 + it * G + f;
-    const bool act = l < l1;
-    cx<T> v[8];
-    if constexpr (PACKED) {
-      // conj(eig0) . R0 + i conj(eigN) . RN with R0, RN split from the packed spectrum
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const cx<T> A = R[i], C = Rm[i];
-        const T h = T(0.5);
-        const cx<T> r0{h * (A.re + C.re), h * (A.im - C.im)};
-        const cx<T> rn{h * (A.im + C.im), h * (C.re - A.re)};
-        const cx<T> p0 = cmulc(r0, en[i]), pn = cmulc(rn, enN[i]);
-        v[i] = cx<T>{p0.re - pn.im, p0.im + pn.re};
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], en[i]);
-    }
-    if (it + 1 < nit) fetch(l + G);
-    F.template run<true>(v, buf, t, gsync);
-    if (act) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int p = t + i * TPF;
-        if (p < a.nout) {
-          if constexpr (PACKED) {
-            dst[l * lstride_out + p] = cx<T>{v[i].re, T(0)};
-            dstN[l * lstride_out + p] = cx<T>{v[i].im, T(0)};
-          } else {
-            dst[l * lstride_out + p] = v[i];
-          }
-        }
-      }
-    }
-  }
-}
-
-// Transpose: R = FFT_x(Rrow column) once per block (group 0, shared through LDS), then for
-// each layer of chunk c, conj(eig_l) R and the inverse FFT_x; rows a < nout are written
-// to out[l][k2][a] (ldout = padded rows).  Rrow is row-major Rrow[p][k2] (ldin = padded K2).
-template <typename T, int N>
-__global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_adj(FColArgs<T> a) {
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
-  const int G = a.fpb;
-  const int job = blockIdx.x, c = blockIdx.y, b = blockIdx.z;
-  const bool packed = job == 0;
-  const int k2 = job, kN = a.K2 - 1;
-  const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
-  cx<T>* buf = smem + f * P::BUF;
-  cx<T>* Rs = smem + G * P::BUF;  // the shared column spectrum, N values
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
-  F.init(a.tw, t);
-  const cx<T>* col = a.in + b * a.in_bs;
-  if (TPF > 64 || f == 0) {
-    cx<T> R[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      const long long o = (long long)n * a.ldin;
-      R[i] = n >= a.nin ? cx<T>{T(0), T(0)} : (packed ? cx<T>{col[o].re, col[o + kN].re} : col[o + k2]);
-    }
-    F.template run<false>(R, buf, t, gsync);
-    if (f == 0) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) Rs[t + i * TPF] = R[i];
-    }
-  }
-  __syncthreads();
-  cx<T> R[8], Rm[8];  // Rm: the mirrored values Z[-k] of the packed job
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int k = t + i * TPF;
-    R[i] = Rs[k];
-    if (packed) Rm[i] = Rs[(N - k) & (N - 1)];
-  }
-  if (packed) adj_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-  else adj_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-}
 
 // ------------------------------------------------------------------------------------
 // Dispatch on the transform size

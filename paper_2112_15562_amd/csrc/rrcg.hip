@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(RB) k_weights(long long n, const T* m0, const 
     v[1] += u1 * u1;
     v[2] += u0 * u1;
   }
-  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11);
+  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, blockIdx.x, gridDim.x);
 }
 
 // l = A~^T r~ (already in l) + alpha (w m - w m_apr) + lambda l_G;  partials of ||l_i||^2.
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(RB) k_grad(long long n, T* l0, T* l1, const T*
     v[0] += (double)r0 * (double)r0;
     v[1] += (double)r1 * (double)r1;
   }
-  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_L0);
+  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_L0, blockIdx.x, gridDim.x);
 }
 
 // beta from ||l||^2; p = l + beta p; partials (p, l)_i and ||p_i||^2.
@@ -146,7 +146,7 @@ __global__ void __launch_bounds__(RB) k_dir(long long n, const T* l0, const T* l
     v[2] += (double)pbv * lb;
     v[3] += (double)pbv * (double)pbv;
   }
-  block_partials<4>(v, rd.pb, rd.pbn, rd.pbs, PB_PL0);
+  block_partials<4>(v, rd.pb, rd.pbn, rd.pbs, PB_PL0, blockIdx.x, gridDim.x);
 }
 
 // partials of ||q_i||^2.
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(RB) k_sumsq2(long long n, const T* a0, const T
     v[0] += x * x;
     v[1] += y * y;
   }
-  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_Q0);
+  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_Q0, blockIdx.x, gridDim.x);
 }
 
 // s from the partials (RRCG:6); m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w);
@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(RB) k_update(long long n, long long nd, T* m0,
       r1[j] = (T)((double)r1[j] - s1 * (double)q1[j]);
     }
   }
-  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11);
+  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, blockIdx.x, gridDim.x);
 }
 
 // m <- clip(m, lo, hi); Gramian partials of the projected m (original space).
@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(RB) k_clip(long long n, T* m0, T* m1, double l
     v[1] += (double)bt * (double)bt;
     v[2] += (double)at * (double)bt;
   }
-  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11);
+  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, blockIdx.x, gridDim.x);
 }
 
 // r~ = W_d (A m - d) (A m already in r); partials of ||r~_i||^2.
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(RB) k_resid(long long nd, T* r0, T* r1, const 
     v[0] += (double)a * (double)a;
     v[1] += (double)b * (double)b;
   }
-  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_F0);
+  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_F0, blockIdx.x, gridDim.x);
 }
 
 // Phi, S_G, and (advance = 1) the chi^2 test, freeze flags and alpha schedule (Sec. 2.6, 2.8);

@@ -49,13 +49,12 @@ struct Fuse {
   int pbs;        // partials per slot (>= blocks of any reducing launch)
 };
 
-__device__ __forceinline__ int flat_block() { return blockIdx.x + gridDim.x * blockIdx.y; }
-
 // Sum of v over the block (every thread calls; blockDim a multiple of 64 or a power of two
-// below 64, at most 1024) stored at pb[(slot0 + k) * pbs + block]; block 0 records the
-// number of blocks.
+// below 64, at most 1024) stored at pb[(slot0 + k) * pbs + bid]; block 0 of the nb blocks
+// records their number.
 template <int K>
-__device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* pbn, int pbs, int slot0) {
+__device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* pbn, int pbs, int slot0, int bid,
+                                               int nb) {
   __shared__ double sh[K][16];
   const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;  // xor partners stay among active lanes
 #pragma unroll
@@ -72,13 +71,12 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* 
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = (blockDim.x + 63) >> 6;
-    const int b = flat_block();
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += sh[k][w];
-      pb[(slot0 + k) * pbs + b] = s;
-      if (b == 0) pbn[slot0 + k] = gridDim.x * gridDim.y;
+      pb[(slot0 + k) * pbs + bid] = s;
+      if (bid == 0) pbn[slot0 + k] = nb;
     }
   }
 }
@@ -199,16 +197,20 @@ __device__ __forceinline__ void gram_from(double* sc, const double* pb, const in
 template <typename T>
 __device__ __forceinline__ T grad_element(const Fuse<T>& fz, long long j, T zt, double al, double lam, double g11,
                                           double g22, double g12) {
+  // pointers selected by condition, not by a run-time array index (which would put a
+  // private copy of the arguments in scratch memory)
+  const bool s0 = fz.self == 0;
+  const T* wself = s0 ? fz.w[0] : fz.w[1];
   const double a = fz.m[0][j], b = fz.m[1][j];
-  const double Ws = fz.w[fz.self][j];
+  const double Ws = wself[j];
   double u0 = a, u1 = b;
   if (fz.gram_w) {
-    const double Wo = fz.w[1 - fz.self][j];
-    u0 = fz.self == 0 ? Ws * a : Wo * a;
-    u1 = fz.self == 0 ? Wo * b : Ws * b;
+    const double Wo = (s0 ? fz.w[1] : fz.w[0])[j];
+    u0 = s0 ? Ws * a : Wo * a;
+    u1 = s0 ? Wo * b : Ws * b;
   }
-  const double lg = fz.self == 0 ? g22 * u0 - g12 * u1 : g11 * u1 - g12 * u0;
-  const double ms = fz.self == 0 ? a : b;
+  const double lg = s0 ? g22 * u0 - g12 * u1 : g11 * u1 - g12 * u0;
+  const double ms = s0 ? a : b;
   const double mt = Ws * ms, mta = fz.ma ? Ws * (double)fz.ma[j] : 0.0;
   return (T)((double)zt + al * (mt - mta) + lam * lg);
 }

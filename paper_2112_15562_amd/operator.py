@@ -54,7 +54,7 @@ class Operator:
     """
 
     def __init__(self, kernels: torch.Tensor, stations: Sequence[int], dtype=torch.float64,
-                 max_batch: int = 1, device="cuda"):
+                 max_batch: int = 1, device="cuda", pad_pow2: bool = False):
         if dtype not in _DT:
             raise TypeError("dtype must be torch.float32 or torch.float64")
         self.device = torch.device(device)
@@ -72,14 +72,16 @@ class Operator:
         self.dtype = dtype
         self.max_batch = int(max_batch)
         self._plan = C.c_void_p()
-        L.check(L.lib().bttb_setup(_ptr(k), sx, sy, nx, ny, nz, _DT[dtype], self.max_batch,
+        flags = _DT[dtype] | (L.BTTB_PAD_POW2 if pad_pow2 else 0)
+        L.check(L.lib().bttb_setup(_ptr(k), sx, sy, nx, ny, nz, flags, self.max_batch,
                                    C.c_void_p(_stream(self.device)), C.byref(self._plan)), "bttb_setup")
 
     @classmethod
-    def from_geometry(cls, kind: int, geometry, dtype=torch.float64, max_batch: int = 1, device="cuda"):
+    def from_geometry(cls, kind: int, geometry, dtype=torch.float64, max_batch: int = 1, device="cuda",
+                      pad_pow2: bool = False):
         T = prism_kernels(kind, geometry, device)
         g = _geometry(geometry)
-        return cls(T, (g.sx, g.sy), dtype=dtype, max_batch=max_batch, device=device)
+        return cls(T, (g.sx, g.sy), dtype=dtype, max_batch=max_batch, device=device, pad_pow2=pad_pow2)
 
     # ------------------------------------------------------------------------------
     @property
@@ -184,5 +186,87 @@ class Operator:
             if getattr(self, "_plan", None):
                 L.lib().bttb_destroy(self._plan)
                 self._plan = C.c_void_p()
+        except Exception:
+            pass
+
+
+def pointer_array(tensors, device) -> torch.Tensor:
+    """Device array of the tensors' addresses (int64), for the group entry points."""
+    return torch.tensor([0 if t is None else t.data_ptr() for t in tensors], dtype=torch.int64, device=device)
+
+
+class Group:
+    """The products of many operators (e.g. gravity and magnetic of many inversions of
+    uneven sizes) in one kernel launch per stage.  Members must be power-of-two plans
+    (Operator(..., pad_pow2=True)) of one dtype; the operators must stay open."""
+
+    def __init__(self, ops: Sequence[Operator]):
+        ops = list(ops)
+        if not ops:
+            raise ValueError("empty group")
+        self.ops = ops
+        self.dtype = ops[0].dtype
+        self.device = ops[0].device
+        arr = (C.c_void_p * len(ops))(*[op.plan.value for op in ops])
+        self._g = C.c_void_p()
+        L.check(L.lib().bttb_group_create(arr, len(ops), C.c_void_p(_stream(self.device)), C.byref(self._g)),
+                "bttb_group_create")
+
+    @property
+    def handle(self) -> C.c_void_p:
+        if not self._g:
+            raise RuntimeError("group is closed")
+        return self._g
+
+    def info(self) -> dict:
+        d = L.GroupDesc()
+        L.check(L.lib().bttb_group_info(self.handle, C.byref(d)), "bttb_group_info")
+        return {"count": d.count, "model_row_threads": d.model_row_threads,
+                "data_row_threads": d.data_row_threads, "col_threads": d.col_threads,
+                "layer_chunks": d.layer_chunks, "blocks": list(d.blocks)}
+
+    def set_launch(self, model_row_threads: int = 0, data_row_threads: int = 0, col_threads: int = 0,
+                   layer_chunks: int = 0):
+        L.check(L.lib().bttb_group_set_launch(self.handle, int(model_row_threads), int(data_row_threads),
+                                              int(col_threads), int(layer_chunks),
+                                              C.c_void_p(_stream(self.device))), "bttb_group_set_launch")
+
+    def apply_ptrs(self, op: int, ins: torch.Tensor, outs: torch.Tensor, winv: Optional[torch.Tensor] = None,
+                   wd: Optional[torch.Tensor] = None) -> None:
+        """Products with device pointer arrays (int64 tensors of one address per member)."""
+        L.check(L.lib().bttb_group_apply(self.handle, int(op), _ptr(ins), _ptr(outs), _ptr(winv), _ptr(wd),
+                                         C.c_void_p(_stream(self.device))), "bttb_group_apply")
+
+    def apply(self, op: int, xs: Sequence[torch.Tensor], winv=None, wd=None, outs=None):
+        n = len(self.ops)
+        if len(xs) != n:
+            raise ValueError("one input per member")
+        fwd = op == L.BTTB_OP_FORWARD
+        for o, x in zip(self.ops, xs):
+            if o._check_vec(x, o.model_shape if fwd else o.data_shape, "input") != 1:
+                raise ValueError("group products take one vector per member")
+        if outs is None:
+            outs = [torch.empty(o.data_shape if fwd else o.model_shape, dtype=self.dtype, device=self.device)
+                    for o in self.ops]
+        keep = [pointer_array(xs, self.device), pointer_array(outs, self.device),
+                pointer_array(winv, self.device) if winv is not None else None,
+                pointer_array(wd, self.device) if wd is not None else None]
+        self.apply_ptrs(op, *keep)
+        return outs
+
+    def matvec(self, xs, winv=None, wd=None):
+        return self.apply(L.BTTB_OP_FORWARD, xs, winv, wd)
+
+    def rmatvec(self, rs, winv=None, wd=None):
+        return self.apply(L.BTTB_OP_ADJOINT, rs, winv, wd)
+
+    def close(self):
+        if self._g:
+            L.lib().bttb_group_destroy(self._g)
+            self._g = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -1,0 +1,145 @@
+"""Group products (one launch per stage over many uneven plans) vs the FP64 oracle and vs
+the one-plan products (run on an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bttb as obttb
+from oracle import prism as oprism
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2112_15562_amd as pk
+    assert torch.cuda.is_available()
+    return pk
+
+
+# uneven members: transform sizes 32 .. 512 after power-of-two padding, ragged shapes,
+# sx < nx, both operators.  With the default shapes the smallest members run 64 row
+# transforms per block: row tiles of 128 rows over 12 rows padded to 16.
+MEMBERS = [
+    (oprism.GRAVITY, synth.Grid(12, 10, 12, 10, 5, 50.0, 50.0, 50.0)),
+    (oprism.MAGNETIC, synth.Grid(12, 10, 12, 10, 5, 50.0, 50.0, 50.0)),
+    (oprism.MAGNETIC, synth.Grid(30, 21, 33, 20, 7, 40.0, 45.0, 25.0, decl=15.0)),
+    (oprism.GRAVITY, synth.Grid(64, 64, 64, 64, 16, 40.0, 40.0, 25.0)),
+    (oprism.MAGNETIC, synth.Grid(40, 57, 40, 50, 9, 40.0, 40.0, 25.0)),
+    (oprism.GRAVITY, synth.Grid(100, 100, 100, 100, 12, 40.0, 40.0, 25.0)),
+    (oprism.MAGNETIC, synth.Grid(190, 130, 200, 120, 6, 40.0, 40.0, 25.0)),
+]
+
+_CACHE = {}
+
+
+def oracle_case(idx):
+    """Oracle kernel array, inputs and FP64 FFT2 products of member idx."""
+    if idx in _CACHE:
+        return _CACHE[idx]
+    kind, g = MEMBERS[idx]
+    og = oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+    T = obttb.kernel_array(kind, og)
+    x = synth.rng(6, idx).uniform(0.0, 1.0, g.model_shape)
+    r = synth.rng(6, 100 + idx).standard_normal(g.data_shape)
+    winv = synth.rng(6, 200 + idx).uniform(0.5, 2.0, g.model_shape)
+    wd = synth.rng(6, 300 + idx).uniform(0.5, 2.0, g.data_shape)
+    y = obttb.fft_matvec(T, x, g.sx, g.sy)
+    z = obttb.fft_rmatvec(T, r, g.sx, g.sy)
+    yw = obttb.weighted_matvec(T, x, winv, wd, g.sx, g.sy)
+    zw = obttb.weighted_rmatvec(T, r, winv, wd, g.sx, g.sy)
+    _CACHE[idx] = (T, x, r, winv, wd, y, z, yw, zw)
+    return _CACHE[idx]
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def make(pk, dtype, idxs=None):
+    idxs = list(range(len(MEMBERS))) if idxs is None else idxs
+    ops = []
+    for i in idxs:
+        T = oracle_case(i)[0]
+        g = MEMBERS[i][1]
+        ops.append(pk.Operator(torch.as_tensor(T, device="cuda"), (g.sx, g.sy), dtype=dtype, pad_pow2=True))
+    return ops, pk.Group(ops)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_group_products_match_oracle(pk, dtype, tol):
+    ops, grp = make(pk, dtype)
+    cases = [oracle_case(i) for i in range(len(MEMBERS))]
+    dev = lambda a: torch.as_tensor(a, dtype=dtype, device="cuda").contiguous()
+    xs = [dev(c[1]) for c in cases]
+    rs = [dev(c[2]) for c in cases]
+    ys = grp.matvec(xs)
+    zs = grp.rmatvec(rs)
+    yw = grp.matvec(xs, winv=[dev(c[3]) for c in cases], wd=[dev(c[4]) for c in cases])
+    zw = grp.rmatvec(rs, winv=[dev(c[3]) for c in cases], wd=[dev(c[4]) for c in cases])
+    for i, c in enumerate(cases):
+        assert rel(host(ys[i]), c[5]) <= tol, (i, "forward")
+        assert rel(host(zs[i]), c[6]) <= tol, (i, "transpose")
+        assert rel(host(yw[i]), c[7]) <= tol, (i, "weighted forward")
+        assert rel(host(zw[i]), c[8]) <= tol, (i, "weighted transpose")
+    # the same plans one at a time: the transposes do the same arithmetic per element; the
+    # forward layer sums may group differently
+    for i, op in enumerate(ops):
+        assert rel(host(op.matvec(xs[i])), host(ys[i])) <= (1e-14 if dtype == torch.float64 else 1e-6)
+        assert np.array_equal(host(op.rmatvec(rs[i])), host(zs[i]))
+    grp.close()
+    for op in ops:
+        op.close()
+
+
+def test_group_launch_shapes(pk):
+    ops, grp = make(pk, torch.float64)
+    cases = [oracle_case(i) for i in range(len(MEMBERS))]
+    dev = lambda a: torch.as_tensor(a, device="cuda").contiguous()
+    xs = [dev(c[1]) for c in cases]
+    rs = [dev(c[2]) for c in cases]
+    y0 = [host(y) for y in grp.matvec(xs)]
+    z0 = [host(z) for z in grp.rmatvec(rs)]
+    info = grp.info()
+    for rm, rd, cc, nch in [(64, 64, 64, 1), (512, 128, 256, 4), (128, 512, 128, 2)]:
+        grp.set_launch(rm, rd, cc, nch)
+        got = grp.info()
+        assert (got["model_row_threads"], got["data_row_threads"], got["col_threads"]) == (rm, rd, cc)
+        for i, y in enumerate(grp.matvec(xs)):
+            assert rel(host(y), y0[i]) <= 1e-14
+        for i, z in enumerate(grp.rmatvec(rs)):
+            assert np.array_equal(host(z), z0[i])
+    grp.set_launch(info["model_row_threads"], info["data_row_threads"], info["col_threads"], info["layer_chunks"])
+    grp.close()
+    for op in ops:
+        op.close()
+
+
+def test_group_rejects_bad_members_and_shapes(pk):
+    from paper_2112_15562_amd import _lib as L
+    T = torch.as_tensor(oracle_case(0)[0], device="cuda")
+    g = MEMBERS[0][1]
+    radix3 = pk.Operator(torch.zeros((2, 23, 23), dtype=torch.float64, device="cuda"), (12, 12))  # 24 x 24
+    a = pk.Operator(T, (g.sx, g.sy), dtype=torch.float64, pad_pow2=True)
+    b = pk.Operator(T, (g.sx, g.sy), dtype=torch.float32, pad_pow2=True)
+    assert a.info()["Px"] == 32 and radix3.info()["Px"] == 24
+    for members in ([radix3], [a, b]):
+        with pytest.raises(L.BTTBError) as e:
+            pk.Group(members)
+        assert e.value.status == L.BTTB_ESTATE
+    grp = pk.Group([a])
+    for bad in [(3, 0, 0, 0), (0, 1024, 0, 0), (0, 0, 512, 0), (2, 0, 0, 0)]:
+        with pytest.raises(L.BTTBError) as e:
+            grp.set_launch(*bad)
+        assert e.value.status == L.BTTB_EINVAL
+    with pytest.raises(ValueError):
+        grp.matvec([torch.zeros((2,) + g.model_shape, dtype=torch.float64, device="cuda")])
+    grp.close()
+    for op in (radix3, a, b):
+        op.close()
