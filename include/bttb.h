@@ -286,6 +286,37 @@ BTTB_API int rrcg_refresh(rrcg_handle h, void* stream);
 
 BTTB_API int rrcg_destroy(rrcg_handle h);
 
+/* Group solver: up to 32 joint inversions of uneven sizes stepped together.  Each
+ * inversion is described by its own rrcg_desc and keeps its own state, scalars and
+ * parameters, with the same arithmetic as a one-inversion solver; every phase of a step
+ * is one launch over all of them (the products of all their operators through one
+ * product group, the CG pieces fused into the row transforms, and the elementwise
+ * updates over the concatenated vectors).  All plans must be power-of-two plans
+ * (BTTB_PAD_POW2) of one precision; descs[0].use_graph decides graph capture for the
+ * whole group.  Creation allocates the work vectors and synchronises `stream`. */
+BTTB_API int rrcg_group_create(const rrcg_desc* descs, int count, void* stream, rrcg_group* out);
+
+/* One outer step of every inversion (as rrcg_step).  Asynchronous. */
+BTTB_API int rrcg_group_step(rrcg_group g, int n_inner, void* stream);
+
+/* Scalars of inversion `index` (0-based); synchronise `stream`. */
+BTTB_API int rrcg_group_read_scalars(rrcg_group g, int index, rrcg_scalars* out, void* stream);
+BTTB_API int rrcg_group_write_scalars(rrcg_group g, int index, const rrcg_scalars* in, void* stream);
+
+/* Recompute resid, Phi and S_G of every inversion from its current m. */
+BTTB_API int rrcg_group_refresh(rrcg_group g, void* stream);
+
+/* Launch shape of the group's products (as bttb_group_set_launch); recaptures the step
+ * graphs.  Synchronises `stream`. */
+BTTB_API int rrcg_group_set_launch(rrcg_group g, int model_row_threads, int data_row_threads, int col_threads,
+                                   int layer_chunks, void* stream);
+
+/* The product group the solver uses (owned by the solver; valid until rrcg_group_destroy),
+ * for inspection and timing. */
+BTTB_API int rrcg_group_products(rrcg_group g, bttb_group* out);
+
+BTTB_API int rrcg_group_destroy(rrcg_group g);
+
 /* ---------------------------------------------------------------------------------- */
 
 BTTB_API const char* bttb_strerror(int status);

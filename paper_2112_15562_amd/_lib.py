@@ -24,6 +24,8 @@ EXPORTED = [
     "rrcg_read_scalars", "rrcg_write_scalars", "rrcg_refresh", "rrcg_destroy", "bttb_strerror",
     "bttb_last_error", "bttb_timing_enable", "bttb_timing_read",
     "bttb_group_create", "bttb_group_apply", "bttb_group_set_launch", "bttb_group_info", "bttb_group_destroy",
+    "rrcg_group_create", "rrcg_group_step", "rrcg_group_read_scalars", "rrcg_group_write_scalars",
+    "rrcg_group_refresh", "rrcg_group_set_launch", "rrcg_group_products", "rrcg_group_destroy",
 ]
 NKERNELS = 6
 KERNEL_NAMES = ["fwd_row_r2c", "fwd_col_eig_sum", "fwd_row_c2r", "adj_row_r2c", "adj_col_conj_eig", "adj_row_c2r"]
@@ -107,6 +109,14 @@ def lib() -> C.CDLL:
         "bttb_group_set_launch": [vp, i, i, i, i, vp],
         "bttb_group_info": [vp, C.POINTER(GroupDesc)],
         "bttb_group_destroy": [vp],
+        "rrcg_group_create": [C.POINTER(RrcgDesc), i, vp, C.POINTER(vp)],
+        "rrcg_group_step": [vp, i, vp],
+        "rrcg_group_read_scalars": [vp, i, C.POINTER(RrcgScalars), vp],
+        "rrcg_group_write_scalars": [vp, i, C.POINTER(RrcgScalars), vp],
+        "rrcg_group_refresh": [vp, vp],
+        "rrcg_group_set_launch": [vp, i, i, i, i, vp],
+        "rrcg_group_products": [vp, C.POINTER(vp)],
+        "rrcg_group_destroy": [vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -30,11 +30,9 @@
 
 #include "common.h"
 #include "rrcg_fuse.h"
+#include "rrcg_kernels.h"
 
 namespace bttb {
-
-constexpr int RB = 256;     // threads per elementwise block
-constexpr int RGRID = 512;  // elementwise blocks (fixed, so reductions are repeatable)
 
 struct Rrcg {
   Plan* P[2];
@@ -65,193 +63,57 @@ struct Rrcg {
   hipGraphExec_t g_weights, g_inner_restart, g_inner, g_outer;
 };
 
-struct Red {  // where a reducing kernel puts its partials
-  double* pb;
-  int* pbn;
-  int pbs;
-};
-
 template <typename T>
 __global__ void __launch_bounds__(RB) k_weights(long long n, const T* m0, const T* m1, const T* ma0, const T* ma1,
                                                 const T* wz0, const T* wz1, const T* wh0, const T* wh1, double eps2,
                                                 int p_norm, int gram_w, T* w0, T* w1, T* wi0, T* wi1, double* sc,
                                                 Red rd) {
-  double v[3] = {0.0, 0.0, 0.0};
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
-    const double a = m0[j], b = m1[j];
-    double W0 = wz0[j], W1 = wz1[j];
-    if (wh0) W0 *= (double)wh0[j];
-    if (wh1) W1 *= (double)wh1[j];
-    if (p_norm == 1) {
-      const double d0 = a - (ma0 ? (double)ma0[j] : 0.0), d1 = b - (ma1 ? (double)ma1[j] : 0.0);
-      W0 *= 1.0 / pow(d0 * d0 + eps2, 0.25);
-      W1 *= 1.0 / pow(d1 * d1 + eps2, 0.25);
-    }
-    const T W0t = (T)W0, W1t = (T)W1;
-    w0[j] = W0t;
-    w1[j] = W1t;
-    wi0[j] = (T)(1.0 / (double)W0t);
-    wi1[j] = (T)(1.0 / (double)W1t);
-    const double u0 = gram_w ? (double)W0t * a : a, u1 = gram_w ? (double)W1t * b : b;
-    v[0] += u0 * u0;
-    v[1] += u1 * u1;
-    v[2] += u0 * u1;
-  }
-  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, blockIdx.x, gridDim.x);
+  weights_body<T>(n, m0, m1, ma0, ma1, wz0, wz1, wh0, wh1, eps2, p_norm, gram_w, w0, w1, wi0, wi1, sc, rd,
+                  blockIdx.x, gridDim.x);
 }
 
-// l = A~^T r~ (already in l) + alpha (w m - w m_apr) + lambda l_G;  partials of ||l_i||^2.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_grad(long long n, T* l0, T* l1, const T* m0, const T* m1, const T* w0,
                                              const T* w1, const T* ma0, const T* ma1, double* sc, double lam0,
                                              double lam1, int gram_w, Red rd) {
-  double gg[3];
-  gram_from(sc, rd.pb, rd.pbn, rd.pbs, blockIdx.x == 0, gg);
-  const double g11 = gg[0], g22 = gg[1], g12 = gg[2];
-  const double al0 = sc[S_ALPHA], al1 = sc[S_ALPHA + 1];
-  double v[2] = {0.0, 0.0};
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
-    const double a = m0[j], b = m1[j], W0 = w0[j], W1 = w1[j];
-    const double u0 = gram_w ? W0 * a : a, u1 = gram_w ? W1 * b : b;
-    const double lg0 = g22 * u0 - g12 * u1, lg1 = g11 * u1 - g12 * u0;
-    const double mt0 = W0 * a, mt1 = W1 * b;
-    const double mta0 = ma0 ? W0 * (double)ma0[j] : 0.0, mta1 = ma1 ? W1 * (double)ma1[j] : 0.0;
-    const T r0 = (T)((double)l0[j] + al0 * (mt0 - mta0) + lam0 * lg0);
-    const T r1 = (T)((double)l1[j] + al1 * (mt1 - mta1) + lam1 * lg1);
-    l0[j] = r0;
-    l1[j] = r1;
-    v[0] += (double)r0 * (double)r0;
-    v[1] += (double)r1 * (double)r1;
-  }
-  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_L0, blockIdx.x, gridDim.x);
+  grad_body<T>(n, l0, l1, m0, m1, w0, w1, ma0, ma1, sc, lam0, lam1, gram_w, rd, blockIdx.x, gridDim.x);
 }
 
-// beta from ||l||^2; p = l + beta p; partials (p, l)_i and ||p_i||^2.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_dir(long long n, const T* l0, const T* l1, T* p0, T* p1, double* sc,
                                             int restart_now, int coupled, Red rd) {
-  double bt[2], L[2];
-  beta_from(sc, rd.pb, rd.pbn, rd.pbs, restart_now, coupled, bt, L);
-  if (blockIdx.x == 0 && threadIdx.x == 0) record_beta(sc, bt, L);
-  const double b0 = bt[0], b1 = bt[1];
-  double v[4] = {0.0, 0.0, 0.0, 0.0};  // (p0,l0), ||p0||^2, (p1,l1), ||p1||^2
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
-    const double la = l0[j], lb = l1[j];
-    const T pa = (T)(la + b0 * (double)p0[j]);
-    const T pbv = (T)(lb + b1 * (double)p1[j]);
-    p0[j] = pa;
-    p1[j] = pbv;
-    v[0] += (double)pa * la;
-    v[1] += (double)pa * (double)pa;
-    v[2] += (double)pbv * lb;
-    v[3] += (double)pbv * (double)pbv;
-  }
-  block_partials<4>(v, rd.pb, rd.pbn, rd.pbs, PB_PL0, blockIdx.x, gridDim.x);
+  dir_body<T>(n, l0, l1, p0, p1, sc, restart_now, coupled, rd, blockIdx.x, gridDim.x);
 }
 
-// partials of ||q_i||^2.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_sumsq2(long long n, const T* a0, const T* a1, Red rd) {
-  double v[2] = {0.0, 0.0};
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
-    const double x = a0[j], y = a1[j];
-    v[0] += x * x;
-    v[1] += y * y;
-  }
-  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_Q0, blockIdx.x, gridDim.x);
+  sumsq2_body<T>(n, a0, a1, rd, blockIdx.x, gridDim.x);
 }
 
-// s from the partials (RRCG:6); m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w);
-// r~ <- r~ - s q; Gramian partials of the new m (on m or on w m).
 template <typename T>
 __global__ void __launch_bounds__(RB) k_update(long long n, long long nd, T* m0, T* m1, const T* p0, const T* p1,
                                                const T* w0, const T* w1, T* r0, T* r1, const T* q0, const T* q1,
                                                double* sc, double lam0, double lam1, int coupled, int gram_w,
                                                Red rd) {
-  double st[2];
-  step_from(sc, rd.pb, rd.pbn, rd.pbs, lam0, lam1, coupled, blockIdx.x == 0, st);
-  const double s0 = st[0], s1 = st[1];
-  double v[3] = {0.0, 0.0, 0.0};
-  const long long top = n > nd ? n : nd;
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < top; j += (long long)RGRID * RB) {
-    if (j < n) {
-      const double W0 = w0[j], W1 = w1[j];
-      const T a = (T)((W0 * (double)m0[j] - s0 * (double)p0[j]) / W0);
-      const T b = (T)((W1 * (double)m1[j] - s1 * (double)p1[j]) / W1);
-      m0[j] = a;
-      m1[j] = b;
-      const double u0 = gram_w ? W0 * (double)a : (double)a, u1 = gram_w ? W1 * (double)b : (double)b;
-      v[0] += u0 * u0;
-      v[1] += u1 * u1;
-      v[2] += u0 * u1;
-    }
-    if (j < nd) {
-      r0[j] = (T)((double)r0[j] - s0 * (double)q0[j]);
-      r1[j] = (T)((double)r1[j] - s1 * (double)q1[j]);
-    }
-  }
-  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, blockIdx.x, gridDim.x);
+  update_body<T>(n, nd, m0, m1, p0, p1, w0, w1, r0, r1, q0, q1, sc, lam0, lam1, coupled, gram_w, rd, blockIdx.x,
+                 gridDim.x);
 }
 
-// m <- clip(m, lo, hi); Gramian partials of the projected m (original space).
 template <typename T>
 __global__ void __launch_bounds__(RB) k_clip(long long n, T* m0, T* m1, double lo0, double hi0, double lo1,
                                              double hi1, Red rd) {
-  double v[3] = {0.0, 0.0, 0.0};
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < n; j += (long long)RGRID * RB) {
-    const double a = fmin(fmax((double)m0[j], lo0), hi0);
-    const double b = fmin(fmax((double)m1[j], lo1), hi1);
-    const T at = (T)a, bt = (T)b;
-    m0[j] = at;
-    m1[j] = bt;
-    v[0] += (double)at * (double)at;
-    v[1] += (double)bt * (double)bt;
-    v[2] += (double)at * (double)bt;
-  }
-  block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, blockIdx.x, gridDim.x);
+  clip_body<T>(n, m0, m1, lo0, hi0, lo1, hi1, rd, blockIdx.x, gridDim.x);
 }
 
-// r~ = W_d (A m - d) (A m already in r); partials of ||r~_i||^2.
 template <typename T>
 __global__ void __launch_bounds__(RB) k_resid(long long nd, T* r0, T* r1, const T* d0, const T* d1, const T* wd0,
                                               const T* wd1, Red rd) {
-  double v[2] = {0.0, 0.0};
-  for (long long j = blockIdx.x * (long long)RB + threadIdx.x; j < nd; j += (long long)RGRID * RB) {
-    const T a = (T)((double)wd0[j] * ((double)r0[j] - (double)d0[j]));
-    const T b = (T)((double)wd1[j] * ((double)r1[j] - (double)d1[j]));
-    r0[j] = a;
-    r1[j] = b;
-    v[0] += (double)a * (double)a;
-    v[1] += (double)b * (double)b;
-  }
-  block_partials<2>(v, rd.pb, rd.pbn, rd.pbs, PB_F0, blockIdx.x, gridDim.x);
+  resid_body<T>(nd, r0, r1, d0, d1, wd0, wd1, rd, blockIdx.x, gridDim.x);
 }
 
-// Phi, S_G, and (advance = 1) the chi^2 test, freeze flags and alpha schedule (Sec. 2.6, 2.8);
-// one block.
 __global__ void __launch_bounds__(RB) k_fin_outer(double* sc, Red rd, double q0, double q1, double amin0,
                                                   double amin1, int advance) {
-  const int sl[5] = {PB_G11, PB_G22, PB_G12, PB_F0, PB_F1};
-  double t[5];
-  slot_totals<5>(rd.pb, rd.pbn, rd.pbs, sl, t);
-  const double g11 = t[0], g22 = t[1], g12 = t[2], f0 = t[3], f1 = t[4];
-  if (threadIdx.x == 0) {
-    sc[S_PHI] = f0;
-    sc[S_PHI + 1] = f1;
-    sc[S_GRAM] = g11 * g22 - g12 * g12;
-    if (!isfinite(f0) || !isfinite(f1) || !isfinite(g11) || !isfinite(g22)) sc[S_NONFIN] = 1.0;
-    if (advance) {
-      const double thr = sc[S_THR];
-      const bool p0 = f0 <= thr, p1 = f1 <= thr;
-      const bool fr0 = sc[S_FROZEN] != 0.0 || p0, fr1 = sc[S_FROZEN + 1] != 0.0 || p1;
-      sc[S_FROZEN] = fr0 ? 1.0 : 0.0;
-      sc[S_FROZEN + 1] = fr1 ? 1.0 : 0.0;
-      sc[S_CONV] = (p0 && p1) ? 1.0 : 0.0;
-      if (!fr0) sc[S_ALPHA] = fmax(q0 * sc[S_ALPHA], amin0);
-      if (!fr1) sc[S_ALPHA + 1] = fmax(q1 * sc[S_ALPHA + 1], amin1);
-      sc[S_K] += 1.0;
-    }
-  }
+  fin_outer_body(sc, rd, q0, q1, amin0, amin1, advance, 0, 1);
 }
 
 static Red red_of(const Rrcg* h) { return Red{h->pb, h->pbn, h->pbs}; }

@@ -1,0 +1,536 @@
+// Joint RRCG over many inversions at once (Sec. 2.4 eqs. RRCG:1-8, Sec. 2.5-2.6, Sec. 2.8).
+//
+// Every inversion keeps its own state, scalars and parameters, exactly as the one-inversion
+// solver (rrcg.hip), but each phase of a step is one launch over all of them: the products
+// of all gravity and magnetic operators go through a product group (group.hip) with the CG
+// pieces fused into their row transforms (gradient, direction, ||q||^2), and each
+// elementwise kernel runs over the concatenated blocks of all inversions, a block finding
+// its inversion in a prefix table.  The step's phases are captured once into HIP graphs.
+// Inversions of uneven sizes therefore share every launch: the small ones ride along
+// with the large ones instead of each leaving most of the GPU idle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "group.h"
+#include "rrcg_fuse.h"
+#include "rrcg_kernels.h"
+
+namespace bttb {
+
+constexpr int GINV_MAX = GMAX / 2;  // inversions per group (two operators each)
+
+// One inversion as the elementwise kernels see it (device table).
+template <typename T>
+struct GInv {
+  long long n, nd;
+  T* m[2];
+  T* p[2];
+  T* rt[2];
+  T* l[2];
+  T* w[2];
+  T* wi[2];
+  T* qv[2];
+  const T* dobs[2];
+  const T* wd[2];
+  const T* wdepth[2];
+  const T* whard[2];
+  const T* mapr[2];
+  double lo[2], hi[2], q[2], amin[2], lam[2], eps2;
+  int coupled, p_norm, gram_w;
+  double* sc;
+  double* pb;
+  int* pbn;
+  int pbs;
+};
+
+struct GStart {  // first elementwise block of each inversion
+  int count;
+  int start[GINV_MAX + 1];
+};
+
+__device__ __forceinline__ int inversion_of(const GStart& st, int blk) {
+  int i = 0;
+  while (i + 1 < st.count && blk >= st.start[i + 1]) ++i;
+  return i;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_gweights(const GInv<T>* inv, GStart st) {
+  const int i = inversion_of(st, blockIdx.x);
+  const GInv<T>& v = inv[i];
+  const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
+  weights_body<T>(v.n, v.m[0], v.m[1], v.mapr[0], v.mapr[1], v.wdepth[0], v.wdepth[1], v.whard[0], v.whard[1],
+                  v.eps2, v.p_norm, v.gram_w, v.w[0], v.w[1], v.wi[0], v.wi[1], v.sc, Red{v.pb, v.pbn, v.pbs},
+                  local, nb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_gupdate(const GInv<T>* inv, GStart st) {
+  const int i = inversion_of(st, blockIdx.x);
+  const GInv<T>& v = inv[i];
+  const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
+  update_body<T>(v.n, v.nd, v.m[0], v.m[1], v.p[0], v.p[1], v.w[0], v.w[1], v.rt[0], v.rt[1], v.qv[0], v.qv[1],
+                 v.sc, v.lam[0], v.lam[1], v.coupled, v.gram_w, Red{v.pb, v.pbn, v.pbs}, local, nb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_gclip(const GInv<T>* inv, GStart st, int advance) {
+  const int i = inversion_of(st, blockIdx.x);
+  const GInv<T>& v = inv[i];
+  const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
+  if (advance)
+    clip_body<T>(v.n, v.m[0], v.m[1], v.lo[0], v.hi[0], v.lo[1], v.hi[1], Red{v.pb, v.pbn, v.pbs}, local, nb);
+  else  // Gramian partials only
+    clip_body<T>(v.n, v.m[0], v.m[1], -HUGE_VAL, HUGE_VAL, -HUGE_VAL, HUGE_VAL, Red{v.pb, v.pbn, v.pbs}, local, nb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_gresid(const GInv<T>* inv, GStart st) {
+  const int i = inversion_of(st, blockIdx.x);
+  const GInv<T>& v = inv[i];
+  const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
+  resid_body<T>(v.nd, v.rt[0], v.rt[1], v.dobs[0], v.dobs[1], v.wd[0], v.wd[1], Red{v.pb, v.pbn, v.pbs}, local, nb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RB) k_gfin_outer(const GInv<T>* inv, int advance) {  // one block per inversion
+  const GInv<T>& v = inv[blockIdx.x];
+  fin_outer_body(v.sc, Red{v.pb, v.pbn, v.pbs}, v.q[0], v.q[1], v.amin[0], v.amin[1], advance, 0, 1);
+}
+
+// ------------------------------------------------------------------------------------
+struct RrcgGroup {
+  int count, precision, use_graph;
+  Group* grp;             // products of the 2 count operators: member 2 i + d = data set d of inversion i
+  void* inv;              // dev GInv<T>[count]
+  GStart est;             // elementwise blocks
+  void** ptrs;            // dev pointer arrays, PA_COUNT x (2 count)
+  void* fz[2];            // dev Fuse<T>[2 count]: [0] plain step, [1] restart step
+  double* sc;             // [count][S_COUNT]
+  double* pb;             // partials of all inversions
+  int* pbn;               // [count][PB_NSLOT]
+  void* vec[GINV_MAX][7];  // owned: l0, l1, w0, w1, wi0, wi1, qv (qv holds both data sets)
+  long long n[GINV_MAX], nd[GINV_MAX];
+  double alpha0[GINV_MAX][2];
+  hipStream_t cap;
+  hipGraphExec_t g_weights, g_inner_restart, g_inner, g_outer;
+};
+
+// Device pointer arrays (one entry per member) of the group products.
+enum { PA_RT = 0, PA_L, PA_WI, PA_WD, PA_P, PA_QV, PA_M, PA_COUNT };
+
+static const void* const* pa(const RrcgGroup* h, int k) {
+  return reinterpret_cast<const void* const*>(h->ptrs + (size_t)k * 2 * h->count);
+}
+
+template <typename T>
+static int g_outer(RrcgGroup* h, hipStream_t s, int advance) {
+  const GInv<T>* inv = static_cast<const GInv<T>*>(h->inv);
+  const int nb = h->est.start[h->count];
+  hipLaunchKernelGGL(k_gclip<T>, dim3(nb), dim3(RB), 0, s, inv, h->est, advance);
+  BTTB_LAUNCHED("k_gclip");
+  int rc = group_apply_impl<T>(h->grp, BTTB_OP_FORWARD, pa(h, PA_M), const_cast<void* const*>(pa(h, PA_RT)),
+                               nullptr, nullptr, nullptr, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_gresid<T>, dim3(nb), dim3(RB), 0, s, inv, h->est);
+  BTTB_LAUNCHED("k_gresid");
+  hipLaunchKernelGGL(k_gfin_outer<T>, dim3(h->count), dim3(RB), 0, s, inv, advance);
+  BTTB_LAUNCHED("k_gfin_outer");
+  return BTTB_OK;
+}
+
+template <typename T>
+static int g_weights(RrcgGroup* h, hipStream_t s) {
+  hipLaunchKernelGGL(k_gweights<T>, dim3(h->est.start[h->count]), dim3(RB), 0, s,
+                     static_cast<const GInv<T>*>(h->inv), h->est);
+  BTTB_LAUNCHED("k_gweights");
+  return BTTB_OK;
+}
+
+template <typename T>
+static int g_inner(RrcgGroup* h, int restart_now, hipStream_t s) {
+  const Fuse<T>* fz = static_cast<const Fuse<T>*>(h->fz[restart_now ? 1 : 0]);
+  int rc = group_apply_impl<T>(h->grp, BTTB_OP_ADJOINT, pa(h, PA_RT), const_cast<void* const*>(pa(h, PA_L)),
+                               pa(h, PA_WI), pa(h, PA_WD), fz, s);
+  if (rc) return rc;
+  rc = group_apply_impl<T>(h->grp, BTTB_OP_FORWARD, pa(h, PA_P), const_cast<void* const*>(pa(h, PA_QV)),
+                           pa(h, PA_WI), pa(h, PA_WD), fz, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_gupdate<T>, dim3(h->est.start[h->count]), dim3(RB), 0, s,
+                     static_cast<const GInv<T>*>(h->inv), h->est);
+  BTTB_LAUNCHED("k_gupdate");
+  return BTTB_OK;
+}
+
+template <typename Fn>
+static int g_capture(RrcgGroup* h, Fn fn, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  int rc = BTTB_OK;
+  hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "rrcg_group: hipStreamBeginCapture");
+  rc = fn(h->cap);
+  e = hipStreamEndCapture(h->cap, &g);
+  if (rc == BTTB_OK && e != hipSuccess) rc = hip_fail(e, "rrcg_group: hipStreamEndCapture");
+  if (rc == BTTB_OK) {
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = hip_fail(e, "rrcg_group: hipGraphInstantiate");
+  }
+  if (g) (void)hipGraphDestroy(g);
+  return rc;
+}
+
+static void g_drop_graphs(RrcgGroup* h) {
+  for (hipGraphExec_t* g : {&h->g_weights, &h->g_inner_restart, &h->g_inner, &h->g_outer}) {
+    if (*g) (void)hipGraphExecDestroy(*g);
+    *g = nullptr;
+  }
+}
+
+template <typename T>
+static int g_build_graphs(RrcgGroup* h) {
+  g_drop_graphs(h);
+  int rc = g_capture(h, [&](hipStream_t s) { return g_weights<T>(h, s); }, &h->g_weights);
+  if (!rc) rc = g_capture(h, [&](hipStream_t s) { return g_inner<T>(h, 1, s); }, &h->g_inner_restart);
+  if (!rc) rc = g_capture(h, [&](hipStream_t s) { return g_inner<T>(h, 0, s); }, &h->g_inner);
+  if (!rc) rc = g_capture(h, [&](hipStream_t s) { return g_outer<T>(h, s, 1); }, &h->g_outer);
+  return rc;
+}
+
+template <typename T>
+static int g_step(RrcgGroup* h, int n_inner, hipStream_t s) {
+  if (h->use_graph) {
+    BTTB_HIP(hipGraphLaunch(h->g_weights, s));
+    for (int j = 0; j < n_inner; ++j) BTTB_HIP(hipGraphLaunch(j == 0 ? h->g_inner_restart : h->g_inner, s));
+    BTTB_HIP(hipGraphLaunch(h->g_outer, s));
+    return BTTB_OK;
+  }
+  int rc = g_weights<T>(h, s);
+  for (int j = 0; j < n_inner && !rc; ++j) rc = g_inner<T>(h, j == 0 ? 1 : 0, s);
+  return rc ? rc : g_outer<T>(h, s, 1);
+}
+
+static void g_free(RrcgGroup* h) {
+  if (!h) return;
+  g_drop_graphs(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->grp) group_destroy(h->grp);
+  for (int i = 0; i < h->count; ++i)
+    for (void* v : h->vec[i]) dfree(v);
+  dfree(h->inv);
+  dfree(h->ptrs);
+  dfree(h->fz[0]);
+  dfree(h->fz[1]);
+  dfree(h->sc);
+  dfree(h->pb);
+  dfree(h->pbn);
+  delete h;
+}
+
+static int check_desc(const rrcg_desc* d, size_t es) {
+  Plan* P0 = reinterpret_cast<Plan*>(d->plan[0]);
+  Plan* P1 = reinterpret_cast<Plan*>(d->plan[1]);
+  if (!P0 || !P1) return fail(BTTB_EINVAL, "rrcg_group_create: NULL plan");
+  if (P0->sx != P1->sx || P0->sy != P1->sy || P0->nx != P1->nx || P0->ny != P1->ny || P0->nz != P1->nz ||
+      P0->precision != P1->precision)
+    return fail(BTTB_ESTATE, "rrcg_group_create: the two plans of an inversion differ in grid or precision");
+  for (int i = 0; i < 2; ++i) {
+    if (!d->m[i] || !d->p[i] || !d->resid[i] || !d->dobs[i] || !d->wd[i] || !d->wdepth[i])
+      return fail(BTTB_EINVAL, "rrcg_group_create: NULL vector");
+    const void* vs[8] = {d->m[i], d->p[i], d->resid[i], d->dobs[i], d->wd[i], d->wdepth[i], d->whard[i],
+                         d->mapr[i]};
+    for (const void* v : vs)
+      if (v && !aligned(v, es)) return fail(BTTB_EINVAL, "rrcg_group_create: misaligned vector");
+    if (!(d->lo[i] <= d->hi[i])) return fail(BTTB_EINVAL, "rrcg_group_create: lo > hi");
+    if (!(d->alpha0[i] >= 0) || !(d->q[i] > 0) || !(d->lambda[i] >= 0) || !(d->alpha_min[i] >= 0))
+      return fail(BTTB_EINVAL, "rrcg_group_create: alpha0, alpha_min, lambda must be >= 0 and q > 0");
+  }
+  if (!(d->eps2 > 0)) return fail(BTTB_EINVAL, "rrcg_group_create: eps2 must be > 0");
+  if (d->p_norm != 1 && d->p_norm != 2) return fail(BTTB_EINVAL, "rrcg_group_create: p_norm must be 1 or 2");
+  return BTTB_OK;
+}
+
+template <typename T>
+static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
+  const int n2 = 2 * h->count;
+  GInv<T> inv[GINV_MAX];
+  Fuse<T> fz[2][GMAX];
+  const void* ptr[PA_COUNT][GMAX];
+  long long pb_off = 0;
+  std::vector<long long> offs(h->count);
+  for (int i = 0; i < h->count; ++i) {
+    const Plan* P = reinterpret_cast<const Plan*>(descs[i].plan[0]);
+    const long long rows_blocks = (long long)P->nz * ((P->nx + 1) / 2);
+    offs[i] = pb_off;
+    const int pbs = (int)std::max<long long>(RGRID, std::max<long long>(rows_blocks, (P->sx + 1) / 2));
+    inv[i].pbs = pbs;
+    pb_off += (long long)PB_NSLOT * pbs;
+  }
+  if (hipMalloc((void**)&h->pb, (size_t)pb_off * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BTTB_ENOMEM, "rrcg_group_create: device allocation failed");
+  }
+  for (int i = 0; i < h->count; ++i) {
+    const rrcg_desc& d = descs[i];
+    GInv<T>& v = inv[i];
+    v.n = h->n[i];
+    v.nd = h->nd[i];
+    T* qv = static_cast<T*>(h->vec[i][6]);
+    for (int k = 0; k < 2; ++k) {
+      v.m[k] = static_cast<T*>(d.m[k]);
+      v.p[k] = static_cast<T*>(d.p[k]);
+      v.rt[k] = static_cast<T*>(d.resid[k]);
+      v.l[k] = static_cast<T*>(h->vec[i][k]);
+      v.w[k] = static_cast<T*>(h->vec[i][2 + k]);
+      v.wi[k] = static_cast<T*>(h->vec[i][4 + k]);
+      v.qv[k] = qv + k * h->nd[i];
+      v.dobs[k] = static_cast<const T*>(d.dobs[k]);
+      v.wd[k] = static_cast<const T*>(d.wd[k]);
+      v.wdepth[k] = static_cast<const T*>(d.wdepth[k]);
+      v.whard[k] = static_cast<const T*>(d.whard[k]);
+      v.mapr[k] = static_cast<const T*>(d.mapr[k]);
+      v.lo[k] = d.lo[k];
+      v.hi[k] = d.hi[k];
+      v.q[k] = d.q[k];
+      v.amin[k] = d.alpha_min[k];
+      v.lam[k] = d.lambda[k];
+    }
+    v.eps2 = d.eps2;
+    v.coupled = d.coupled ? 1 : 0;
+    v.p_norm = d.p_norm;
+    v.gram_w = d.gramian_weighted ? 1 : 0;
+    v.sc = h->sc + (size_t)i * S_COUNT;
+    v.pb = h->pb + offs[i];
+    v.pbn = h->pbn + (size_t)i * PB_NSLOT;
+    for (int k = 0; k < 2; ++k) {
+      const int mi = 2 * i + k;
+      ptr[PA_RT][mi] = v.rt[k];
+      ptr[PA_L][mi] = v.l[k];
+      ptr[PA_WI][mi] = v.wi[k];
+      ptr[PA_WD][mi] = v.wd[k];
+      ptr[PA_P][mi] = v.p[k];
+      ptr[PA_QV][mi] = v.qv[k];
+      ptr[PA_M][mi] = v.m[k];
+      for (int r = 0; r < 2; ++r) {
+        Fuse<T>& f = fz[r][mi];
+        f = Fuse<T>{};
+        f.self = k;
+        f.lead = k == 0;
+        f.restart = r == 1 && d.restart ? 1 : 0;
+        f.coupled = v.coupled;
+        f.gram_w = v.gram_w;
+        f.lam[0] = d.lambda[0];
+        f.lam[1] = d.lambda[1];
+        f.l = v.l[k];
+        f.p = v.p[k];
+        f.m[0] = v.m[0];
+        f.m[1] = v.m[1];
+        f.w[0] = v.w[0];
+        f.w[1] = v.w[1];
+        f.ma = v.mapr[k];
+        f.sc = v.sc;
+        f.pb = v.pb;
+        f.pbn = v.pbn;
+        f.pbs = v.pbs;
+      }
+    }
+  }
+  BTTB_HIP(hipMemcpyAsync(h->inv, inv, sizeof(GInv<T>) * h->count, hipMemcpyHostToDevice, s));
+  for (int r = 0; r < 2; ++r)
+    BTTB_HIP(hipMemcpyAsync(h->fz[r], fz[r], sizeof(Fuse<T>) * n2, hipMemcpyHostToDevice, s));
+  for (int k = 0; k < PA_COUNT; ++k)
+    BTTB_HIP(hipMemcpyAsync(h->ptrs + (size_t)k * n2, ptr[k], sizeof(void*) * n2, hipMemcpyHostToDevice, s));
+  // scalars: alpha = alpha0, chi^2 threshold, everything else zero
+  std::vector<double> sc((size_t)h->count * S_COUNT, 0.0);
+  for (int i = 0; i < h->count; ++i) {
+    sc[(size_t)i * S_COUNT + S_ALPHA] = descs[i].alpha0[0];
+    sc[(size_t)i * S_COUNT + S_ALPHA + 1] = descs[i].alpha0[1];
+    sc[(size_t)i * S_COUNT + S_THR] = (double)h->nd[i] + std::sqrt(2.0 * (double)h->nd[i]);
+  }
+  BTTB_HIP(hipMemcpyAsync(h->sc, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  BTTB_HIP(hipMemsetAsync(h->pbn, 0, (size_t)h->count * PB_NSLOT * sizeof(int), s));
+  BTTB_HIP(hipStreamSynchronize(s));
+  return BTTB_OK;
+}
+
+static void elementwise_blocks(RrcgGroup* h) {
+  h->est.count = h->count;
+  h->est.start[0] = 0;
+  for (int i = 0; i < h->count; ++i) {
+    const long long top = std::max(h->n[i], h->nd[i]);
+    const long long nb = std::min<long long>(RGRID, std::max<long long>(1, ceil_div((int)std::min<long long>(
+                                                                                top, 1LL << 30), RB * 4)));
+    h->est.start[i + 1] = h->est.start[i] + (int)nb;
+  }
+}
+
+}  // namespace bttb
+
+using namespace bttb;
+
+extern "C" int rrcg_group_create(const rrcg_desc* descs, int count, void* stream, rrcg_group* out) {
+  if (!descs || !out) return fail(BTTB_EINVAL, "rrcg_group_create: NULL argument");
+  *out = nullptr;
+  if (count < 1 || count > GINV_MAX) return fail(BTTB_EINVAL, "rrcg_group_create: count must be in [1, 32]");
+  const Plan* P00 = reinterpret_cast<const Plan*>(descs[0].plan[0]);
+  if (!P00) return fail(BTTB_EINVAL, "rrcg_group_create: NULL plan");
+  const int precision = P00->precision;
+  const size_t es = precision == BTTB_F64 ? 8 : 4;
+  for (int i = 0; i < count; ++i) {
+    int rc = check_desc(&descs[i], es);
+    if (rc) return rc;
+    if (reinterpret_cast<const Plan*>(descs[i].plan[0])->precision != precision)
+      return fail(BTTB_ESTATE, "rrcg_group_create: inversions differ in precision");
+  }
+  RrcgGroup* h = new (std::nothrow) RrcgGroup{};
+  if (!h) return fail(BTTB_ENOMEM, "rrcg_group_create: host allocation failed");
+  h->count = count;
+  h->precision = precision;
+  h->use_graph = descs[0].use_graph ? 1 : 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bttb_plan plans[GMAX];
+  for (int i = 0; i < count; ++i) {
+    plans[2 * i] = descs[i].plan[0];
+    plans[2 * i + 1] = descs[i].plan[1];
+    const Plan* P = reinterpret_cast<const Plan*>(descs[i].plan[0]);
+    h->n[i] = (long long)P->nx * P->ny * P->nz;
+    h->nd[i] = (long long)P->sx * P->sy;
+  }
+  int rc = group_create(plans, 2 * count, stream, &h->grp);
+  if (rc) {
+    h->grp = nullptr;
+    g_free(h);
+    return rc;
+  }
+  bool ok = true;
+  for (int i = 0; i < count && ok; ++i) {
+    const size_t nb = (size_t)h->n[i] * es;
+    for (int k = 0; k < 6 && ok; ++k) ok = hipMalloc(&h->vec[i][k], nb) == hipSuccess;
+    ok = ok && hipMalloc(&h->vec[i][6], 2 * (size_t)h->nd[i] * es) == hipSuccess;
+  }
+  const size_t fzb = (precision == BTTB_F64 ? sizeof(Fuse<double>) : sizeof(Fuse<float>)) * 2 * count;
+  const size_t invb = (precision == BTTB_F64 ? sizeof(GInv<double>) : sizeof(GInv<float>)) * count;
+  ok = ok && hipMalloc(&h->inv, invb) == hipSuccess && hipMalloc(&h->fz[0], fzb) == hipSuccess &&
+       hipMalloc(&h->fz[1], fzb) == hipSuccess &&
+       hipMalloc((void**)&h->ptrs, sizeof(void*) * PA_COUNT * 2 * count) == hipSuccess &&
+       hipMalloc((void**)&h->sc, sizeof(double) * S_COUNT * count) == hipSuccess &&
+       hipMalloc((void**)&h->pbn, sizeof(int) * PB_NSLOT * count) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    g_free(h);
+    return fail(BTTB_ENOMEM, "rrcg_group_create: device allocation failed");
+  }
+  elementwise_blocks(h);
+  rc = precision == BTTB_F64 ? g_tables<double>(h, descs, s) : g_tables<float>(h, descs, s);
+  if (!rc) rc = precision == BTTB_F64 ? g_outer<double>(h, s, 0) : g_outer<float>(h, s, 0);
+  if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(BTTB_EHIP, "rrcg_group_create: synchronize");
+  if (!rc && h->use_graph) {
+    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
+      rc = fail(BTTB_EHIP, "rrcg_group_create: capture stream");
+    else
+      rc = precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
+  }
+  if (rc) {
+    g_free(h);
+    return rc;
+  }
+  *out = reinterpret_cast<rrcg_group>(h);
+  return BTTB_OK;
+}
+
+extern "C" int rrcg_group_step(rrcg_group hh, int n_inner, void* stream) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_group_step: NULL handle");
+  if (n_inner < 1) return fail(BTTB_EINVAL, "rrcg_group_step: n_inner must be >= 1");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->precision == BTTB_F64 ? g_step<double>(h, n_inner, s) : g_step<float>(h, n_inner, s);
+}
+
+extern "C" int rrcg_group_refresh(rrcg_group hh, void* stream) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_group_refresh: NULL handle");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return h->precision == BTTB_F64 ? g_outer<double>(h, s, 0) : g_outer<float>(h, s, 0);
+}
+
+extern "C" int rrcg_group_set_launch(rrcg_group hh, int model_row_threads, int data_row_threads, int col_threads,
+                                     int layer_chunks, void* stream) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_group_set_launch: NULL handle");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BTTB_HIP(hipStreamSynchronize(s));
+  int rc = group_set_launch(h->grp, model_row_threads, data_row_threads, col_threads, layer_chunks, s);
+  if (!rc && h->use_graph) rc = h->precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
+  return rc;
+}
+
+extern "C" int rrcg_group_products(rrcg_group hh, bttb_group* out) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h || !out) return fail(BTTB_EINVAL, "rrcg_group_products: NULL argument");
+  *out = reinterpret_cast<bttb_group>(h->grp);
+  return BTTB_OK;
+}
+
+static int g_scalars_io(RrcgGroup* h, int index, double* sc, bool write, hipStream_t s) {
+  if (index < 0 || index >= h->count) return fail(BTTB_EINVAL, "rrcg_group scalars: index out of range");
+  double* dev = h->sc + (size_t)index * S_COUNT;
+  if (write)
+    BTTB_HIP(hipMemcpyAsync(dev, sc, S_COUNT * sizeof(double), hipMemcpyHostToDevice, s));
+  else
+    BTTB_HIP(hipMemcpyAsync(sc, dev, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+  BTTB_HIP(hipStreamSynchronize(s));
+  return BTTB_OK;
+}
+
+extern "C" int rrcg_group_read_scalars(rrcg_group hh, int index, rrcg_scalars* out, void* stream) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h || !out) return fail(BTTB_EINVAL, "rrcg_group_read_scalars: NULL argument");
+  double sc[S_COUNT];
+  int rc = g_scalars_io(h, index, sc, false, static_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  for (int i = 0; i < 2; ++i) {
+    out->alpha[i] = sc[S_ALPHA + i];
+    out->L_prev[i] = sc[S_LPREV + i];
+    out->phi[i] = sc[S_PHI + i];
+    out->beta[i] = sc[S_BETA + i];
+    out->step[i] = sc[S_STEP + i];
+    out->frozen[i] = sc[S_FROZEN + i] != 0.0;
+  }
+  out->threshold = sc[S_THR];
+  out->gramian = sc[S_GRAM];
+  out->k = (int)sc[S_K];
+  out->converged = sc[S_CONV] != 0.0;
+  out->nonfinite = sc[S_NONFIN] != 0.0;
+  return BTTB_OK;
+}
+
+extern "C" int rrcg_group_write_scalars(rrcg_group hh, int index, const rrcg_scalars* in, void* stream) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h || !in) return fail(BTTB_EINVAL, "rrcg_group_write_scalars: NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double sc[S_COUNT];
+  int rc = g_scalars_io(h, index, sc, false, s);
+  if (rc) return rc;
+  for (int i = 0; i < 2; ++i) {
+    sc[S_ALPHA + i] = in->alpha[i];
+    sc[S_LPREV + i] = in->L_prev[i];
+    sc[S_PHI + i] = in->phi[i];
+    sc[S_BETA + i] = in->beta[i];
+    sc[S_STEP + i] = in->step[i];
+    sc[S_FROZEN + i] = in->frozen[i] ? 1.0 : 0.0;
+  }
+  sc[S_GRAM] = in->gramian;
+  sc[S_K] = (double)in->k;
+  sc[S_CONV] = in->converged ? 1.0 : 0.0;
+  sc[S_NONFIN] = in->nonfinite ? 1.0 : 0.0;
+  return g_scalars_io(h, index, sc, true, s);
+}
+
+extern "C" int rrcg_group_destroy(rrcg_group hh) {
+  g_free(reinterpret_cast<RrcgGroup*>(hh));
+  return BTTB_OK;
+}

@@ -21,13 +21,8 @@ def _pair(v):
     return (float(v), float(v))
 
 
-class JointRRCG:
-    """Joint gravity-magnetic inversion with L1 reweighting and the Gramian constraint.
-
-    ops: (gravity operator, magnetic operator) with the same grids and dtype.
-    dobs, wd: [sx][sy] tensors per data set (wd = 1/sigma); wdepth (and optional whard,
-    mapr): [nz][nx][ny].  m0: starting models (default m_apr, or zeros).
-    """
+class _Inversion:
+    """Device state and C description of one joint inversion (tensors owned here)."""
 
     def __init__(self, ops: Sequence[Operator], dobs, wd, wdepth, whard=None, mapr=None, *,
                  lo=-math.inf, hi=math.inf, alpha0=20000.0, q=0.95, alpha_min=0.0, lam=0.0,
@@ -80,8 +75,46 @@ class JointRRCG:
         d.p_norm = int(p_norm)
         d.gramian_weighted = 1 if gramian == "weighted" else 0
         d.use_graph = int(bool(use_graph))
+        self.desc = d
+
+
+def _scalars_dict(s: L.RrcgScalars) -> dict:
+    return dict(alpha=list(s.alpha), L_prev=list(s.L_prev), phi=list(s.phi), threshold=s.threshold,
+                beta=list(s.beta), step=list(s.step), gramian=s.gramian, frozen=[bool(x) for x in s.frozen],
+                k=s.k, converged=bool(s.converged), nonfinite=bool(s.nonfinite))
+
+
+def _apply_scalars(s: L.RrcgScalars, kw: dict) -> None:
+    for k, v in kw.items():
+        if k in ("alpha", "L_prev", "phi", "beta", "step"):
+            getattr(s, k)[:] = [float(x) for x in v]
+        elif k == "frozen":
+            s.frozen[:] = [int(bool(x)) for x in v]
+        elif k in ("k", "converged", "nonfinite"):
+            setattr(s, k, int(v))
+        elif k == "gramian":
+            s.gramian = float(v)
+        else:
+            raise KeyError(k)
+
+
+class JointRRCG:
+    """Joint gravity-magnetic inversion with L1 reweighting and the Gramian constraint.
+
+    ops: (gravity operator, magnetic operator) with the same grids and dtype.
+    dobs, wd: [sx][sy] tensors per data set (wd = 1/sigma); wdepth (and optional whard,
+    mapr): [nz][nx][ny].  m0: starting models (default m_apr, or zeros).
+    """
+
+    def __init__(self, ops: Sequence[Operator], dobs, wd, wdepth, whard=None, mapr=None, **kw):
+        self._inv = _Inversion(ops, dobs, wd, wdepth, whard, mapr, **kw)
+        inv = self._inv
+        self.ops, self.dtype, self.device = inv.ops, inv.dtype, inv.device
+        self.dobs, self.wd, self.wdepth, self.whard, self.mapr = inv.dobs, inv.wd, inv.wdepth, inv.whard, inv.mapr
+        self.m, self.p, self.resid = inv.m, inv.p, inv.resid
         self._h = C.c_void_p()
-        L.check(L.lib().rrcg_create(C.byref(d), C.c_void_p(self._stream()), C.byref(self._h)), "rrcg_create")
+        L.check(L.lib().rrcg_create(C.byref(inv.desc), C.c_void_p(self._stream()), C.byref(self._h)),
+                "rrcg_create")
 
     def _stream(self) -> int:
         return _stream(self.device)
@@ -93,24 +126,12 @@ class JointRRCG:
     def scalars(self) -> dict:
         s = L.RrcgScalars()
         L.check(L.lib().rrcg_read_scalars(self._h, C.byref(s), C.c_void_p(self._stream())), "rrcg_read_scalars")
-        return dict(alpha=list(s.alpha), L_prev=list(s.L_prev), phi=list(s.phi), threshold=s.threshold,
-                    beta=list(s.beta), step=list(s.step), gramian=s.gramian, frozen=[bool(x) for x in s.frozen],
-                    k=s.k, converged=bool(s.converged), nonfinite=bool(s.nonfinite))
+        return _scalars_dict(s)
 
     def set_scalars(self, **kw) -> None:
         s = L.RrcgScalars()
         L.check(L.lib().rrcg_read_scalars(self._h, C.byref(s), C.c_void_p(self._stream())), "rrcg_read_scalars")
-        for k, v in kw.items():
-            if k in ("alpha", "L_prev", "phi", "beta", "step"):
-                getattr(s, k)[:] = [float(x) for x in v]
-            elif k == "frozen":
-                s.frozen[:] = [int(bool(x)) for x in v]
-            elif k in ("k", "converged", "nonfinite"):
-                setattr(s, k, int(v))
-            elif k == "gramian":
-                s.gramian = float(v)
-            else:
-                raise KeyError(k)
+        _apply_scalars(s, kw)
         L.check(L.lib().rrcg_write_scalars(self._h, C.byref(s), C.c_void_p(self._stream())), "rrcg_write_scalars")
 
     def refresh(self) -> None:
@@ -156,5 +177,86 @@ class JointRRCG:
             if getattr(self, "_h", None):
                 L.lib().rrcg_destroy(self._h)
                 self._h = C.c_void_p()
+        except Exception:
+            pass
+
+
+class JointRRCGGroup:
+    """Many joint inversions (up to 32, uneven sizes) stepped together: every phase of an
+    outer step is one launch over all of them.  problems: sequence of dicts with the
+    arguments of JointRRCG (ops, dobs, wd, wdepth and optionally whard, mapr and any solver
+    parameter); `defaults` fills parameters a problem does not give.  The operators must be
+    power-of-two plans (Operator(..., pad_pow2=True)) of one dtype."""
+
+    def __init__(self, problems, use_graph: bool = True, **defaults):
+        self.inv = []
+        for pr in problems:
+            kw = dict(defaults)
+            kw.update(pr)
+            ops = kw.pop("ops")
+            args = [kw.pop(k) for k in ("dobs", "wd", "wdepth")]
+            whard, mapr = kw.pop("whard", None), kw.pop("mapr", None)
+            kw["use_graph"] = use_graph
+            self.inv.append(_Inversion(ops, *args, whard, mapr, **kw))
+        if not self.inv:
+            raise ValueError("no problems")
+        self.device = self.inv[0].device
+        arr = (L.RrcgDesc * len(self.inv))(*[v.desc for v in self.inv])
+        self._h = C.c_void_p()
+        L.check(L.lib().rrcg_group_create(arr, len(self.inv), C.c_void_p(self._stream()), C.byref(self._h)),
+                "rrcg_group_create")
+
+    def __len__(self):
+        return len(self.inv)
+
+    def _stream(self) -> int:
+        return _stream(self.device)
+
+    def m(self, i: int):
+        return self.inv[i].m
+
+    def step(self, n_inner: int = 1) -> None:
+        """One outer step of every inversion (asynchronous)."""
+        L.check(L.lib().rrcg_group_step(self._h, int(n_inner), C.c_void_p(self._stream())), "rrcg_group_step")
+
+    def scalars(self, i: int) -> dict:
+        s = L.RrcgScalars()
+        L.check(L.lib().rrcg_group_read_scalars(self._h, int(i), C.byref(s), C.c_void_p(self._stream())),
+                "rrcg_group_read_scalars")
+        return _scalars_dict(s)
+
+    def set_scalars(self, i: int, **kw) -> None:
+        s = L.RrcgScalars()
+        L.check(L.lib().rrcg_group_read_scalars(self._h, int(i), C.byref(s), C.c_void_p(self._stream())),
+                "rrcg_group_read_scalars")
+        _apply_scalars(s, kw)
+        L.check(L.lib().rrcg_group_write_scalars(self._h, int(i), C.byref(s), C.c_void_p(self._stream())),
+                "rrcg_group_write_scalars")
+
+    def refresh(self) -> None:
+        L.check(L.lib().rrcg_group_refresh(self._h, C.c_void_p(self._stream())), "rrcg_group_refresh")
+
+    def set_launch(self, model_row_threads=0, data_row_threads=0, col_threads=0, layer_chunks=0) -> None:
+        L.check(L.lib().rrcg_group_set_launch(self._h, int(model_row_threads), int(data_row_threads),
+                                              int(col_threads), int(layer_chunks), C.c_void_p(self._stream())),
+                "rrcg_group_set_launch")
+
+    def launch_info(self) -> dict:
+        g = C.c_void_p()
+        L.check(L.lib().rrcg_group_products(self._h, C.byref(g)), "rrcg_group_products")
+        d = L.GroupDesc()
+        L.check(L.lib().bttb_group_info(g, C.byref(d)), "bttb_group_info")
+        return {"count": d.count, "model_row_threads": d.model_row_threads, "data_row_threads": d.data_row_threads,
+                "col_threads": d.col_threads, "layer_chunks": d.layer_chunks, "blocks": list(d.blocks)}
+
+    def close(self):
+        if self._h:
+            torch.cuda.synchronize(self.device)
+            L.lib().rrcg_group_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

@@ -1,0 +1,133 @@
+"""Group solver (many joint inversions stepped together, one launch per phase) vs the FP64
+oracle and vs one-inversion solvers (run on an MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import rrcg as orrcg
+from test_gpu_rrcg import BASE, host, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2112_15562_amd as pk
+    assert torch.cuda.is_available()
+    return pk
+
+
+# uneven inversions (transforms 32 after power-of-two padding, ragged 7 x 9 over 11 x 5 x 3)
+GRIDS = [synth.SMALL, synth.SUB, synth.Grid(7, 9, 11, 5, 3, 40.0, 30.0, 25.0, decl=20.0),
+         synth.Grid(10, 14, 10, 14, 4, 50.0, 40.0, 30.0)]
+# one solver variant per inversion: nested with restart, stand-alone, joint minimum length,
+# weighted Gramian without restart
+VARIANTS = [
+    dict(restart=True),
+    dict(restart=True, coupled=False, lam=(0.0, 0.0)),
+    dict(restart=True, p_norm=2, alpha_min=(500.0, 500.0)),
+    dict(restart=False, gramian="weighted", lam=(1e-3, 1e-1)),
+]
+N_INNER = 3
+
+
+def params(v):
+    kw = dict(BASE)
+    kw.update(v)
+    return orrcg.Params(**kw)
+
+
+def solver_kwargs(prm):
+    return dict(lo=prm.lo, hi=prm.hi, alpha0=prm.alpha0, q=prm.q, alpha_min=prm.alpha_min, lam=prm.lam,
+                eps2=prm.eps2, coupled=prm.coupled, restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian)
+
+
+def ops_for(pk, g, T, dtype):
+    return [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=dtype, pad_pow2=True)
+            for i in range(2)]
+
+
+def build_group(pk, dtype, use_graph=True):
+    probs, refs = [], []
+    for g, v in zip(GRIDS, VARIANTS):
+        ops, T, data, _ = problem(g, dense=True)
+        prm = params(v)
+        probs.append(dict(ops=ops_for(pk, g, T, dtype), dobs=data.dobs, wd=data.wd, wdepth=data.wdepth,
+                          **solver_kwargs(prm)))
+        refs.append((g, ops, T, data, prm))
+    return pk.JointRRCGGroup(probs, use_graph=use_graph), refs
+
+
+def set_state(grp, i, st, dtype):
+    for k in range(2):
+        grp.inv[i].m[k].copy_(torch.as_tensor(st.m[k], dtype=dtype, device="cuda"))
+        grp.inv[i].p[k].copy_(torch.as_tensor(st.p[k], dtype=dtype, device="cuda"))
+    grp.set_scalars(i, alpha=st.alpha, L_prev=st.L_prev, frozen=st.frozen, k=st.k)
+
+
+# p, the CG direction, is an intermediate: in FP32 it carries the rounding of the gradient
+# l = A~^T r~ + alpha m~ + ..., whose terms cancel more and more as the inner CG converges
+# (1e-3 relative after three steps here), so only the FP64 run checks it; the results -- the
+# models and the misfits -- are held to the precision bounds in both.
+@pytest.mark.parametrize("dtype,tol_m,tol_p", [(torch.float64, 1e-12, 1e-11), (torch.float32, 1e-5, None)])
+def test_group_step_parity_per_inversion(pk, dtype, tol_m, tol_p):
+    grp, refs = build_group(pk, dtype)
+    expected = []
+    for i, (g, ops, T, data, prm) in enumerate(refs):
+        st, _ = orrcg.run(ops, data, prm, n_outer=2, n_inner=N_INNER)   # a mid-solve state
+        ref, rec = orrcg.outer_step(ops, data, prm, st, N_INNER)
+        set_state(grp, i, st, dtype)
+        expected.append((ref, rec))
+    grp.refresh()
+    grp.step(N_INNER)
+    for i, (ref, rec) in enumerate(expected):
+        sc = grp.scalars(i)
+        for k in range(2):
+            assert rel(host(grp.inv[i].m[k]), ref.m[k]) <= tol_m, (i, k)
+            if tol_p is not None:
+                assert rel(host(grp.inv[i].p[k]), ref.p[k]) <= tol_p, (i, k)
+            assert sc["alpha"][k] == pytest.approx(ref.alpha[k], rel=1e-15)
+            assert sc["phi"][k] == pytest.approx(rec["phi"][k], rel=tol_m * 10)
+            assert sc["frozen"][k] == ref.frozen[k]
+        assert sc["k"] == ref.k
+        assert not sc["nonfinite"]
+    grp.close()
+
+
+def test_group_equals_one_inversion_solvers_and_graphs(pk):
+    grp, refs = build_group(pk, torch.float64, use_graph=True)
+    eager, _ = build_group(pk, torch.float64, use_graph=False)
+    singles = []
+    for g, ops, T, data, prm in refs:
+        singles.append(pk.JointRRCG(ops_for(pk, g, T, torch.float64), data.dobs, data.wd, data.wdepth,
+                                    **solver_kwargs(prm)))
+    for _ in range(3):
+        grp.step(N_INNER)
+        eager.step(N_INNER)
+        for s in singles:
+            s.step(N_INNER)
+    for i, s in enumerate(singles):
+        for k in range(2):
+            a, b = host(grp.inv[i].m[k]), host(eager.inv[i].m[k])
+            assert np.array_equal(a, b), (i, k)          # graph replay == eager
+            assert rel(a, host(s.m[k])) <= 1e-12, (i, k)  # same arithmetic, other partial sums
+        assert grp.scalars(i)["k"] == s.scalars()["k"] == 3
+        s.close()
+    grp.close()
+    eager.close()
+
+
+def test_group_launch_shape_recaptures(pk):
+    grp, _ = build_group(pk, torch.float64)
+    ref, _ = build_group(pk, torch.float64)
+    grp.set_launch(model_row_threads=64, data_row_threads=64, col_threads=64, layer_chunks=2)
+    info = grp.launch_info()
+    assert (info["model_row_threads"], info["col_threads"], info["layer_chunks"]) == (64, 64, 2)
+    grp.step(N_INNER)
+    ref.step(N_INNER)
+    for i in range(len(grp)):
+        for k in range(2):
+            assert rel(host(grp.inv[i].m[k]), host(ref.inv[i].m[k])) <= 1e-12
+    grp.close()
+    ref.close()
