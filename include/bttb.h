@@ -205,6 +205,30 @@ BTTB_API int bttb_group_info(bttb_group g, bttb_group_desc* out);
 BTTB_API int bttb_group_destroy(bttb_group g);
 
 /* ---------------------------------------------------------------------------------- */
+/* Launch-shape autotuning                                                              */
+/* ---------------------------------------------------------------------------------- */
+
+/* Result of an autotuning call. */
+typedef struct {
+  double us_per_pair; /* time of one forward plus one transpose product (per member set
+                         for a group) with the chosen shape, microseconds */
+  int shape[4];       /* plan: column FFTs per block, row FFTs per block, layer chunks, 0;
+                         group: model-row, data-row and column threads per block, layer chunks */
+  int tried;          /* candidate shapes timed */
+} bttb_tune_result;
+
+/* Time the products of a plan (or group) under candidate launch shapes and keep the
+ * fastest: `reps` (1..1000) forward and transpose products per candidate on zero-filled
+ * scratch vectors, between HIP events on `stream`.  A plan sweeps every valid
+ * combination of column FFTs per block, row FFTs per block (1, 2, 4, 8) and layer chunks
+ * (1, 2, 4, 8, 16); a group tunes its four coordinates one at a time, twice round.
+ * Results of later products are unchanged up to the grouping of the forward layer sums.
+ * Allocates and frees the scratch vectors; synchronises `stream`.  Tune a plan before
+ * creating a solver on it (a solver captures the shapes in its graphs).  out nullable. */
+BTTB_API int bttb_autotune(bttb_plan plan, int reps, void* stream, bttb_tune_result* out);
+BTTB_API int bttb_group_autotune(bttb_group g, int reps, void* stream, bttb_tune_result* out);
+
+/* ---------------------------------------------------------------------------------- */
 /* Joint RRCG (Sec. 2.4 eqs. RRCG:1-8, Sec. 2.5-2.6, Sec. 2.8)                          */
 /* ---------------------------------------------------------------------------------- */
 
@@ -310,6 +334,9 @@ BTTB_API int rrcg_group_refresh(rrcg_group g, void* stream);
  * graphs.  Synchronises `stream`. */
 BTTB_API int rrcg_group_set_launch(rrcg_group g, int model_row_threads, int data_row_threads, int col_threads,
                                    int layer_chunks, void* stream);
+
+/* bttb_group_autotune on the solver's products, then the step graphs are recaptured. */
+BTTB_API int rrcg_group_autotune(rrcg_group g, int reps, void* stream, bttb_tune_result* out);
 
 /* The product group the solver uses (owned by the solver; valid until rrcg_group_destroy),
  * for inspection and timing. */

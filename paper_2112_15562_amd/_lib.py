@@ -26,6 +26,7 @@ EXPORTED = [
     "bttb_group_create", "bttb_group_apply", "bttb_group_set_launch", "bttb_group_info", "bttb_group_destroy",
     "rrcg_group_create", "rrcg_group_step", "rrcg_group_read_scalars", "rrcg_group_write_scalars",
     "rrcg_group_refresh", "rrcg_group_set_launch", "rrcg_group_products", "rrcg_group_destroy",
+    "bttb_autotune", "bttb_group_autotune", "rrcg_group_autotune",
 ]
 NKERNELS = 6
 KERNEL_NAMES = ["fwd_row_r2c", "fwd_col_eig_sum", "fwd_row_c2r", "adj_row_r2c", "adj_col_conj_eig", "adj_row_c2r"]
@@ -55,6 +56,10 @@ class GroupDesc(C.Structure):
     _fields_ = [("count", C.c_int), ("precision", C.c_int), ("model_row_threads", C.c_int),
                 ("data_row_threads", C.c_int), ("col_threads", C.c_int), ("layer_chunks", C.c_int),
                 ("blocks", C.c_int * 6)]
+
+
+class TuneResult(C.Structure):
+    _fields_ = [("us_per_pair", C.c_double), ("shape", C.c_int * 4), ("tried", C.c_int)]
 
 
 class RrcgDesc(C.Structure):
@@ -117,6 +122,9 @@ def lib() -> C.CDLL:
         "rrcg_group_set_launch": [vp, i, i, i, i, vp],
         "rrcg_group_products": [vp, C.POINTER(vp)],
         "rrcg_group_destroy": [vp],
+        "bttb_autotune": [vp, i, vp, C.POINTER(TuneResult)],
+        "bttb_group_autotune": [vp, i, vp, C.POINTER(TuneResult)],
+        "rrcg_group_autotune": [vp, i, vp, C.POINTER(TuneResult)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -51,6 +51,7 @@ struct Group {
 int group_create(const bttb_plan* plans, int count, void* stream, Group** out);
 void group_destroy(Group* g);
 int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s);
+int group_autotune(Group* g, int reps, hipStream_t s, bttb_tune_result* out);
 template <typename T>
 int group_apply_impl(const Group* g, int op, const void* const* in, void* const* out, const void* const* winv,
                      const void* const* wd, const Fuse<T>* fz, hipStream_t s);

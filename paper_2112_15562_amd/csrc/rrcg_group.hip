@@ -468,6 +468,17 @@ extern "C" int rrcg_group_set_launch(rrcg_group hh, int model_row_threads, int d
   return rc;
 }
 
+extern "C" int rrcg_group_autotune(rrcg_group hh, int reps, void* stream, bttb_tune_result* out) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_group_autotune: NULL handle");
+  if (reps < 1 || reps > 1000) return fail(BTTB_EINVAL, "rrcg_group_autotune: reps must be in [1, 1000]");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BTTB_HIP(hipStreamSynchronize(s));
+  int rc = group_autotune(h->grp, reps, s, out);
+  if (!rc && h->use_graph) rc = h->precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
+  return rc;
+}
+
 extern "C" int rrcg_group_products(rrcg_group hh, bttb_group* out) {
   RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
   if (!h || !out) return fail(BTTB_EINVAL, "rrcg_group_products: NULL argument");

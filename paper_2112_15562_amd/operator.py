@@ -107,6 +107,15 @@ class Operator:
         L.check(L.lib().bttb_set_launch(self.plan, col_fft_per_block, row_fft_per_block, layer_chunks),
                 "bttb_set_launch")
 
+    def autotune(self, reps: int = 5) -> dict:
+        """Time the products under every valid launch shape and keep the fastest (run it
+        before creating a solver on this operator)."""
+        r = L.TuneResult()
+        L.check(L.lib().bttb_autotune(self.plan, int(reps), C.c_void_p(_stream(self.device)), C.byref(r)),
+                "bttb_autotune")
+        return {"us_per_pair": r.us_per_pair, "col_fft_per_block": r.shape[0], "row_fft_per_block": r.shape[1],
+                "layer_chunks": r.shape[2], "tried": r.tried}
+
     def timing_enable(self, max_launches: int, repeat: int = 1) -> None:
         """Record HIP events around each product kernel (max_launches kernels), each kernel
         launched `repeat` times back to back between its events."""
@@ -190,6 +199,11 @@ class Operator:
             pass
 
 
+def _tune_dict(r) -> dict:
+    return {"us_per_pair": r.us_per_pair, "model_row_threads": r.shape[0], "data_row_threads": r.shape[1],
+            "col_threads": r.shape[2], "layer_chunks": r.shape[3], "tried": r.tried}
+
+
 def pointer_array(tensors, device) -> torch.Tensor:
     """Device array of the tensors' addresses (int64), for the group entry points."""
     return torch.tensor([0 if t is None else t.data_ptr() for t in tensors], dtype=torch.int64, device=device)
@@ -230,6 +244,13 @@ class Group:
         L.check(L.lib().bttb_group_set_launch(self.handle, int(model_row_threads), int(data_row_threads),
                                               int(col_threads), int(layer_chunks),
                                               C.c_void_p(_stream(self.device))), "bttb_group_set_launch")
+
+    def autotune(self, reps: int = 5) -> dict:
+        """Tune the threads per block of each stage and the layer chunks by timing."""
+        r = L.TuneResult()
+        L.check(L.lib().bttb_group_autotune(self.handle, int(reps), C.c_void_p(_stream(self.device)), C.byref(r)),
+                "bttb_group_autotune")
+        return _tune_dict(r)
 
     def apply_ptrs(self, op: int, ins: torch.Tensor, outs: torch.Tensor, winv: Optional[torch.Tensor] = None,
                    wd: Optional[torch.Tensor] = None) -> None:

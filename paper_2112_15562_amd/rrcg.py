@@ -241,6 +241,14 @@ class JointRRCGGroup:
                                               int(col_threads), int(layer_chunks), C.c_void_p(self._stream())),
                 "rrcg_group_set_launch")
 
+    def autotune(self, reps: int = 5) -> dict:
+        """Tune the launch shape of the group's products by timing; recaptures the graphs."""
+        from .operator import _tune_dict
+        r = L.TuneResult()
+        L.check(L.lib().rrcg_group_autotune(self._h, int(reps), C.c_void_p(self._stream()), C.byref(r)),
+                "rrcg_group_autotune")
+        return _tune_dict(r)
+
     def launch_info(self) -> dict:
         g = C.c_void_p()
         L.check(L.lib().rrcg_group_products(self._h, C.byref(g)), "rrcg_group_products")

@@ -121,6 +121,25 @@ def test_group_launch_shapes(pk):
         op.close()
 
 
+def test_group_autotune(pk):
+    ops, grp = make(pk, torch.float32)
+    cases = [oracle_case(i) for i in range(len(MEMBERS))]
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float32, device="cuda").contiguous()
+    res = grp.autotune(reps=2)
+    info = grp.info()
+    assert res["tried"] >= 4 and res["us_per_pair"] > 0
+    assert [info[k] for k in ("model_row_threads", "data_row_threads", "col_threads", "layer_chunks")] == \
+        [res[k] for k in ("model_row_threads", "data_row_threads", "col_threads", "layer_chunks")]
+    ys = grp.matvec([dev(c[1]) for c in cases])
+    zs = grp.rmatvec([dev(c[2]) for c in cases])
+    for i, c in enumerate(cases):
+        assert rel(host(ys[i]), c[5]) <= 1e-5
+        assert rel(host(zs[i]), c[6]) <= 1e-5
+    grp.close()
+    for op in ops:
+        op.close()
+
+
 def test_group_rejects_bad_members_and_shapes(pk):
     from paper_2112_15562_amd import _lib as L
     T = torch.as_tensor(oracle_case(0)[0], device="cuda")

@@ -228,6 +228,24 @@ def test_launch_shape_and_repeatability(pk):
     op.close()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_autotune_keeps_results(pk, dtype):
+    g = synth.MID
+    x, _ = synth.random_boxes(g)
+    v = synth.normal_like(g.data_shape, 2, 3)
+    op = pk.Operator.from_geometry(pk.GRAVITY, g, dtype=dtype)
+    y0, z0 = host(op.matvec(dev(x, dtype))), host(op.rmatvec(dev(v, dtype)))
+    res = op.autotune(reps=2)
+    info = op.info()
+    assert res["tried"] >= 8 and res["us_per_pair"] > 0
+    assert (info["col_fft_per_block"], info["row_fft_per_block"], info["layer_chunks"]) == \
+        (res["col_fft_per_block"], res["row_fft_per_block"], res["layer_chunks"])
+    tol = 1e-14 if dtype == torch.float64 else 1e-6
+    assert relerr(host(op.matvec(dev(x, dtype))), y0) <= tol
+    assert np.array_equal(host(op.rmatvec(dev(v, dtype))), z0)
+    op.close()
+
+
 @pytest.mark.parametrize("g", [synth.MID, synth.SUB])
 def test_timing_with_repeats_leaves_results_unchanged(pk, g):
     # power-of-two (register FFT) and radix-3 (generic) paths

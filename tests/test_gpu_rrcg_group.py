@@ -118,12 +118,17 @@ def test_group_equals_one_inversion_solvers_and_graphs(pk):
     eager.close()
 
 
-def test_group_launch_shape_recaptures(pk):
+@pytest.mark.parametrize("how", ["set_launch", "autotune"])
+def test_group_launch_shape_recaptures(pk, how):
     grp, _ = build_group(pk, torch.float64)
     ref, _ = build_group(pk, torch.float64)
-    grp.set_launch(model_row_threads=64, data_row_threads=64, col_threads=64, layer_chunks=2)
-    info = grp.launch_info()
-    assert (info["model_row_threads"], info["col_threads"], info["layer_chunks"]) == (64, 64, 2)
+    if how == "set_launch":
+        grp.set_launch(model_row_threads=64, data_row_threads=64, col_threads=64, layer_chunks=2)
+        info = grp.launch_info()
+        assert (info["model_row_threads"], info["col_threads"], info["layer_chunks"]) == (64, 64, 2)
+    else:
+        res = grp.autotune(reps=2)
+        assert res["col_threads"] == grp.launch_info()["col_threads"]
     grp.step(N_INNER)
     ref.step(N_INNER)
     for i in range(len(grp)):
