@@ -204,6 +204,12 @@ typedef struct {
 BTTB_API int bttb_group_info(bttb_group g, bttb_group_desc* out);
 BTTB_API int bttb_group_destroy(bttb_group g);
 
+/* Event timing of a group's launches, as bttb_timing_enable / bttb_timing_read for a plan
+ * (kernel ids as there; each id covers every member of the launch).  Launches captured
+ * into a graph are not timed. */
+BTTB_API int bttb_group_timing_enable(bttb_group g, int max_launches, int repeat);
+BTTB_API int bttb_group_timing_read(bttb_group g, double* total_ms, int* count);
+
 /* ---------------------------------------------------------------------------------- */
 /* Launch-shape autotuning                                                              */
 /* ---------------------------------------------------------------------------------- */
@@ -290,7 +296,9 @@ typedef struct {
 
 /* Create a solver for one inversion: the scalars start at alpha = alpha0, no previous
  * gradient, k = 0, and resid / Phi / S_G are computed from the given m.  Allocates the
- * solver's own work vectors.  Synchronises `stream`. */
+ * solver's own work vectors.  When both plans have power-of-two transforms the solver runs
+ * as a one-inversion group solver (rrcg_group_create): both operators' products share each
+ * launch and the CG pieces ride on their row transforms.  Synchronises `stream`. */
 BTTB_API int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out);
 
 /* One outer step: n_inner >= 1 CG steps at the outer step's W and alpha (RRCG:1-7, the
@@ -307,6 +315,10 @@ BTTB_API int rrcg_write_scalars(rrcg_handle h, const rrcg_scalars* in, void* str
 /* Recompute resid, Phi and S_G of the current m, e.g. after m was written to resume
  * from a checkpoint (with rrcg_write_scalars for the scalar state). */
 BTTB_API int rrcg_refresh(rrcg_handle h, void* stream);
+
+/* The product group of a solver on power-of-two plans (owned by the solver), for
+ * inspection and timing; BTTB_ESTATE for other plans. */
+BTTB_API int rrcg_products(rrcg_handle h, bttb_group* out);
 
 BTTB_API int rrcg_destroy(rrcg_handle h);
 

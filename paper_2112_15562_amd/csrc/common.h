@@ -72,30 +72,23 @@ struct Plan {
   int* t_kid;        // [t_cap]
 };
 
-// Arguments of the fused forms of the row transforms (rrcg_fuse.h).
-template <typename T>
-struct Fuse;
-
 // Power-of-two path (operator_fast.hip).
 size_t fast_row_lds(int N, size_t esz, int G);
 size_t fast_col_lds(int N, size_t esz, int G, bool fwd);
 template <typename T>
 int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L, int nrows,
-                 int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s,
-                 const Fuse<T>* fz = nullptr);
+                 int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s);
 template <typename T>
 int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
                  const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
-                 hipStream_t s, const Fuse<T>* fz = nullptr);
+                 hipStream_t s);
 template <typename T>
 int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs,
              long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
              const cx<T>* tw, int batch, hipStream_t s);
 
-// fz (power-of-two plans only): the CG step's fused forms -- forward: direction update in the
-// first row pass and ||q||^2 in the last; transpose: the gradient in the last row pass.
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,
-               const T* winv, const T* wd, hipStream_t s, const Fuse<T>* fz = nullptr);
+               const T* winv, const T* wd, hipStream_t s);
 
 }  // namespace bttb

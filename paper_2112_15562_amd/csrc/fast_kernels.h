@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "fft_reg.h"
 #include "rrcg_fuse.h"
@@ -171,9 +173,9 @@ __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
                                     gridDim.x * gridDim.y, smem_raw);
 }
 
-// ROWIN = false: half spectra read column-major in[c][l][k2][row] (ld = padded rows), summed over
-// nsum partials, through an LDS transpose; ROWIN = true: row-major in[l][row][k2] (ld = padded
-// K2, nsum = 1) read straight into the strided layout.
+// ROWIN = false: half spectra read column-major in[l][k2][row] (ld = padded rows, nsum = 1)
+// through an LDS transpose; ROWIN = true: row-major in[c][l][row][k2] (ld = padded K2) summed
+// over the nsum partials, read straight into the strided layout.
 // MODE = FUSE_QQ (ROWIN = true, the forward product inside the CG step): block partials of
 // ||q||^2 for the output q (for the step length of RRCG:6).
 // MODE = FUSE_GRAD (ROWIN = false, the transpose product inside the CG step): the output is the
@@ -231,27 +233,26 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
                         : cx<T>{ha[i].re + hb[i].im, hb[i].re - ha[i].im};
     }
   } else {
-    // `in` is complex [nsum][L][K2][ld], summed over the nsum partials
+    // `in` is complex [L][K2][ld] (nsum = 1).  Each thread loads its ITER values first, then
+    // stages them in LDS, so the loads are in flight together.
+    constexpr int ITER = (2 * K2 + TPF - 1) / TPF;  // >= K2 * RT / blockDim, blockDim = RT * TPF / 2
     const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + (long long)l * K2 * a.ld + tile * RT;
-    for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
+    const int rows = min(RT, a.nrows - tile * RT);
+    cx<T> hv[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
       const int k2 = idx / RT, rr = idx - k2 * RT;
-      const int row = tile * RT + rr;
-      cx<T> hv{T(0), T(0)};
-      if (row < a.nrows) {
-        if (a.nsum == 1) {
-          hv = src[(long long)k2 * a.ld + rr];
-        } else {
-          double hr = 0.0, hi = 0.0;
-          for (int c = 0; c < a.nsum; ++c) {
-            const cx<T> u = src[c * a.in_cs + (long long)k2 * a.ld + rr];
-            hr += (double)u.re;
-            hi += (double)u.im;
-          }
-          hv = cx<T>{(T)hr, (T)hi};
-        }
+      hv[it] = (idx < K2 * RT && rr < rows) ? src[(long long)k2 * a.ld + rr] : cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = threadIdx.x + it * blockDim.x;
+      const int k2 = idx / RT, rr = idx - k2 * RT;
+      if (idx < K2 * RT) {
+        if (k2 == 0 || k2 == K2 - 1) hv[it].im = T(0);  // DC and Nyquist of a real row are real
+        smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv[it];
       }
-      if (k2 == 0 || k2 == K2 - 1) hv.im = T(0);  // DC and Nyquist of a real row are real
-      smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv;
     }
     __syncthreads();
 #pragma unroll
@@ -345,14 +346,30 @@ struct FColArgs {
 // stay Hermitian, so the inverse of S0 + i SN returns s0 in its real and sN in its
 // imaginary part.  This gives Py/2 equal jobs.
 
+// Accumulator of the forward layer sum: the plan's type (the sum is part of the product,
+// whose FFTs and multiplies run in that type), or FP64 when built with BTTB_LAYER_SUM_F64=1.
+#ifndef BTTB_LAYER_SUM_F64
+#define BTTB_LAYER_SUM_F64 0
+#endif
+template <typename T>
+struct LayerAcc {
+  using type = typename std::conditional<BTTB_LAYER_SUM_F64 != 0, double, T>::type;
+};
+template <typename A>
+struct AccPair {
+  A x, y;
+};
+
 // Layer loop of the forward column pass for one group: acc += eig_l . FFT_x(column_l)
 // (PACKED: eig0 . X0 + i eigN . XN from the packed pair of real columns).  The next
 // layer's eigenvalues (and in FP32 its column) are loaded while the current one is
 // transformed; FP64 keeps the column load in place to stay within 256 registers.
 template <typename T, int N, bool PACKED>
 __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
-                                           int G, int k2, int l0, int l1, int b, double (&ar)[8],
-                                           double (&ai)[8]) {
+                                           int G, int k2, int l0, int l1, int b,
+                                           typename LayerAcc<T>::type (&ar)[8],
+                                           typename LayerAcc<T>::type (&ai)[8]) {
+  using Acc = typename LayerAcc<T>::type;
   constexpr int TPF = N / 8;
   constexpr bool PF_IN = sizeof(T) == 4;
   GroupSync<TPF> gsync;
@@ -400,12 +417,13 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
       for (int i = 0; i < 8; ++i) {
         const int k = t + i * TPF;
         const cx<T> A = v[i], C = buf[lds_pad((N - k) & (N - 1))];
-        const double x0r = 0.5 * ((double)A.re + C.re), x0i = 0.5 * ((double)A.im - C.im);
-        const double xnr = 0.5 * ((double)A.im + C.im), xni = 0.5 * ((double)C.re - A.re);
-        const double pr = (double)e[i].re * x0r - (double)e[i].im * x0i;
-        const double pi = (double)e[i].re * x0i + (double)e[i].im * x0r;
-        const double qr = (double)eN[i].re * xnr - (double)eN[i].im * xni;
-        const double qi = (double)eN[i].re * xni + (double)eN[i].im * xnr;
+        const Acc h = Acc(0.5);
+        const Acc x0r = h * ((Acc)A.re + C.re), x0i = h * ((Acc)A.im - C.im);
+        const Acc xnr = h * ((Acc)A.im + C.im), xni = h * ((Acc)C.re - A.re);
+        const Acc pr = (Acc)e[i].re * x0r - (Acc)e[i].im * x0i;
+        const Acc pi = (Acc)e[i].re * x0i + (Acc)e[i].im * x0r;
+        const Acc qr = (Acc)eN[i].re * xnr - (Acc)eN[i].im * xni;
+        const Acc qi = (Acc)eN[i].re * xni + (Acc)eN[i].im * xnr;
         if (act) {
           ar[i] += pr - qi;
           ai[i] += pi + qr;
@@ -415,7 +433,7 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
     } else if (act) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const double xr = v[i].re, xi = v[i].im, wr = e[i].re, wi = e[i].im;
+        const Acc xr = v[i].re, xi = v[i].im, wr = e[i].re, wi = e[i].im;
         ar[i] += wr * xr - wi * xi;
         ai[i] += wr * xi + wi * xr;
       }
@@ -444,24 +462,25 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
   F.init(a.tw, t);
-  double ar[8], ai[8];
+  using Acc = typename LayerAcc<T>::type;
+  Acc ar[8], ai[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) ar[i] = ai[i] = 0.0;
+  for (int i = 0; i < 8; ++i) ar[i] = ai[i] = Acc(0);
   if (packed) fwd_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
   else fwd_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
   // tree reduction of the groups' accumulators (G is a power of two)
-  double2* red = reinterpret_cast<double2*>(smem_raw);
+  AccPair<Acc>* red = reinterpret_cast<AccPair<Acc>*>(smem_raw);
   for (int half = G >> 1; half >= 1; half >>= 1) {
     __syncthreads();
     if (f >= half && f < 2 * half) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) red[(f - half) * N + t + i * TPF] = make_double2(ar[i], ai[i]);
+      for (int i = 0; i < 8; ++i) red[(f - half) * N + t + i * TPF] = AccPair<Acc>{ar[i], ai[i]};
     }
     __syncthreads();
     if (f < half) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const double2 u = red[f * N + t + i * TPF];
+        const AccPair<Acc> u = red[f * N + t + i * TPF];
         ar[i] += u.x;
         ai[i] += u.y;
       }

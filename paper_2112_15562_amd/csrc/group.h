@@ -23,7 +23,7 @@ struct GMember {
   long long V_fcs;  // elements between layer-chunk partials of the data spectrum
 };
 
-// Arguments of one group launch (by value).
+// Arguments of one group launch (by value): the members of one transform size.
 template <typename T>
 struct GLaunch {
   const GMember<T>* mem;
@@ -33,9 +33,20 @@ struct GLaunch {
   const T* const* winv;  // nullable arrays; entries nullable
   const T* const* wd;
   int bt;                // threads per block
-  int count;
-  int start[GMAX + 1];   // first block of each member; start[count] = blocks of the launch
+  int count;             // members in this launch
+  int idx[GMAX];         // their indices in the group
+  int start[GMAX + 1];   // first block of each; start[count] = blocks of the launch
 };
+
+// The members of one stage that share a transform size (one launch).
+struct GClass {
+  int N, count;
+  int idx[GMAX];
+  int start[GMAX + 1];
+  size_t lds;
+};
+
+constexpr int GSIZES = 7;  // transform sizes 32 .. 2048
 
 struct Group {
   int count, precision;
@@ -44,8 +55,14 @@ struct Group {
   int bt_rm, bt_rd, bt_c;  // threads per block: model rows (F1, T3), data rows (F3, T1), columns
   int nchunk;              // layer chunks requested for the forward column pass
   int nch[GMAX];           // per member, bounded by its plan
-  int start[GS_COUNT][GMAX + 1];
-  size_t lds[GS_COUNT];
+  int blocks[GS_COUNT];              // blocks of each stage over all its launches
+  GClass cls[GS_COUNT][GSIZES];      // per stage: one launch per transform size present
+  int ncls[GS_COUNT];
+  // optional per-launch event timing (as for plans)
+  int t_cap, t_used, t_repeat;
+  int t_suspend;  // > 0 while launches are being captured into a graph
+  hipEvent_t* t_ev;
+  int* t_kid;
 };
 
 int group_create(const bttb_plan* plans, int count, void* stream, Group** out);

@@ -1,13 +1,14 @@
 // Group products: the forward or transpose products of many plans (members: the gravity
 // and magnetic operators of many inversions, of uneven sizes) in one launch per stage.
 //
-// Each stage (row transform, column pass, inverse row transform; Sec. 2.7.1) is one
-// launch over the concatenated blocks of all members.  A block finds its member in the
+// Each stage (row transform, column pass, inverse row transform; Sec. 2.7.1) runs over the
+// concatenated blocks of all members.  A block finds its member in the
 // launch's prefix table of first blocks, builds that member's stage arguments from the
-// member table, and runs the register-FFT body for the member's transform size; every
-// member uses its own plan's eigenvalues and scratch.  All blocks of a launch have the
-// same thread count, so a member of transform size N runs (threads / (N / 8)) FFTs per
-// block.  The per-call vectors come from device arrays of pointers, so a group product
+// member table, and runs the register-FFT body; every member uses its own plan's
+// eigenvalues and scratch.  A stage is one launch per transform size present (so each
+// kernel is compiled for one size and keeps that size's register budget).  All blocks of a
+// stage have the same thread count, so a member of transform size N runs
+// (threads / (N / 8)) FFTs per block.  The per-call vectors come from device arrays of pointers, so a group product
 // can be captured in a HIP graph and replayed with new data in the same buffers.
 #include <hip/hip_runtime.h>
 
@@ -26,34 +27,23 @@ __device__ __forceinline__ int group_member(const int* start, int count, int blk
   return i;
 }
 
-// Sizes a group kernel is compiled for.
-#define BTTB_GROUP_SWITCH(N, CALL) \
-  switch (N) {                     \
-    case 32: CALL(32); break;      \
-    case 64: CALL(64); break;      \
-    case 128: CALL(128); break;    \
-    case 256: CALL(256); break;    \
-    case 512: CALL(512); break;    \
-    case 1024: CALL(1024); break;  \
-    case 2048: CALL(2048); break;  \
-    default: break;                \
-  }
-
-template <typename T>
+template <typename T, int MODE>
 __device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
-  if (g.fz) return g.fz[i];
+  if constexpr (MODE != FUSE_NONE) return g.fz[i];
   return Fuse<T>{};
 }
 
-// Row transform R2C.  ROWOUT = false: model rows into U (forward, first stage);
-// ROWOUT = true: data rows into V (transpose, first stage).
-template <typename T, bool ROWOUT, int MODE>
+// Row transform R2C of transform size N.  ROWOUT = false: model rows into U (forward, first
+// stage); ROWOUT = true: data rows into V (transpose, first stage).
+template <typename T, int N, bool ROWOUT, int MODE>
 __global__ void __launch_bounds__(512) k_grow_r2c(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = group_member(g.start, g.count, blockIdx.x);
+  const int k = group_member(g.start, g.count, blockIdx.x);
+  const int i = g.idx[k];
   const GMember<T>& M = g.mem[i];
-  const int local = blockIdx.x - g.start[i], nb = g.start[i + 1] - g.start[i];
-  const int G = g.bt / (M.Py / 8);
+  const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
+  constexpr int G1 = N / 8;
+  const int G = g.bt / G1;
   const T* in = g.in[i];
   FRowArgs<T> a;
   if constexpr (!ROWOUT) {
@@ -63,21 +53,20 @@ __global__ void __launch_bounds__(512) k_grow_r2c(GLaunch<T> g) {
     a = FRowArgs<T>{in, 0, g.wd ? g.wd[i] : nullptr, M.V, 0, 0, 1, 1, M.sx, M.sy, M.ldk, M.K2, G,
                     (M.sx + 2 * G - 1) / (2 * G), M.twy};
   }
-  const Fuse<T> fz = member_fuse(g, i);
-#define BTTB_B(NN) frow_r2c_body<T, NN, ROWOUT, MODE>(a, fz, local, 0, local, nb, smem_raw)
-  BTTB_GROUP_SWITCH(M.Py, BTTB_B)
-#undef BTTB_B
+  const Fuse<T> fz = member_fuse<T, MODE>(g, i);
+  frow_r2c_body<T, N, ROWOUT, MODE>(a, fz, local, 0, local, nb, smem_raw);
 }
 
-// Inverse row transform C2R.  ROWIN = true: data rows from V (forward, last stage, sums
-// the layer-chunk partials); ROWIN = false: model rows from U (transpose, last stage).
-template <typename T, bool ROWIN, int MODE>
+// Inverse row transform C2R of size N.  ROWIN = true: data rows from V (forward, last
+// stage, sums the layer-chunk partials); ROWIN = false: model rows from U (transpose, last).
+template <typename T, int N, bool ROWIN, int MODE>
 __global__ void __launch_bounds__(512) k_grow_c2r(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = group_member(g.start, g.count, blockIdx.x);
+  const int k = group_member(g.start, g.count, blockIdx.x);
+  const int i = g.idx[k];
   const GMember<T>& M = g.mem[i];
-  const int local = blockIdx.x - g.start[i], nb = g.start[i + 1] - g.start[i];
-  const int G = g.bt / (M.Py / 8);
+  const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
+  const int G = g.bt / (N / 8);
   T* out = g.out[i];
   FRowArgs<T> a;
   if constexpr (ROWIN) {
@@ -88,37 +77,28 @@ __global__ void __launch_bounds__(512) k_grow_c2r(GLaunch<T> g) {
                     reinterpret_cast<cx<T>*>(out), 0, 0, 1, M.nz, M.nx, M.ny, M.ldx, M.K2, G,
                     (M.nx + 2 * G - 1) / (2 * G), M.twy};
   }
-  const Fuse<T> fz = member_fuse(g, i);
-#define BTTB_B(NN) frow_c2r_body<T, NN, ROWIN, MODE>(a, fz, local, 0, local, nb, smem_raw)
-  BTTB_GROUP_SWITCH(M.Py, BTTB_B)
-#undef BTTB_B
+  const Fuse<T> fz = member_fuse<T, MODE>(g, i);
+  frow_c2r_body<T, N, ROWIN, MODE>(a, fz, local, 0, local, nb, smem_raw);
 }
 
-// Column pass: forward (eigenvalue multiply and layer sum into V partials) or transpose
-// (conjugate eigenvalue multiply per layer into U).
-template <typename T, bool FWD>
+// Column pass of size N: forward (eigenvalue multiply and layer sum into V partials) or
+// transpose (conjugate eigenvalue multiply per layer into U).
+template <typename T, int N, bool FWD>
 __global__ void __launch_bounds__(col_threads(sizeof(T))) k_gcol(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = group_member(g.start, g.count, blockIdx.x);
+  const int k = group_member(g.start, g.count, blockIdx.x);
+  const int i = g.idx[k];
   const GMember<T>& M = g.mem[i];
-  const int local = blockIdx.x - g.start[i];
+  const int local = blockIdx.x - g.start[k];
   const int jobs = M.K2 - 1;
   const int c = local / jobs, job = local - c * jobs;
-  const int G = g.bt / (M.Px / 8);
-  FColArgs<T> a;
+  const int G = g.bt / (N / 8);
   if constexpr (FWD) {
-    a = FColArgs<T>{M.U, 0, M.eig, M.V, 0, M.V_fcs, M.nz, M.nx, M.sx, M.ldx, M.ldk, M.K2, G, M.nchunk, M.twx};
+    const FColArgs<T> a{M.U, 0, M.eig, M.V, 0, M.V_fcs, M.nz, M.nx, M.sx, M.ldx, M.ldk, M.K2, G, M.nchunk, M.twx};
+    fcol_fwd_body<T, N>(a, job, c, 0, smem_raw);
   } else {
-    a = FColArgs<T>{M.V, 0, M.eig, M.U, 0, 0, M.nz, M.sx, M.nx, M.ldk, M.ldx, M.K2, G, M.nchunk, M.twx};
-  }
-  if constexpr (FWD) {
-#define BTTB_B(NN) fcol_fwd_body<T, NN>(a, job, c, 0, smem_raw)
-    BTTB_GROUP_SWITCH(M.Px, BTTB_B)
-#undef BTTB_B
-  } else {
-#define BTTB_B(NN) fcol_adj_body<T, NN>(a, job, c, 0, smem_raw)
-    BTTB_GROUP_SWITCH(M.Px, BTTB_B)
-#undef BTTB_B
+    const FColArgs<T> a{M.V, 0, M.eig, M.U, 0, 0, M.nz, M.sx, M.nx, M.ldk, M.ldx, M.K2, G, M.nchunk, M.twx};
+    fcol_adj_body<T, N>(a, job, c, 0, smem_raw);
   }
 }
 
@@ -135,12 +115,13 @@ static int stage_threads(const Group* g, int st) {
   }
 }
 
-// Block counts and LDS of every stage for the current launch shape.
+// Block counts and LDS of every stage for the current launch shape; each stage is split into
+// one launch per transform size present (rows: Py, columns: Px).
 static int layout(Group* g) {
   const size_t esz = g->precision == BTTB_F64 ? 8 : 4;
   for (int st = 0; st < GS_COUNT; ++st) {
-    g->start[st][0] = 0;
-    g->lds[st] = 0;
+    g->ncls[st] = 0;
+    g->blocks[st] = 0;
   }
   for (int i = 0; i < g->count; ++i) {
     const Plan* P = g->P[i];
@@ -161,14 +142,28 @@ static int layout(Group* g) {
         fast_row_lds(P->Py, esz, Grm), fast_col_lds(P->Px, esz, Gc, true), fast_row_lds(P->Py, esz, Grd),
         fast_row_lds(P->Py, esz, Grd), fast_col_lds(P->Px, esz, Gc, false), fast_row_lds(P->Py, esz, Grm)};
     for (int st = 0; st < GS_COUNT; ++st) {
-      const long long nx = g->start[st][i] + b[st];
-      if (nx > (1LL << 30)) return fail(BTTB_ESIZE, "group: too many blocks");
-      g->start[st][i + 1] = (int)nx;
-      g->lds[st] = std::max(g->lds[st], l[st]);
+      const int N = (st == GS_F2 || st == GS_T2) ? P->Px : P->Py;
+      int c = 0;
+      while (c < g->ncls[st] && g->cls[st][c].N != N) ++c;
+      GClass& C = g->cls[st][c];
+      if (c == g->ncls[st]) {
+        if (c == GSIZES) return fail(BTTB_EINVAL, "group: too many transform sizes");
+        g->ncls[st] += 1;
+        C.N = N;
+        C.count = 0;
+        C.start[0] = 0;
+        C.lds = 0;
+      }
+      const long long nb = C.start[C.count] + b[st];
+      if (nb > (1LL << 30)) return fail(BTTB_ESIZE, "group: too many blocks");
+      C.idx[C.count] = i;
+      C.start[C.count + 1] = (int)nb;
+      C.count += 1;
+      C.lds = std::max(C.lds, l[st]);
+      if (C.lds > 160 * 1024) return fail(BTTB_EINVAL, "group: launch shape needs more LDS than a CU has");
+      g->blocks[st] += (int)b[st];
     }
   }
-  for (int st = 0; st < GS_COUNT; ++st)
-    if (g->lds[st] > 160 * 1024) return fail(BTTB_EINVAL, "group: launch shape needs more LDS than a CU has");
   return BTTB_OK;
 }
 
@@ -200,8 +195,8 @@ static int check_threads(const Group* g, int rm, int rd, int c) {
 }
 
 template <typename T>
-static GLaunch<T> launch_of(const Group* g, int st, const Fuse<T>* fz, const void* const* in, void* const* out,
-                            const void* const* winv, const void* const* wd) {
+static GLaunch<T> launch_of(const Group* g, int st, const GClass& C, const Fuse<T>* fz, const void* const* in,
+                            void* const* out, const void* const* winv, const void* const* wd) {
   GLaunch<T> L{};
   L.mem = static_cast<const GMember<T>*>(g->mem);
   L.fz = fz;
@@ -210,37 +205,74 @@ static GLaunch<T> launch_of(const Group* g, int st, const Fuse<T>* fz, const voi
   L.winv = reinterpret_cast<const T* const*>(winv);
   L.wd = reinterpret_cast<const T* const*>(wd);
   L.bt = stage_threads(g, st);
-  L.count = g->count;
-  for (int i = 0; i <= g->count; ++i) L.start[i] = g->start[st][i];
+  L.count = C.count;
+  for (int i = 0; i < C.count; ++i) L.idx[i] = C.idx[i];
+  for (int i = 0; i <= C.count; ++i) L.start[i] = C.start[i];
   return L;
 }
 
+#define BTTB_GROUP_SIZES(N, CALL) \
+  switch (N) {                    \
+    case 32: CALL(32); break;     \
+    case 64: CALL(64); break;     \
+    case 128: CALL(128); break;   \
+    case 256: CALL(256); break;   \
+    case 512: CALL(512); break;   \
+    case 1024: CALL(1024); break; \
+    case 2048: CALL(2048); break; \
+    default: return fail(BTTB_ESIZE, "group: transform size out of range"); \
+  }
+
+// The kernel of stage st at transform size N (in the CG step's fused form when fused).
+template <typename T, int N>
+static auto stage_kernel(int st, bool fused) -> void (*)(GLaunch<T>) {
+  switch (st) {
+    case GS_F1: return fused ? k_grow_r2c<T, N, false, FUSE_DIR> : k_grow_r2c<T, N, false, FUSE_NONE>;
+    case GS_F2: return k_gcol<T, N, true>;
+    case GS_F3: return fused ? k_grow_c2r<T, N, true, FUSE_QQ> : k_grow_c2r<T, N, true, FUSE_NONE>;
+    case GS_T1: return k_grow_r2c<T, N, true, FUSE_NONE>;
+    case GS_T2: return k_gcol<T, N, false>;
+    default: return fused ? k_grow_c2r<T, N, false, FUSE_GRAD> : k_grow_c2r<T, N, false, FUSE_NONE>;
+  }
+}
+
 template <typename T>
-int group_apply_impl(const Group* g, int op, const void* const* in, void* const* out, const void* const* winv,
+int group_apply_impl(const Group* g_, int op, const void* const* in, void* const* out, const void* const* winv,
                      const void* const* wd, const Fuse<T>* fz, hipStream_t s) {
-  auto run = [&](int st, auto kernel) -> int {
-    const GLaunch<T> L = launch_of<T>(g, st, fz, in, out, winv, wd);
-    const int nb = g->start[st][g->count];
-    if (nb == 0) return BTTB_OK;
-    hipLaunchKernelGGL(kernel, dim3(nb), dim3(L.bt), g->lds[st], s, L);
-    BTTB_LAUNCHED("group stage");
+  Group* g = const_cast<Group*>(g_);  // timing state only
+  auto run = [&](int st) -> int {
+    if (g->blocks[st] == 0) return BTTB_OK;
+    int tk = -1;
+    if (g->t_ev && g->t_suspend == 0 && g->t_used < g->t_cap) {
+      tk = g->t_used++;
+      g->t_kid[tk] = st;
+      (void)hipEventRecord(g->t_ev[2 * tk], s);
+    }
+    const int reps = tk >= 0 ? g->t_repeat : 1;  // every stage reads one buffer and writes another
+    for (int r = 0; r < reps; ++r) {
+      for (int c = 0; c < g->ncls[st]; ++c) {
+        const GClass& C = g->cls[st][c];
+        const GLaunch<T> L = launch_of<T>(g, st, C, fz, in, out, winv, wd);
+        void (*kern)(GLaunch<T>) = nullptr;
+#define BTTB_K(NN) kern = stage_kernel<T, NN>(st, fz != nullptr)
+        BTTB_GROUP_SIZES(C.N, BTTB_K)
+#undef BTTB_K
+        hipLaunchKernelGGL(kern, dim3(C.start[C.count]), dim3(L.bt), C.lds, s, L);
+        BTTB_LAUNCHED("group stage");
+      }
+    }
+    if (tk >= 0) (void)hipEventRecord(g->t_ev[2 * tk + 1], s);
     return BTTB_OK;
   };
   int rc;
   if (op == BTTB_OP_FORWARD) {
-    if (fz) {
-      rc = run(GS_F1, k_grow_r2c<T, false, FUSE_DIR>);
-      if (!rc) rc = run(GS_F2, k_gcol<T, true>);
-      if (!rc) rc = run(GS_F3, k_grow_c2r<T, true, FUSE_QQ>);
-    } else {
-      rc = run(GS_F1, k_grow_r2c<T, false, FUSE_NONE>);
-      if (!rc) rc = run(GS_F2, k_gcol<T, true>);
-      if (!rc) rc = run(GS_F3, k_grow_c2r<T, true, FUSE_NONE>);
-    }
+    rc = run(GS_F1);
+    if (!rc) rc = run(GS_F2);
+    if (!rc) rc = run(GS_F3);
   } else {
-    rc = run(GS_T1, k_grow_r2c<T, true, FUSE_NONE>);
-    if (!rc) rc = run(GS_T2, k_gcol<T, false>);
-    if (!rc) rc = fz ? run(GS_T3, k_grow_c2r<T, false, FUSE_GRAD>) : run(GS_T3, k_grow_c2r<T, false, FUSE_NONE>);
+    rc = run(GS_T1);
+    if (!rc) rc = run(GS_T2);
+    if (!rc) rc = run(GS_T3);
   }
   return rc;
 }
@@ -324,10 +356,44 @@ int group_create(const bttb_plan* plans, int count, void* stream, Group** out) {
   return BTTB_OK;
 }
 
+static void group_timing_free(Group* g) {
+  if (g->t_ev) {
+    for (int i = 0; i < 2 * g->t_cap; ++i)
+      if (g->t_ev[i]) (void)hipEventDestroy(g->t_ev[i]);
+  }
+  delete[] g->t_ev;
+  delete[] g->t_kid;
+  g->t_ev = nullptr;
+  g->t_kid = nullptr;
+  g->t_cap = g->t_used = 0;
+}
+
 void group_destroy(Group* g) {
   if (!g) return;
+  group_timing_free(g);
   dfree(g->mem);
   delete g;
+}
+
+int group_timing_enable(Group* g, int max_launches, int repeat) {
+  if (max_launches < 0 || repeat < 1 || repeat > 1000) return fail(BTTB_EINVAL, "group timing: bad argument");
+  group_timing_free(g);
+  g->t_repeat = repeat;
+  if (max_launches == 0) return BTTB_OK;
+  g->t_ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches]();
+  g->t_kid = new (std::nothrow) int[max_launches];
+  if (!g->t_ev || !g->t_kid) {
+    group_timing_free(g);
+    return fail(BTTB_ENOMEM, "group timing: host allocation failed");
+  }
+  g->t_cap = max_launches;
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    if (hipEventCreate(&g->t_ev[i]) != hipSuccess) {
+      group_timing_free(g);
+      return fail(BTTB_EHIP, "group timing: hipEventCreate");
+    }
+  }
+  return BTTB_OK;
 }
 
 }  // namespace bttb
@@ -371,7 +437,31 @@ extern "C" int bttb_group_info(bttb_group gg, bttb_group_desc* out) {
   out->data_row_threads = g->bt_rd;
   out->col_threads = g->bt_c;
   out->layer_chunks = g->nchunk;
-  for (int st = 0; st < GS_COUNT; ++st) out->blocks[st] = g->start[st][g->count];
+  for (int st = 0; st < GS_COUNT; ++st) out->blocks[st] = g->blocks[st];
+  return BTTB_OK;
+}
+
+extern "C" int bttb_group_timing_enable(bttb_group gg, int max_launches, int repeat) {
+  Group* g = reinterpret_cast<Group*>(gg);
+  if (!g) return fail(BTTB_EINVAL, "bttb_group_timing_enable: NULL group");
+  return group_timing_enable(g, max_launches, repeat);
+}
+
+extern "C" int bttb_group_timing_read(bttb_group gg, double* total_ms, int* count) {
+  Group* g = reinterpret_cast<Group*>(gg);
+  if (!g || !total_ms || !count) return fail(BTTB_EINVAL, "bttb_group_timing_read: NULL argument");
+  for (int k = 0; k < BTTB_NKERNELS; ++k) {
+    total_ms[k] = 0.0;
+    count[k] = 0;
+  }
+  for (int i = 0; i < g->t_used; ++i) {
+    BTTB_HIP(hipEventSynchronize(g->t_ev[2 * i + 1]));
+    float ms = 0.0f;
+    BTTB_HIP(hipEventElapsedTime(&ms, g->t_ev[2 * i], g->t_ev[2 * i + 1]));
+    total_ms[g->t_kid[i]] += ms;
+    count[g->t_kid[i]] += g->t_repeat;
+  }
+  g->t_used = 0;
   return BTTB_OK;
 }
 

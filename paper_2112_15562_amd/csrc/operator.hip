@@ -446,8 +446,7 @@ static int small_row_groups(const Plan* P, int nrows, int batch) {
 
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,
-               const T* winv, const T* wd, hipStream_t s, const Fuse<T>* fz) {
-  if (fz && (!P->fast || batch != 1)) return fail(BTTB_EINVAL, "apply: fused CG forms need a power-of-two plan");
+               const T* winv, const T* wd, hipStream_t s) {
   const cx<T>* eig = static_cast<const cx<T>*>(P->eig);
   const cx<T>* twx = static_cast<const cx<T>*>(P->twx);
   const cx<T>* twy = static_cast<const cx<T>*>(P->twy);
@@ -479,7 +478,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
       if (op == BTTB_OP_FORWARD) {
         rc = stage(KT_FWD_ROW, [&]() -> int {
           return fast_row_r2c<T>(false, x, in_stride, winv, U, U_bs, P->nz, P->nx, P->ny, P->ldx, P->Py,
-                                 P->row_fpb, twy, nb, s, fz);
+                                 P->row_fpb, twy, nb, s);
         });
         if (rc) return rc;
         rc = stage(KT_FWD_COL, [&]() -> int {
@@ -489,7 +488,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
         if (rc) return rc;
         rc = stage(KT_FWD_INV, [&]() -> int {
           return fast_row_c2r<T>(true, V, V_bs, V_fcs, P->nchunk, y, out_stride, wd, 1, P->sx, P->sy, P->ldk,
-                                 P->Py, gs, twy, nb, s, fz);
+                                 P->Py, gs, twy, nb, s);
         });
         if (rc) return rc;
       } else {
@@ -504,7 +503,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
         if (rc) return rc;
         rc = stage(KT_ADJ_INV, [&]() -> int {
           return fast_row_c2r<T>(false, U, U_bs, 0, 1, y, out_stride, winv, P->nz, P->nx, P->ny, P->ldx, P->Py,
-                                 P->row_fpb, twy, nb, s, fz);
+                                 P->row_fpb, twy, nb, s);
         });
         if (rc) return rc;
       }
@@ -558,9 +557,9 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
 }
 
 template int apply_impl<float>(Plan*, int, int, const float*, long long, float*, long long, const float*,
-                               const float*, hipStream_t, const Fuse<float>*);
+                               const float*, hipStream_t);
 template int apply_impl<double>(Plan*, int, int, const double*, long long, double*, long long, const double*,
-                                const double*, hipStream_t, const Fuse<double>*);
+                                const double*, hipStream_t);
 
 // ------------------------------------------------------------------------------------
 // Launch shapes

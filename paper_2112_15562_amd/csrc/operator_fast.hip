@@ -1,12 +1,13 @@
-// Products for power-of-two transform sizes with the register-resident FFT (fft_reg.h).
+// Products for power-of-two transform sizes with the register-resident FFT (fft_reg.h):
+// the launchers of the one-plan kernels whose bodies are in fast_kernels.h.
 //
-// Same passes and intermediate layouts as the general kernels in operator.hip, with
-// three differences: (1) a transform's first pass reads global memory directly and its
-// last pass feeds the eigenvalue multiply, the layer accumulation and the stores from
-// registers; (2) the forward column pass gives each block one column k2 and splits the
-// layers over its groups, which reduce their FP64 accumulators in LDS, so one inverse
-// column transform per column is written (no layer-chunk partials); (3) exchanges
-// inside a transform use a wave-level barrier when the transform fits in one wave.
+// Same passes and intermediate layouts as the general kernels in operator.hip, with three
+// differences: (1) a transform's first pass reads global memory directly and its last pass
+// feeds the eigenvalue multiply, the layer accumulation and the stores from registers;
+// (2) the forward column pass gives each block one column job and splits the layers of its
+// layer chunk over the block's groups, which reduce their accumulators in LDS before one
+// inverse column transform per chunk; (3) exchanges inside a transform use a wave-level
+// barrier when the transform fits in one wave.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,19 +48,12 @@ size_t fast_col_lds(int N, size_t esz, int G, bool fwd) {
 
 template <typename T>
 int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T>* out, long long out_bs, int L,
-                 int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s,
-                 const Fuse<T>* fz) {
+                 int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch, hipStream_t s) {
   FRowArgs<T> a{in, in_bs, scale, out, out_bs, 0, 1, L, nrows, ncols, ld, N / 2 + 1, G, ceil_div(nrows, 2 * G), tw};
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
   const Fuse<T> f0{};
-  if (fz) {
-    if (rowout || batch != 1 || !scale || (long long)grid.x > fz->pbs)
-      return fail(BTTB_EINVAL, "fast_row_r2c: fused form needs one column-major launch of at most pbs blocks");
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, false, FUSE_DIR>), grid, block, sh, s, a, *fz)
-    BTTB_POW2_SWITCH(N, BTTB_L)
-#undef BTTB_L
-  } else if (rowout) {
+  if (rowout) {
 #define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, true, FUSE_NONE>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
@@ -75,23 +69,14 @@ int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T
 template <typename T>
 int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, int nsum, T* out, long long out_bs,
                  const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
-                 hipStream_t s, const Fuse<T>* fz) {
+                 hipStream_t s) {
   FRowArgs<T> a{reinterpret_cast<const T*>(in), in_bs, scale, reinterpret_cast<cx<T>*>(out), out_bs, in_cs,
                 nsum, L, nrows, ncols, ld, N / 2 + 1, G, ceil_div(nrows, 2 * G), tw};
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
   const Fuse<T> f0{};
-  if (fz && (batch != 1 || !scale || (long long)grid.x > fz->pbs))
-    return fail(BTTB_EINVAL, "fast_row_c2r: fused form needs one weighted launch of at most pbs blocks");
-  if (fz && rowin) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_QQ>), grid, block, sh, s, a, *fz)
-    BTTB_POW2_SWITCH(N, BTTB_L)
-#undef BTTB_L
-  } else if (fz) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, false, FUSE_GRAD>), grid, block, sh, s, a, *fz)
-    BTTB_POW2_SWITCH(N, BTTB_L)
-#undef BTTB_L
-  } else if (rowin) {
+  if (!rowin && nsum != 1) return fail(BTTB_EINVAL, "fast_row_c2r: column-major input takes no partial sums");
+  if (rowin) {
 #define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_NONE>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
@@ -126,14 +111,13 @@ int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>
 }
 
 template int fast_row_r2c<float>(bool, const float*, long long, const float*, cx<float>*, long long, int, int, int, int,
-                                 int, int, const cx<float>*, int, hipStream_t, const Fuse<float>*);
+                                 int, int, const cx<float>*, int, hipStream_t);
 template int fast_row_r2c<double>(bool, const double*, long long, const double*, cx<double>*, long long, int, int, int,
-                                  int, int, int, const cx<double>*, int, hipStream_t, const Fuse<double>*);
+                                  int, int, int, const cx<double>*, int, hipStream_t);
 template int fast_row_c2r<float>(bool, const cx<float>*, long long, long long, int, float*, long long, const float*, int,
-                                 int, int, int, int, int, const cx<float>*, int, hipStream_t, const Fuse<float>*);
+                                 int, int, int, int, int, const cx<float>*, int, hipStream_t);
 template int fast_row_c2r<double>(bool, const cx<double>*, long long, long long, int, double*, long long, const double*,
-                                  int, int, int, int, int, int, const cx<double>*, int, hipStream_t,
-                                  const Fuse<double>*);
+                                  int, int, int, int, int, int, const cx<double>*, int, hipStream_t);
 template int fast_col<float>(bool, const cx<float>*, long long, const cx<float>*, cx<float>*, long long, long long,
                              int, int, int, int, int, int, int, int, int, const cx<float>*, int, hipStream_t);
 template int fast_col<double>(bool, const cx<double>*, long long, const cx<double>*, cx<double>*, long long,

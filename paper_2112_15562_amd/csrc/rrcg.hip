@@ -45,7 +45,7 @@ struct Rrcg {
   const void* mapr[2];
   double lo[2], hi[2], alpha0[2], q[2], amin[2], lam[2], eps2;
   int coupled, restart, p_norm, gram_w;
-  int fused;       // both plans on the power-of-two path: CG pieces ride on the products
+  rrcg_group grp;  // power-of-two plans: the step runs as a one-inversion group solver
   void* m[2];      // caller-owned
   void* p[2];      // caller-owned
   void* rt[2];     // caller-owned
@@ -163,9 +163,8 @@ static int phase_weights(Rrcg* h, hipStream_t s) {
 }
 
 // One CG step (RRCG:2-7) at the outer step's W and alpha; restart_now sets beta = 0.
-// Power-of-two plans carry the gradient (RRCG:4), beta (RRCG:5), the direction update and the
-// step length (RRCG:6) inside the row transforms of the products; otherwise separate
-// elementwise kernels do the same arithmetic.
+// (Power-of-two plans do not come here: their solver is a one-inversion group solver, whose
+// products carry the gradient, direction and step-length sums in their row transforms.)
 template <typename T>
 static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
   T** m = reinterpret_cast<T**>(h->m);
@@ -178,40 +177,7 @@ static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
   const T* ma0 = static_cast<const T*>(h->mapr[0]);
   const T* ma1 = static_cast<const T*>(h->mapr[1]);
   const Red rd = red_of(h);
-  if (h->fused) {
-    Fuse<T> fz[2];
-    for (int i = 0; i < 2; ++i) {
-      Fuse<T>& f = fz[i];
-      f.self = i;
-      f.lead = i == 0;
-      f.restart = restart_now;
-      f.coupled = h->coupled;
-      f.gram_w = h->gram_w;
-      f.lam[0] = h->lam[0];
-      f.lam[1] = h->lam[1];
-      f.l = l[i];
-      f.p = p[i];
-      f.m[0] = m[0];
-      f.m[1] = m[1];
-      f.w[0] = w[0];
-      f.w[1] = w[1];
-      f.ma = static_cast<const T*>(h->mapr[i]);
-      f.sc = h->sc;
-      f.pb = h->pb;
-      f.pbn = h->pbn;
-      f.pbs = h->pbs;
-    }
-    for (int i = 0; i < 2; ++i) {
-      int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i],
-                             static_cast<const T*>(h->wd[i]), s, &fz[i]);
-      if (rc) return rc;
-    }
-    for (int i = 0; i < 2; ++i) {
-      int rc = apply_impl<T>(h->P[i], BTTB_OP_FORWARD, 1, p[i], 0, qv[i], 0, wi[i],
-                             static_cast<const T*>(h->wd[i]), s, &fz[i]);
-      if (rc) return rc;
-    }
-  } else {
+  {
     for (int i = 0; i < 2; ++i) {
       int rc = apply_impl<T>(h->P[i], BTTB_OP_ADJOINT, 1, rt[i], 0, l[i], 0, wi[i],
                              static_cast<const T*>(h->wd[i]), s);
@@ -284,6 +250,11 @@ static int build_graphs(Rrcg* h) {
 }
 
 static void free_rrcg(Rrcg* h) {
+  if (h->grp) {
+    (void)rrcg_group_destroy(h->grp);
+    delete h;
+    return;
+  }
   for (hipGraphExec_t g : {h->g_weights, h->g_inner_restart, h->g_inner, h->g_outer})
     if (g) (void)hipGraphExecDestroy(g);
   if (h->cap) (void)hipStreamDestroy(h->cap);
@@ -325,6 +296,16 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   if (d->p_norm != 1 && d->p_norm != 2) return fail(BTTB_EINVAL, "rrcg_create: p_norm must be 1 or 2");
   Rrcg* h = new (std::nothrow) Rrcg{};
   if (!h) return fail(BTTB_ENOMEM, "rrcg_create: host allocation failed");
+  if (P0->fast && P1->fast && P0->Px >= 32 && P0->Py >= 32) {
+    // both operators' products in one launch per stage, the CG pieces fused into them
+    const int rc = rrcg_group_create(d, 1, stream, &h->grp);
+    if (rc != BTTB_OK) {
+      delete h;
+      return rc;
+    }
+    *out = reinterpret_cast<rrcg_handle>(h);
+    return BTTB_OK;
+  }
   h->P[0] = P0;
   h->P[1] = P1;
   h->precision = P0->precision;
@@ -353,7 +334,6 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   // have (one row pair per block)
   const long long rows_blocks = (long long)P0->nz * ((P0->nx + 1) / 2);
   h->pbs = (int)std::max<long long>(RGRID, std::max<long long>(rows_blocks, (P0->sx + 1) / 2));
-  h->fused = P0->fast && P1->fast;
   ok = ok && hipMalloc((void**)&h->sc, S_COUNT * sizeof(double)) == hipSuccess &&
        hipMalloc((void**)&h->pb, (size_t)PB_NSLOT * h->pbs * sizeof(double)) == hipSuccess &&
        hipMalloc((void**)&h->pbn, PB_NSLOT * sizeof(int)) == hipSuccess;
@@ -393,6 +373,7 @@ extern "C" int rrcg_step(rrcg_handle hh, int n_inner, void* stream) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h) return fail(BTTB_EINVAL, "rrcg_step: NULL handle");
   if (n_inner < 1) return fail(BTTB_EINVAL, "rrcg_step: n_inner must be >= 1");
+  if (h->grp) return rrcg_group_step(h->grp, n_inner, stream);
   hipStream_t s = static_cast<hipStream_t>(stream);
   return h->precision == BTTB_F64 ? step_impl<double>(h, n_inner, s) : step_impl<float>(h, n_inner, s);
 }
@@ -400,6 +381,7 @@ extern "C" int rrcg_step(rrcg_handle hh, int n_inner, void* stream) {
 extern "C" int rrcg_refresh(rrcg_handle hh, void* stream) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h) return fail(BTTB_EINVAL, "rrcg_refresh: NULL handle");
+  if (h->grp) return rrcg_group_refresh(h->grp, stream);
   hipStream_t s = static_cast<hipStream_t>(stream);
   return h->precision == BTTB_F64 ? outer_update<double>(h, s, 0) : outer_update<float>(h, s, 0);
 }
@@ -407,6 +389,7 @@ extern "C" int rrcg_refresh(rrcg_handle hh, void* stream) {
 extern "C" int rrcg_read_scalars(rrcg_handle hh, rrcg_scalars* out, void* stream) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h || !out) return fail(BTTB_EINVAL, "rrcg_read_scalars: NULL argument");
+  if (h->grp) return rrcg_group_read_scalars(h->grp, 0, out, stream);
   double sc[S_COUNT];
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTTB_HIP(hipMemcpyAsync(sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
@@ -430,6 +413,7 @@ extern "C" int rrcg_read_scalars(rrcg_handle hh, rrcg_scalars* out, void* stream
 extern "C" int rrcg_write_scalars(rrcg_handle hh, const rrcg_scalars* in, void* stream) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h || !in) return fail(BTTB_EINVAL, "rrcg_write_scalars: NULL argument");
+  if (h->grp) return rrcg_group_write_scalars(h->grp, 0, in, stream);
   double sc[S_COUNT];
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTTB_HIP(hipMemcpyAsync(sc, h->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
@@ -449,6 +433,14 @@ extern "C" int rrcg_write_scalars(rrcg_handle hh, const rrcg_scalars* in, void* 
   BTTB_HIP(hipMemcpyAsync(h->sc, sc, sizeof(sc), hipMemcpyHostToDevice, s));
   BTTB_HIP(hipStreamSynchronize(s));
   return BTTB_OK;
+}
+
+extern "C" int rrcg_products(rrcg_handle hh, bttb_group* out) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h || !out) return fail(BTTB_EINVAL, "rrcg_products: NULL argument");
+  *out = nullptr;
+  if (!h->grp) return fail(BTTB_ESTATE, "rrcg_products: the plans are not power-of-two plans");
+  return rrcg_group_products(h->grp, out);
 }
 
 extern "C" int rrcg_destroy(rrcg_handle hh) {

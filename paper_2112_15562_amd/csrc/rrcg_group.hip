@@ -173,7 +173,9 @@ static int g_capture(RrcgGroup* h, Fn fn, hipGraphExec_t* out) {
   int rc = BTTB_OK;
   hipError_t e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "rrcg_group: hipStreamBeginCapture");
+  h->grp->t_suspend += 1;  // no timing events inside graphs
   rc = fn(h->cap);
+  h->grp->t_suspend -= 1;
   e = hipStreamEndCapture(h->cap, &g);
   if (rc == BTTB_OK && e != hipSuccess) rc = hip_fail(e, "rrcg_group: hipStreamEndCapture");
   if (rc == BTTB_OK) {

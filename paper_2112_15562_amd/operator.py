@@ -223,8 +223,20 @@ class Group:
         self.device = ops[0].device
         arr = (C.c_void_p * len(ops))(*[op.plan.value for op in ops])
         self._g = C.c_void_p()
+        self._owned = True
         L.check(L.lib().bttb_group_create(arr, len(ops), C.c_void_p(_stream(self.device)), C.byref(self._g)),
                 "bttb_group_create")
+
+    @classmethod
+    def view(cls, handle: C.c_void_p, ops: Sequence[Operator]) -> "Group":
+        """Non-owning view of a group that a solver owns (for timing and inspection)."""
+        g = cls.__new__(cls)
+        g.ops = list(ops)
+        g.dtype = g.ops[0].dtype
+        g.device = g.ops[0].device
+        g._g = handle
+        g._owned = False
+        return g
 
     @property
     def handle(self) -> C.c_void_p:
@@ -244,6 +256,18 @@ class Group:
         L.check(L.lib().bttb_group_set_launch(self.handle, int(model_row_threads), int(data_row_threads),
                                               int(col_threads), int(layer_chunks),
                                               C.c_void_p(_stream(self.device))), "bttb_group_set_launch")
+
+    def timing_enable(self, max_launches: int, repeat: int = 1) -> None:
+        """Record HIP events around each stage launch (all members), each launched `repeat`
+        times back to back between its events."""
+        L.check(L.lib().bttb_group_timing_enable(self.handle, int(max_launches), int(repeat)),
+                "bttb_group_timing_enable")
+
+    def timing_read(self) -> dict:
+        tot = (C.c_double * L.NKERNELS)()
+        cnt = (C.c_int * L.NKERNELS)()
+        L.check(L.lib().bttb_group_timing_read(self.handle, tot, cnt), "bttb_group_timing_read")
+        return {L.KERNEL_NAMES[k]: (tot[k], cnt[k]) for k in range(L.NKERNELS)}
 
     def autotune(self, reps: int = 5) -> dict:
         """Tune the threads per block of each stage and the layer chunks by timing."""
@@ -283,7 +307,8 @@ class Group:
 
     def close(self):
         if self._g:
-            L.lib().bttb_group_destroy(self._g)
+            if self._owned:
+                L.lib().bttb_group_destroy(self._g)
             self._g = C.c_void_p()
 
     def __del__(self):

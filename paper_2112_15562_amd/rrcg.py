@@ -12,7 +12,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib as L
-from .operator import Operator, _ptr, _stream
+from .operator import Group, Operator, _ptr, _stream
 
 
 def _pair(v):
@@ -118,6 +118,14 @@ class JointRRCG:
 
     def _stream(self) -> int:
         return _stream(self.device)
+
+    def products(self) -> Optional[Group]:
+        """The product group the solver runs on (power-of-two plans), as a non-owning view
+        valid while the solver is open; None for other plans."""
+        g = C.c_void_p()
+        if L.lib().rrcg_products(self._h, C.byref(g)) != L.BTTB_OK:
+            return None
+        return Group.view(g, self.ops)
 
     def step(self, n_inner: int = 1) -> None:
         """One outer step (asynchronous)."""
@@ -249,13 +257,14 @@ class JointRRCGGroup:
                 "rrcg_group_autotune")
         return _tune_dict(r)
 
-    def launch_info(self) -> dict:
+    def products(self) -> Group:
+        """The solver's product group as a non-owning view (valid while the solver is open)."""
         g = C.c_void_p()
         L.check(L.lib().rrcg_group_products(self._h, C.byref(g)), "rrcg_group_products")
-        d = L.GroupDesc()
-        L.check(L.lib().bttb_group_info(g, C.byref(d)), "bttb_group_info")
-        return {"count": d.count, "model_row_threads": d.model_row_threads, "data_row_threads": d.data_row_threads,
-                "col_threads": d.col_threads, "layer_chunks": d.layer_chunks, "blocks": list(d.blocks)}
+        return Group.view(g, [op for v in self.inv for op in v.ops])
+
+    def launch_info(self) -> dict:
+        return self.products().info()
 
     def close(self):
         if self._h:
