@@ -352,6 +352,7 @@ def main():
     torch.cuda.synchronize()
     s32.close()
     s32 = solver(pk, torch, ops32, dobs, wd, wdepth)   # fresh start for the timed solve
+    tune32 = s32.autotune(reps=3)  # launch shape by timing CG steps; the state is restored
     torch.cuda.synchronize()
     log("bench: fp32 timed solve")
     t0 = time.perf_counter()
@@ -372,6 +373,8 @@ def main():
     log("bench: fp32 per-kernel timing")
     se = solver(pk, torch, ops32, dobs, wd, wdepth, use_graph=False)
     prod = se.products()  # both operators' products share each launch of this group
+    prod.set_launch(tune32["model_row_threads"], tune32["data_row_threads"], tune32["col_threads"],
+                    tune32["layer_chunks"])
     launches = 2 * (N_INNER * 6 + 3) + 16
     prod.timing_enable(launches, TIMING_REPEAT)
     for _ in range(2):
@@ -420,6 +423,7 @@ def main():
         torch.cuda.synchronize()
         s64.close()
         s64 = solver(pk, torch, ops64, dobs, wd, wdepth)
+        s64.autotune(reps=3)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -458,7 +462,9 @@ def main():
                                "FP32 FFT with FP64 reductions",
                    "stations": [g.sx, g.sy], "prisms": [g.nx, g.ny, g.nz], "transform": [info32["Px"],
                                                                                       info32["Py"]],
-                   "inner_per_step": N_INNER},
+                   "inner_per_step": N_INNER,
+                   "launch_shape": {k: tune32[k] for k in ("model_row_threads", "data_row_threads", "col_threads",
+                                                           "layer_chunks")}},
         "rrcg_solve_s": {"f32": t32 * 20 / args.steps, "f64": (t64 * 20 / args.steps) if t64 else None,
                          "outer": 20, "inner": N_INNER},
         "product_pairs_per_s": {"f32": rate32, "f64": rate64, "f32_both_operators_per_launch": grate32,

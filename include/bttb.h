@@ -316,6 +316,9 @@ BTTB_API int rrcg_write_scalars(rrcg_handle h, const rrcg_scalars* in, void* str
  * from a checkpoint (with rrcg_write_scalars for the scalar state). */
 BTTB_API int rrcg_refresh(rrcg_handle h, void* stream);
 
+/* rrcg_group_autotune for a solver on power-of-two plans (BTTB_ESTATE otherwise). */
+BTTB_API int rrcg_autotune(rrcg_handle h, int reps, void* stream, bttb_tune_result* out);
+
 /* The product group of a solver on power-of-two plans (owned by the solver), for
  * inspection and timing; BTTB_ESTATE for other plans. */
 BTTB_API int rrcg_products(rrcg_handle h, bttb_group* out);
@@ -347,7 +350,11 @@ BTTB_API int rrcg_group_refresh(rrcg_group g, void* stream);
 BTTB_API int rrcg_group_set_launch(rrcg_group g, int model_row_threads, int data_row_threads, int col_threads,
                                    int layer_chunks, void* stream);
 
-/* bttb_group_autotune on the solver's products, then the step graphs are recaptured. */
+/* Launch shape of the solver's products chosen by timing `reps` CG steps per candidate (the
+ * fused forms the solve runs), one coordinate at a time; the solver state is saved before
+ * and restored after, so the solve is unchanged.  Allocates a temporary copy of the state;
+ * recaptures the step graphs; synchronises `stream`.  us_per_pair in `out` is the CG step
+ * time divided by the operator pairs of a step (2 per inversion). */
 BTTB_API int rrcg_group_autotune(rrcg_group g, int reps, void* stream, bttb_tune_result* out);
 
 /* The product group the solver uses (owned by the solver; valid until rrcg_group_destroy),

@@ -308,7 +308,7 @@ static void default_shape(Group* g) {
     tr = std::max(tr, g->P[i]->Py / 8);
     tc = std::max(tc, g->P[i]->Px / 8);
   }
-  g->bt_rm = std::max(256, tr);
+  g->bt_rm = std::max(512, tr);  // 16-row tiles: whole 128-byte segments in the transposed stores
   g->bt_rd = std::max(64, tr);
   g->bt_c = std::max(g->precision == BTTB_F64 ? 128 : 256, tc);
   g->nchunk = 1;

@@ -435,6 +435,14 @@ extern "C" int rrcg_write_scalars(rrcg_handle hh, const rrcg_scalars* in, void* 
   return BTTB_OK;
 }
 
+extern "C" int rrcg_autotune(rrcg_handle hh, int reps, void* stream, bttb_tune_result* out) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_autotune: NULL handle");
+  if (!h->grp) return fail(BTTB_ESTATE, "rrcg_autotune: the plans are not power-of-two plans (tune them with "
+                                        "bttb_autotune before creating the solver)");
+  return rrcg_group_autotune(h->grp, reps, stream, out);
+}
+
 extern "C" int rrcg_products(rrcg_handle hh, bttb_group* out) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h || !out) return fail(BTTB_EINVAL, "rrcg_products: NULL argument");

@@ -470,13 +470,116 @@ extern "C" int rrcg_group_set_launch(rrcg_group hh, int model_row_threads, int d
   return rc;
 }
 
+// Launch shape of the solver's products chosen by timing `reps` CG steps (the fused forms the
+// solve runs) per candidate, one coordinate at a time, twice round.  The steps advance the
+// iterate, so the solver state (models, directions, residuals, scalars, partials) is saved
+// first and restored afterwards: the solve continues exactly as without tuning.
+template <typename T>
+static int g_autotune(RrcgGroup* h, int reps, hipStream_t s, bttb_tune_result* out) {
+  const size_t es = sizeof(T);
+  struct Seg {
+    void* p;
+    size_t bytes;
+  };
+  std::vector<Seg> segs;
+  long long pb_doubles = 0;
+  for (int i = 0; i < h->count; ++i) {
+    const Plan* P = h->grp->P[2 * i];
+    pb_doubles += (long long)PB_NSLOT * std::max<long long>(
+        RGRID, std::max<long long>((long long)P->nz * ((P->nx + 1) / 2), (P->sx + 1) / 2));
+  }
+  segs.push_back({h->sc, sizeof(double) * S_COUNT * h->count});
+  segs.push_back({h->pb, sizeof(double) * (size_t)pb_doubles});
+  segs.push_back({h->pbn, sizeof(int) * PB_NSLOT * h->count});
+  std::vector<const void*> st(PA_COUNT * 2 * h->count);
+  BTTB_HIP(hipMemcpy(st.data(), h->ptrs, sizeof(void*) * st.size(), hipMemcpyDeviceToHost));
+  for (int mi = 0; mi < 2 * h->count; ++mi) {
+    const int i = mi / 2;
+    segs.push_back({const_cast<void*>(st[(size_t)PA_M * 2 * h->count + mi]), (size_t)h->n[i] * es});
+    segs.push_back({const_cast<void*>(st[(size_t)PA_P * 2 * h->count + mi]), (size_t)h->n[i] * es});
+    segs.push_back({const_cast<void*>(st[(size_t)PA_RT * 2 * h->count + mi]), (size_t)h->nd[i] * es});
+  }
+  size_t total = 0;
+  for (const Seg& g : segs) total += (g.bytes + 255) & ~(size_t)255;
+  void* save = nullptr;
+  if (hipMalloc(&save, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BTTB_ENOMEM, "rrcg_group_autotune: save buffer allocation failed");
+  }
+  auto copy = [&](bool to_save) -> int {
+    size_t off = 0;
+    for (const Seg& g : segs) {
+      char* b = static_cast<char*>(save) + off;
+      BTTB_HIP(hipMemcpyAsync(to_save ? (void*)b : g.p, to_save ? g.p : (void*)b, g.bytes,
+                              hipMemcpyDeviceToDevice, s));
+      off += (g.bytes + 255) & ~(size_t)255;
+    }
+    return BTTB_OK;
+  };
+  hipEvent_t ea = nullptr, eb = nullptr;
+  int rc = copy(true);
+  if (!rc && (hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess))
+    rc = fail(BTTB_EHIP, "rrcg_group_autotune: hipEventCreate");
+  Group* g = h->grp;
+  int cur[4] = {g->bt_rm, g->bt_rd, g->bt_c, g->nchunk};
+  float best = -1.0f;
+  int tried = 0;
+  auto measure = [&](float* ms) -> int {
+    int r = g_weights<T>(h, s);  // valid weights for the timed steps
+    if (!r) r = g_inner<T>(h, 0, s);
+    if (r) return r;
+    BTTB_HIP(hipEventRecord(ea, s));
+    for (int k = 0; k < reps && !r; ++k) r = g_inner<T>(h, 0, s);
+    if (r) return r;
+    BTTB_HIP(hipEventRecord(eb, s));
+    BTTB_HIP(hipEventSynchronize(eb));
+    BTTB_HIP(hipEventElapsedTime(ms, ea, eb));
+    return BTTB_OK;
+  };
+  if (!rc) rc = measure(&best);
+  if (!rc) ++tried;
+  const int cmax = h->precision == BTTB_F64 ? 256 : 512;
+  const int cand[4][4] = {{128, 256, 512, 0}, {64, 128, 256, 0}, {128, 256, cmax, 0}, {1, 2, 4, 0}};
+  for (int round = 0; round < 2 && !rc; ++round) {
+    for (int coord = 0; coord < 4 && !rc; ++coord) {
+      for (int ci = 0; cand[coord][ci] && !rc; ++ci) {
+        int trial[4] = {cur[0], cur[1], cur[2], cur[3]};
+        trial[coord] = cand[coord][ci];
+        if (trial[coord] == cur[coord]) continue;
+        if (group_set_launch(g, trial[0], trial[1], trial[2], trial[3], s) != BTTB_OK) continue;
+        float ms = 0.0f;
+        rc = measure(&ms);
+        if (rc) break;
+        ++tried;
+        if (ms < best) {
+          best = ms;
+          for (int k = 0; k < 4; ++k) cur[k] = trial[k];
+        }
+      }
+      if (!rc) rc = group_set_launch(g, cur[0], cur[1], cur[2], cur[3], s);
+    }
+  }
+  const int rc2 = copy(false);  // restore the solver state in any case
+  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = fail(BTTB_EHIP, "rrcg_group_autotune: synchronize");
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  dfree(save);
+  if (!rc) rc = rc2;
+  if (!rc && out) {
+    out->us_per_pair = 1e3 * (double)best / reps / (2.0 * h->count);
+    for (int k = 0; k < 4; ++k) out->shape[k] = cur[k];
+    out->tried = tried;
+  }
+  return rc;
+}
+
 extern "C" int rrcg_group_autotune(rrcg_group hh, int reps, void* stream, bttb_tune_result* out) {
   RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
   if (!h) return fail(BTTB_EINVAL, "rrcg_group_autotune: NULL handle");
   if (reps < 1 || reps > 1000) return fail(BTTB_EINVAL, "rrcg_group_autotune: reps must be in [1, 1000]");
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTTB_HIP(hipStreamSynchronize(s));
-  int rc = group_autotune(h->grp, reps, s, out);
+  int rc = h->precision == BTTB_F64 ? g_autotune<double>(h, reps, s, out) : g_autotune<float>(h, reps, s, out);
   if (!rc && h->use_graph) rc = h->precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
   return rc;
 }

@@ -119,6 +119,14 @@ class JointRRCG:
     def _stream(self) -> int:
         return _stream(self.device)
 
+    def autotune(self, reps: int = 3) -> dict:
+        """Choose the launch shape of the solver's products by timing CG steps (power-of-two
+        plans); the solver state is restored afterwards."""
+        from .operator import _tune_dict
+        r = L.TuneResult()
+        L.check(L.lib().rrcg_autotune(self._h, int(reps), C.c_void_p(self._stream()), C.byref(r)), "rrcg_autotune")
+        return _tune_dict(r)
+
     def products(self) -> Optional[Group]:
         """The product group the solver runs on (power-of-two plans), as a non-owning view
         valid while the solver is open; None for other plans."""
@@ -249,8 +257,9 @@ class JointRRCGGroup:
                                               int(col_threads), int(layer_chunks), C.c_void_p(self._stream())),
                 "rrcg_group_set_launch")
 
-    def autotune(self, reps: int = 5) -> dict:
-        """Tune the launch shape of the group's products by timing; recaptures the graphs."""
+    def autotune(self, reps: int = 3) -> dict:
+        """Choose the launch shape of the group's products by timing CG steps; the solver
+        state is restored afterwards and the graphs are recaptured."""
         from .operator import _tune_dict
         r = L.TuneResult()
         L.check(L.lib().rrcg_group_autotune(self._h, int(reps), C.c_void_p(self._stream()), C.byref(r)),

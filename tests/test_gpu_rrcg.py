@@ -227,3 +227,26 @@ def test_graph_replay_equals_eager(pk, dtype):
         assert a["phi"] == b["phi"] and a["alpha"] == b["alpha"] and a["k"] == b["k"] == k + 1
     sg.close()
     se.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_autotune_mid_solve_keeps_the_trajectory(pk, dtype, tol):
+    # tuning times CG steps on the live solver and must restore its state exactly; only the
+    # grouping of partial sums changes with the launch shape
+    g = synth.MID
+    ops, T, data, _ = problem(g, dense=False)
+    prm = orrcg.Params(**BASE)
+    a, _ = gpu_solver(pk, g, T, data, prm, dtype)
+    b, _ = gpu_solver(pk, g, T, data, prm, dtype)
+    a.step(5)
+    b.step(5)
+    res = b.autotune(reps=2)
+    assert res["tried"] >= 4
+    for _ in range(2):
+        a.step(5)
+        b.step(5)
+    for i in range(2):
+        assert rel(host(b.m[i]), host(a.m[i])) <= tol
+    assert b.scalars()["k"] == a.scalars()["k"] == 3
+    a.close()
+    b.close()
