@@ -37,13 +37,19 @@ N_INNER = 50
 COPY_BYTES = 256 << 20   # one side of the calibration copy
 TIMING_REPEAT = 10
 
-# HBM traffic of the dominant kernel per launch, from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu --no-f64 --pairs 4` (FETCH_SIZE, then WRITE_SIZE),
+# HBM traffic of the solver's product launches, from two rocprofv3 --pmc runs of
+# `bench.py --steps 1 --warmup 0 --no-cpu --no-f64 --no-batch --pairs 4` (FETCH_SIZE, then WRITE_SIZE),
 # each scaled by the same counter's reading for the calibration copy (COPY_BYTES read,
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
-TRAFFIC = {"kernel": "fwd_col_eig_sum", "fetch_bytes": 50737938, "write_bytes": 2105344,
-           "csrc_sha256": "96f4a8a0ae6b908248dc76624f12f2e0c950bbacc456d702ba96927864891746"}
+TRAFFIC = {
+    "csrc_sha256": "517bf161764df84313613ce30b8da468a5d9cf204da2ab0c41035e22beff30d3",
+    "bytes": {  # FETCH, WRITE per launch (both operators)
+        "fwd_row_r2c": (50718955, 50531444), "fwd_col_eig_sum": (101298763, 4327738),
+        "fwd_row_c2r": (1817622, 532439), "adj_row_r2c": (1205003, 1064960),
+        "adj_col_conj_eig": (76279327, 33685504), "adj_row_c2r": (102735484, 16811643),
+    },
+}
 
 
 def parse():
@@ -216,9 +222,9 @@ def kernel_source_digest():
 
 
 def traffic_for(kernel):
-    if TRAFFIC is None or TRAFFIC["csrc_sha256"] != kernel_source_digest() or TRAFFIC["kernel"] != kernel:
+    if TRAFFIC is None or TRAFFIC["csrc_sha256"] != kernel_source_digest() or kernel not in TRAFFIC["bytes"]:
         return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    return sum(TRAFFIC["bytes"][kernel])
 
 
 def kernel_bytes(info, esz, weighted=True):
@@ -352,7 +358,7 @@ def main():
     torch.cuda.synchronize()
     s32.close()
     s32 = solver(pk, torch, ops32, dobs, wd, wdepth)   # fresh start for the timed solve
-    tune32 = s32.autotune(reps=3)  # launch shape by timing CG steps; the state is restored
+    tune32 = s32.autotune(reps=10)  # launch shape by timing CG steps; the state is restored
     torch.cuda.synchronize()
     log("bench: fp32 timed solve")
     t0 = time.perf_counter()
@@ -423,7 +429,7 @@ def main():
         torch.cuda.synchronize()
         s64.close()
         s64 = solver(pk, torch, ops64, dobs, wd, wdepth)
-        s64.autotune(reps=3)
+        s64.autotune(reps=10)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
