@@ -275,8 +275,8 @@ typedef struct {
   double alpha0[2], q[2], alpha_min[2], lambda[2];
   double eps2;
   int coupled, restart, p_norm, gramian_weighted;
-  int use_graph;  /* 1: the step's kernel sequences are captured once into HIP graphs at creation
-                     and replayed by rrcg_step (fewer launches); 0: launched one by one */
+  int use_graph;  /* 1: the step's kernel sequences are captured into HIP graphs and replayed by
+                     rrcg_step (fewer launches); 0: launched one by one */
 } rrcg_desc;
 
 /* Scalar state (FP64) of a handle. */
@@ -308,6 +308,11 @@ BTTB_API int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out);
  * no device-to-host transfer. */
 BTTB_API int rrcg_step(rrcg_handle h, int n_inner, void* stream);
 
+/* Capture the graph of an outer step with n_inner CG steps ahead of its first use (a
+ * solver on power-of-two plans with use_graph replays each outer step as one graph,
+ * captured on first use per step length; otherwise this does nothing). */
+BTTB_API int rrcg_prepare(rrcg_handle h, int n_inner);
+
 /* Copy the scalar state to / from the host.  Synchronises `stream`. */
 BTTB_API int rrcg_read_scalars(rrcg_handle h, rrcg_scalars* out, void* stream);
 BTTB_API int rrcg_write_scalars(rrcg_handle h, const rrcg_scalars* in, void* stream);
@@ -335,8 +340,11 @@ BTTB_API int rrcg_destroy(rrcg_handle h);
  * whole group.  Creation allocates the work vectors and synchronises `stream`. */
 BTTB_API int rrcg_group_create(const rrcg_desc* descs, int count, void* stream, rrcg_group* out);
 
-/* One outer step of every inversion (as rrcg_step).  Asynchronous. */
+/* One outer step of every inversion (as rrcg_step).  Asynchronous.  With use_graph the whole
+ * outer step is one graph, captured on the first step with this n_inner (the four most
+ * recent step lengths are kept; rrcg_group_prepare captures ahead). */
 BTTB_API int rrcg_group_step(rrcg_group g, int n_inner, void* stream);
+BTTB_API int rrcg_group_prepare(rrcg_group g, int n_inner);
 
 /* Scalars of inversion `index` (0-based); synchronise `stream`. */
 BTTB_API int rrcg_group_read_scalars(rrcg_group g, int index, rrcg_scalars* out, void* stream);

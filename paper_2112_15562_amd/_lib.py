@@ -27,7 +27,7 @@ EXPORTED = [
     "rrcg_group_create", "rrcg_group_step", "rrcg_group_read_scalars", "rrcg_group_write_scalars",
     "rrcg_group_refresh", "rrcg_group_set_launch", "rrcg_group_products", "rrcg_group_destroy",
     "bttb_autotune", "bttb_group_autotune", "rrcg_group_autotune", "bttb_group_timing_enable",
-    "bttb_group_timing_read", "rrcg_products", "rrcg_autotune",
+    "bttb_group_timing_read", "rrcg_products", "rrcg_autotune", "rrcg_prepare", "rrcg_group_prepare",
 ]
 NKERNELS = 6
 KERNEL_NAMES = ["fwd_row_r2c", "fwd_col_eig_sum", "fwd_row_c2r", "adj_row_r2c", "adj_col_conj_eig", "adj_row_c2r"]
@@ -130,6 +130,8 @@ def lib() -> C.CDLL:
         "bttb_group_timing_read": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int)],
         "rrcg_products": [vp, C.POINTER(vp)],
         "rrcg_autotune": [vp, i, vp, C.POINTER(TuneResult)],
+        "rrcg_prepare": [vp, i],
+        "rrcg_group_prepare": [vp, i],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

@@ -435,6 +435,13 @@ extern "C" int rrcg_write_scalars(rrcg_handle hh, const rrcg_scalars* in, void* 
   return BTTB_OK;
 }
 
+extern "C" int rrcg_prepare(rrcg_handle hh, int n_inner) {
+  Rrcg* h = reinterpret_cast<Rrcg*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_prepare: NULL handle");
+  if (n_inner < 1) return fail(BTTB_EINVAL, "rrcg_prepare: n_inner must be >= 1");
+  return h->grp ? rrcg_group_prepare(h->grp, n_inner) : BTTB_OK;
+}
+
 extern "C" int rrcg_autotune(rrcg_handle hh, int reps, void* stream, bttb_tune_result* out) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h) return fail(BTTB_EINVAL, "rrcg_autotune: NULL handle");

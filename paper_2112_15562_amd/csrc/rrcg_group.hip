@@ -118,7 +118,10 @@ struct RrcgGroup {
   long long n[GINV_MAX], nd[GINV_MAX];
   double alpha0[GINV_MAX][2];
   hipStream_t cap;
-  hipGraphExec_t g_weights, g_inner_restart, g_inner, g_outer;
+  // whole outer steps captured as one graph each, per number of CG steps (most recent last)
+  int n_graphs;
+  int graph_inner[4];
+  hipGraphExec_t graph[4];
 };
 
 // Device pointer arrays (one entry per member) of the group products.
@@ -187,28 +190,49 @@ static int g_capture(RrcgGroup* h, Fn fn, hipGraphExec_t* out) {
 }
 
 static void g_drop_graphs(RrcgGroup* h) {
-  for (hipGraphExec_t* g : {&h->g_weights, &h->g_inner_restart, &h->g_inner, &h->g_outer}) {
-    if (*g) (void)hipGraphExecDestroy(*g);
-    *g = nullptr;
-  }
+  for (int k = 0; k < h->n_graphs; ++k)
+    if (h->graph[k]) (void)hipGraphExecDestroy(h->graph[k]);
+  h->n_graphs = 0;
 }
 
+// The graph of a whole outer step with n_inner CG steps, captured on first use (or by
+// rrcg_group_prepare) and kept for the four most recent step lengths.
 template <typename T>
-static int g_build_graphs(RrcgGroup* h) {
-  g_drop_graphs(h);
-  int rc = g_capture(h, [&](hipStream_t s) { return g_weights<T>(h, s); }, &h->g_weights);
-  if (!rc) rc = g_capture(h, [&](hipStream_t s) { return g_inner<T>(h, 1, s); }, &h->g_inner_restart);
-  if (!rc) rc = g_capture(h, [&](hipStream_t s) { return g_inner<T>(h, 0, s); }, &h->g_inner);
-  if (!rc) rc = g_capture(h, [&](hipStream_t s) { return g_outer<T>(h, s, 1); }, &h->g_outer);
-  return rc;
+static int g_step_graph(RrcgGroup* h, int n_inner, hipGraphExec_t* out) {
+  for (int k = 0; k < h->n_graphs; ++k)
+    if (h->graph_inner[k] == n_inner) {
+      *out = h->graph[k];
+      return BTTB_OK;
+    }
+  if (h->n_graphs == 4) {  // forget the oldest
+    (void)hipGraphExecDestroy(h->graph[0]);
+    for (int k = 1; k < 4; ++k) {
+      h->graph[k - 1] = h->graph[k];
+      h->graph_inner[k - 1] = h->graph_inner[k];
+    }
+    h->n_graphs = 3;
+  }
+  hipGraphExec_t e = nullptr;
+  const int rc = g_capture(h, [&](hipStream_t s) {
+    int r = g_weights<T>(h, s);
+    for (int j = 0; j < n_inner && !r; ++j) r = g_inner<T>(h, j == 0 ? 1 : 0, s);
+    return r ? r : g_outer<T>(h, s, 1);
+  }, &e);
+  if (rc) return rc;
+  h->graph[h->n_graphs] = e;
+  h->graph_inner[h->n_graphs] = n_inner;
+  h->n_graphs += 1;
+  *out = e;
+  return BTTB_OK;
 }
 
 template <typename T>
 static int g_step(RrcgGroup* h, int n_inner, hipStream_t s) {
   if (h->use_graph) {
-    BTTB_HIP(hipGraphLaunch(h->g_weights, s));
-    for (int j = 0; j < n_inner; ++j) BTTB_HIP(hipGraphLaunch(j == 0 ? h->g_inner_restart : h->g_inner, s));
-    BTTB_HIP(hipGraphLaunch(h->g_outer, s));
+    hipGraphExec_t e = nullptr;
+    const int rc = g_step_graph<T>(h, n_inner, &e);
+    if (rc) return rc;
+    BTTB_HIP(hipGraphLaunch(e, s));
     return BTTB_OK;
   }
   int rc = g_weights<T>(h, s);
@@ -365,7 +389,7 @@ static void elementwise_blocks(RrcgGroup* h) {
   for (int i = 0; i < h->count; ++i) {
     const long long top = std::max(h->n[i], h->nd[i]);
     const long long nb = std::min<long long>(RGRID, std::max<long long>(1, ceil_div((int)std::min<long long>(
-                                                                                top, 1LL << 30), RB * 4)));
+                                                                                top, 1LL << 30), RB * EW_UNROLL)));
     h->est.start[i + 1] = h->est.start[i] + (int)nb;
   }
 }
@@ -434,7 +458,7 @@ extern "C" int rrcg_group_create(const rrcg_desc* descs, int count, void* stream
     if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
       rc = fail(BTTB_EHIP, "rrcg_group_create: capture stream");
     else
-      rc = precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
+      h->n_graphs = 0;  // step graphs are captured on first use per step length
   }
   if (rc) {
     g_free(h);
@@ -452,6 +476,15 @@ extern "C" int rrcg_group_step(rrcg_group hh, int n_inner, void* stream) {
   return h->precision == BTTB_F64 ? g_step<double>(h, n_inner, s) : g_step<float>(h, n_inner, s);
 }
 
+extern "C" int rrcg_group_prepare(rrcg_group hh, int n_inner) {
+  RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
+  if (!h) return fail(BTTB_EINVAL, "rrcg_group_prepare: NULL handle");
+  if (n_inner < 1) return fail(BTTB_EINVAL, "rrcg_group_prepare: n_inner must be >= 1");
+  if (!h->use_graph) return BTTB_OK;
+  hipGraphExec_t e = nullptr;
+  return h->precision == BTTB_F64 ? g_step_graph<double>(h, n_inner, &e) : g_step_graph<float>(h, n_inner, &e);
+}
+
 extern "C" int rrcg_group_refresh(rrcg_group hh, void* stream) {
   RrcgGroup* h = reinterpret_cast<RrcgGroup*>(hh);
   if (!h) return fail(BTTB_EINVAL, "rrcg_group_refresh: NULL handle");
@@ -466,7 +499,7 @@ extern "C" int rrcg_group_set_launch(rrcg_group hh, int model_row_threads, int d
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTTB_HIP(hipStreamSynchronize(s));
   int rc = group_set_launch(h->grp, model_row_threads, data_row_threads, col_threads, layer_chunks, s);
-  if (!rc && h->use_graph) rc = h->precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
+  if (!rc) g_drop_graphs(h);  // recaptured with the new shape on next use
   return rc;
 }
 
@@ -524,17 +557,37 @@ static int g_autotune(RrcgGroup* h, int reps, hipStream_t s, bttb_tune_result* o
   int cur[4] = {g->bt_rm, g->bt_rd, g->bt_c, g->nchunk};
   float best = -1.0f;
   int tried = 0;
+  // a candidate runs as the solve does: one CG step captured as a graph and replayed; the
+  // best of two rounds of `reps` replays
   auto measure = [&](float* ms) -> int {
     int r = g_weights<T>(h, s);  // valid weights for the timed steps
-    if (!r) r = g_inner<T>(h, 0, s);
     if (r) return r;
-    BTTB_HIP(hipEventRecord(ea, s));
-    for (int k = 0; k < reps && !r; ++k) r = g_inner<T>(h, 0, s);
-    if (r) return r;
-    BTTB_HIP(hipEventRecord(eb, s));
-    BTTB_HIP(hipEventSynchronize(eb));
-    BTTB_HIP(hipEventElapsedTime(ms, ea, eb));
-    return BTTB_OK;
+    hipGraphExec_t e = nullptr;
+    if (h->use_graph) {
+      r = g_capture(h, [&](hipStream_t cs) { return g_inner<T>(h, 0, cs); }, &e);
+      if (r) return r;
+    }
+    auto one = [&]() -> int {
+      if (e) {
+        BTTB_HIP(hipGraphLaunch(e, s));
+        return BTTB_OK;
+      }
+      return g_inner<T>(h, 0, s);
+    };
+    float bestm = -1.0f;
+    r = one();  // warm-up
+    for (int round = 0; round < 2 && !r; ++round) {
+      if (hipEventRecord(ea, s) != hipSuccess) r = fail(BTTB_EHIP, "rrcg_group_autotune: event");
+      for (int k = 0; k < reps && !r; ++k) r = one();
+      if (!r && hipEventRecord(eb, s) != hipSuccess) r = fail(BTTB_EHIP, "rrcg_group_autotune: event");
+      float m = 0.0f;
+      if (!r && (hipEventSynchronize(eb) != hipSuccess || hipEventElapsedTime(&m, ea, eb) != hipSuccess))
+        r = fail(BTTB_EHIP, "rrcg_group_autotune: event timing");
+      if (!r && (bestm < 0.0f || m < bestm)) bestm = m;
+    }
+    if (e) (void)hipGraphExecDestroy(e);
+    *ms = bestm;
+    return r;
   };
   if (!rc) rc = measure(&best);
   if (!rc) ++tried;
@@ -580,7 +633,7 @@ extern "C" int rrcg_group_autotune(rrcg_group hh, int reps, void* stream, bttb_t
   hipStream_t s = static_cast<hipStream_t>(stream);
   BTTB_HIP(hipStreamSynchronize(s));
   int rc = h->precision == BTTB_F64 ? g_autotune<double>(h, reps, s, out) : g_autotune<float>(h, reps, s, out);
-  if (!rc && h->use_graph) rc = h->precision == BTTB_F64 ? g_build_graphs<double>(h) : g_build_graphs<float>(h);
+  if (!rc) g_drop_graphs(h);  // recaptured with the new shape on next use
   return rc;
 }
 

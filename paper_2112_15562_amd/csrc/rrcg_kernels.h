@@ -12,8 +12,12 @@
 
 namespace bttb {
 
-constexpr int RB = 256;     // threads per elementwise block
-constexpr int RGRID = 512;  // elementwise blocks of the one-inversion solver
+constexpr int RB = 256;       // threads per elementwise block
+constexpr int RGRID = 512;    // elementwise blocks of the one-inversion solver
+#ifndef RRCG_EW_UNROLL
+#define RRCG_EW_UNROLL 4
+#endif
+constexpr int EW_UNROLL = RRCG_EW_UNROLL;  // elements per thread whose loads are issued together
 
 struct Red {  // where a reducing kernel puts its partials
   double* pb;
@@ -27,25 +31,40 @@ __device__ __forceinline__ void weights_body(long long n, const T* m0, const T* 
                                              int p_norm, int gram_w, T* w0, T* w1, T* wi0, T* wi1, double* sc,
                                              Red rd, int bid, int nb) {
   double v[3] = {0.0, 0.0, 0.0};
-  for (long long j = bid * (long long)RB + threadIdx.x; j < n; j += (long long)nb * RB) {
-    const double a = m0[j], b = m1[j];
-    double W0 = wz0[j], W1 = wz1[j];
-    if (wh0) W0 *= (double)wh0[j];
-    if (wh1) W1 *= (double)wh1[j];
-    if (p_norm == 1) {
-      const double d0 = a - (ma0 ? (double)ma0[j] : 0.0), d1 = b - (ma1 ? (double)ma1[j] : 0.0);
-      W0 *= 1.0 / pow(d0 * d0 + eps2, 0.25);
-      W1 *= 1.0 / pow(d1 * d1 + eps2, 0.25);
+  for (long long j0 = bid * (long long)RB * EW_UNROLL + threadIdx.x; j0 < n; j0 += (long long)nb * RB * EW_UNROLL) {
+    T a_[EW_UNROLL], b_[EW_UNROLL], z0[EW_UNROLL], z1[EW_UNROLL];
+#pragma unroll
+    for (int u = 0; u < EW_UNROLL; ++u) {  // loads first
+      const long long j = j0 + (long long)u * RB;
+      const bool ok = j < n;
+      a_[u] = ok ? m0[j] : T(0);
+      b_[u] = ok ? m1[j] : T(0);
+      z0[u] = ok ? wz0[j] : T(0);
+      z1[u] = ok ? wz1[j] : T(0);
     }
-    const T W0t = (T)W0, W1t = (T)W1;
-    w0[j] = W0t;
-    w1[j] = W1t;
-    wi0[j] = (T)(1.0 / (double)W0t);
-    wi1[j] = (T)(1.0 / (double)W1t);
-    const double u0 = gram_w ? (double)W0t * a : a, u1 = gram_w ? (double)W1t * b : b;
-    v[0] += u0 * u0;
-    v[1] += u1 * u1;
-    v[2] += u0 * u1;
+#pragma unroll
+    for (int u = 0; u < EW_UNROLL; ++u) {
+      const long long j = j0 + (long long)u * RB;
+      if (j >= n) continue;
+      const double a = a_[u], b = b_[u];
+      double W0 = z0[u], W1 = z1[u];
+      if (wh0) W0 *= (double)wh0[j];
+      if (wh1) W1 *= (double)wh1[j];
+      if (p_norm == 1) {
+        const double d0 = a - (ma0 ? (double)ma0[j] : 0.0), d1 = b - (ma1 ? (double)ma1[j] : 0.0);
+        W0 *= 1.0 / pow(d0 * d0 + eps2, 0.25);
+        W1 *= 1.0 / pow(d1 * d1 + eps2, 0.25);
+      }
+      const T W0t = (T)W0, W1t = (T)W1;
+      w0[j] = W0t;
+      w1[j] = W1t;
+      wi0[j] = (T)(1.0 / (double)W0t);
+      wi1[j] = (T)(1.0 / (double)W1t);
+      const double u0 = gram_w ? (double)W0t * a : a, u1 = gram_w ? (double)W1t * b : b;
+      v[0] += u0 * u0;
+      v[1] += u1 * u1;
+      v[2] += u0 * u1;
+    }
   }
   block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, bid, nb);
 }
@@ -123,21 +142,37 @@ __device__ __forceinline__ void update_body(long long n, long long nd, T* m0, T*
   const double s0 = st[0], s1 = st[1];
   double v[3] = {0.0, 0.0, 0.0};
   const long long top = n > nd ? n : nd;
-  for (long long j = bid * (long long)RB + threadIdx.x; j < top; j += (long long)nb * RB) {
-    if (j < n) {
-      const double W0 = w0[j], W1 = w1[j];
-      const T a = (T)((W0 * (double)m0[j] - s0 * (double)p0[j]) / W0);
-      const T b = (T)((W1 * (double)m1[j] - s1 * (double)p1[j]) / W1);
-      m0[j] = a;
-      m1[j] = b;
-      const double u0 = gram_w ? W0 * (double)a : (double)a, u1 = gram_w ? W1 * (double)b : (double)b;
-      v[0] += u0 * u0;
-      v[1] += u1 * u1;
-      v[2] += u0 * u1;
+  for (long long j0 = bid * (long long)RB * EW_UNROLL + threadIdx.x; j0 < top; j0 += (long long)nb * RB * EW_UNROLL) {
+    T M0[EW_UNROLL], M1[EW_UNROLL], P0[EW_UNROLL], P1[EW_UNROLL], V0[EW_UNROLL], V1[EW_UNROLL];
+#pragma unroll
+    for (int u = 0; u < EW_UNROLL; ++u) {  // loads first: the stores below cannot hold them back
+      const long long j = j0 + (long long)u * RB;
+      const bool ok = j < n;
+      M0[u] = ok ? m0[j] : T(0);
+      M1[u] = ok ? m1[j] : T(0);
+      P0[u] = ok ? p0[j] : T(0);
+      P1[u] = ok ? p1[j] : T(0);
+      V0[u] = ok ? w0[j] : T(1);
+      V1[u] = ok ? w1[j] : T(1);
     }
-    if (j < nd) {
-      r0[j] = (T)((double)r0[j] - s0 * (double)q0[j]);
-      r1[j] = (T)((double)r1[j] - s1 * (double)q1[j]);
+#pragma unroll
+    for (int u = 0; u < EW_UNROLL; ++u) {
+      const long long j = j0 + (long long)u * RB;
+      if (j < n) {
+        const double W0 = V0[u], W1 = V1[u];
+        const T a = (T)((W0 * (double)M0[u] - s0 * (double)P0[u]) / W0);
+        const T b = (T)((W1 * (double)M1[u] - s1 * (double)P1[u]) / W1);
+        m0[j] = a;
+        m1[j] = b;
+        const double u0 = gram_w ? W0 * (double)a : (double)a, u1 = gram_w ? W1 * (double)b : (double)b;
+        v[0] += u0 * u0;
+        v[1] += u1 * u1;
+        v[2] += u0 * u1;
+      }
+      if (j < nd) {
+        r0[j] = (T)((double)r0[j] - s0 * (double)q0[j]);
+        r1[j] = (T)((double)r1[j] - s1 * (double)q1[j]);
+      }
     }
   }
   block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, bid, nb);
@@ -148,15 +183,27 @@ template <typename T>
 __device__ __forceinline__ void clip_body(long long n, T* m0, T* m1, double lo0, double hi0, double lo1,
                                           double hi1, Red rd, int bid, int nb) {
   double v[3] = {0.0, 0.0, 0.0};
-  for (long long j = bid * (long long)RB + threadIdx.x; j < n; j += (long long)nb * RB) {
-    const double a = fmin(fmax((double)m0[j], lo0), hi0);
-    const double b = fmin(fmax((double)m1[j], lo1), hi1);
-    const T at = (T)a, bt = (T)b;
-    m0[j] = at;
-    m1[j] = bt;
-    v[0] += (double)at * (double)at;
-    v[1] += (double)bt * (double)bt;
-    v[2] += (double)at * (double)bt;
+  for (long long j0 = bid * (long long)RB * EW_UNROLL + threadIdx.x; j0 < n; j0 += (long long)nb * RB * EW_UNROLL) {
+    T A[EW_UNROLL], B[EW_UNROLL];
+#pragma unroll
+    for (int u = 0; u < EW_UNROLL; ++u) {
+      const long long j = j0 + (long long)u * RB;
+      A[u] = j < n ? m0[j] : T(0);
+      B[u] = j < n ? m1[j] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < EW_UNROLL; ++u) {
+      const long long j = j0 + (long long)u * RB;
+      if (j >= n) continue;
+      const double a = fmin(fmax((double)A[u], lo0), hi0);
+      const double b = fmin(fmax((double)B[u], lo1), hi1);
+      const T at = (T)a, bt = (T)b;
+      m0[j] = at;
+      m1[j] = bt;
+      v[0] += (double)at * (double)at;
+      v[1] += (double)bt * (double)bt;
+      v[2] += (double)at * (double)bt;
+    }
   }
   block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, bid, nb);
 }

@@ -119,6 +119,10 @@ class JointRRCG:
     def _stream(self) -> int:
         return _stream(self.device)
 
+    def prepare(self, n_inner: int) -> None:
+        """Capture the graph of an outer step with n_inner CG steps ahead of its first use."""
+        L.check(L.lib().rrcg_prepare(self._h, int(n_inner)), "rrcg_prepare")
+
     def autotune(self, reps: int = 3) -> dict:
         """Choose the launch shape of the solver's products by timing CG steps (power-of-two
         plans); the solver state is restored afterwards."""
@@ -230,6 +234,10 @@ class JointRRCGGroup:
 
     def m(self, i: int):
         return self.inv[i].m
+
+    def prepare(self, n_inner: int) -> None:
+        """Capture the graph of an outer step with n_inner CG steps ahead of its first use."""
+        L.check(L.lib().rrcg_group_prepare(self._h, int(n_inner)), "rrcg_group_prepare")
 
     def step(self, n_inner: int = 1) -> None:
         """One outer step of every inversion (asynchronous)."""
