@@ -11,6 +11,30 @@
 
 namespace bttb {
 
+// Copy of a descriptor that stays constant for a launch (a table entry written by the host
+// before it), at an address that is the same for the whole block: through the constant
+// address space the compiler reads it with scalar loads once, into scalar registers,
+// instead of one vector load per field at each use (whose waits would also wait for every
+// load issued before them).
+template <typename S>
+__device__ __forceinline__ S launch_const(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "descriptor of whole words");
+  S out;
+#if __HIP_DEVICE_COMPILE__
+  using W = const __attribute__((address_space(4))) unsigned int;
+  W* src = (W*)p;
+  unsigned int* dst = reinterpret_cast<unsigned int*>(&out);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(S) / 4); ++k) dst[k] = src[k];
+#else
+  out = *p;  // (the host pass only parses device code)
+#endif
+  return out;
+}
+
+// A value that is the same in every lane, kept in a scalar register.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Records `msg` as the calling thread's last error and returns `status`.
 int fail(int status, const std::string& msg);
 // Maps a HIP error to BTTB_EHIP with a message naming `what`.

@@ -79,30 +79,63 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
   cx<T> v[8];
   double acc[2] = {0.0, 0.0};
   if constexpr (MODE == FUSE_DIR) {
+    // The loads of the prologue go out before any store of the new direction (vector memory
+    // operations complete in issue order, so a load issued after a store could only be
+    // waited for together with it), half of a thread's entries (4 h .. 4 h + 3, both rows)
+    // at a time; the first half before the partial sums of beta, whose loads then overlap
+    // them.  The upper half is empty when a row fills at most half the transform.
+    const T* lv = fz.l + lofs;
+    T* pv = fz.p + lofs;
+    T LA[4], LB[4], PA[4], PB[4], SA[4], SB[4];
+    auto dir_load = [&](int h) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = t + (4 * h + i) * TPF;
+        const bool ok = n < a.ncols;
+        const long long oa = (long long)r0 * a.ncols + n;
+        LA[i] = gload_or(lv, oa, ok && ra);
+        PA[i] = gload_or(pv, oa, ok && ra);
+        SA[i] = gload_or(sc, oa, ok && ra);
+        LB[i] = gload_or(lv, oa + a.ncols, ok && rb);
+        PB[i] = gload_or(pv, oa + a.ncols, ok && rb);
+        SB[i] = gload_or(sc, oa + a.ncols, ok && rb);
+      }
+    };
+    dir_load(0);
     double bt[2], L[2];
     beta_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.restart, fz.coupled, bt, L);
     if (fz.lead && pid == 0 && threadIdx.x == 0) record_beta(fz.sc, bt, L);
     const double beta = fz.self == 0 ? bt[0] : bt[1];
-    const T* lv = fz.l + lofs;
-    T* pv = fz.p + lofs;
-    auto dir = [&](long long o) -> T {
-      const double lo = lv[o];
-      const T pn = (T)(lo + beta * (double)pv[o]);
-      pv[o] = pn;
-      acc[0] += (double)pn * lo;
-      acc[1] += (double)pn * (double)pn;
-      return pn * sc[o];
-    };
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      T xa = T(0), xb = T(0);
-      if (n < a.ncols) {
-        const long long oa = (long long)r0 * a.ncols + n;
-        if (ra) xa = dir(oa);
-        if (rb) xb = dir(oa + a.ncols);
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1) {
+        if (t + 4 * TPF < a.ncols) dir_load(1);
       }
-      v[i] = cx<T>{xa, xb};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = t + (4 * h + i) * TPF;
+        T xa = T(0), xb = T(0);
+        if (n < a.ncols) {
+          const long long oa = (long long)r0 * a.ncols + n;
+          if (ra) {
+            const double lo = LA[i];
+            const T pn = (T)(lo + beta * (double)PA[i]);
+            gstore(pv + oa, pn);
+            acc[0] += (double)pn * lo;
+            acc[1] += (double)pn * (double)pn;
+            xa = pn * SA[i];
+          }
+          if (rb) {
+            const double lo = LB[i];
+            const T pn = (T)(lo + beta * (double)PB[i]);
+            gstore(pv + oa + a.ncols, pn);
+            acc[0] += (double)pn * lo;
+            acc[1] += (double)pn * (double)pn;
+            xb = pn * SB[i];
+          }
+        }
+        v[4 * h + i] = cx<T>{xa, xb};
+      }
     }
   } else {
 #pragma unroll
@@ -111,8 +144,8 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
       T xa = T(0), xb = T(0);
       if (n < a.ncols) {
         const long long oa = (long long)r0 * a.ncols + n;
-        if (ra) xa = sc ? src[oa] * sc[oa] : src[oa];
-        if (rb) xb = sc ? src[oa + a.ncols] * sc[oa + a.ncols] : src[oa + a.ncols];
+        if (ra) xa = sc ? gload(src + oa) * gload(sc + oa) : gload(src + oa);
+        if (rb) xb = sc ? gload(src + oa + a.ncols) * gload(sc + oa + a.ncols) : gload(src + oa + a.ncols);
       }
       v[i] = cx<T>{xa, xb};
     }
@@ -140,8 +173,8 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     for (int i = 0; i < 5; ++i) {
       const int k = t + i * TPF;
       if (k <= N / 2) {
-        if (ra) dst[k] = xa[i];
-        if (rb) dst[a.ld + k] = xb[i];
+        if (ra) gstore(dst + k, xa[i]);
+        if (rb) gstore(dst + a.ld + k, xb[i]);
       }
     }
     return;
@@ -161,7 +194,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
   const int rows = min(RT, a.nrows - tile * RT);
   for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
     const int k2 = idx / RT, rr = idx - k2 * RT;
-    if (rr < rows) dst[(long long)k2 * a.ld + rr] = smem[(rr >> 1) * BS + (rr & 1) * K2 + k2];
+    if (rr < rows) gstore(dst + (long long)k2 * a.ld + rr, smem[(rr >> 1) * BS + (rr & 1) * K2 + k2]);
   }
   if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0, pid, pcount);
 }
@@ -197,28 +230,33 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   RegFFT<T, N> F;
   F.init(a.tw, t);
   double gg[3] = {0.0, 0.0, 0.0};  // Gramian scalars for the gradient form
-  if constexpr (MODE == FUSE_GRAD) gram_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lead && pid == 0, gg);
   const int r0 = tile * RT + 2 * f;
   const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
+  const long long lofs = (long long)l * a.nrows * a.ncols;
+  const T* sc = a.scale ? a.scale + lofs : nullptr;
   cx<T> v[8];
   if constexpr (ROWIN) {
-    const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + ((long long)l * a.nrows + r0) * a.ld;
+    // base: the start of this batch entry (valid for every lane); rows r0, r0 + 1 may lie
+    // beyond nrows, where the guarded loads read the base instead
+    const cx<T>* base = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs;
+    const long long off = ((long long)l * a.nrows + r0) * a.ld;
+    const cx<T>* src = base + off;
     cx<T> ha[8], hb[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int k = t + i * TPF;
       const int kk = k <= N / 2 ? k : N - k;
-      ha[i] = ra ? src[kk] : cx<T>{T(0), T(0)};
-      hb[i] = rb ? src[a.ld + kk] : cx<T>{T(0), T(0)};
+      ha[i] = gload_or(base, off + kk, ra);
+      hb[i] = gload_or(base, off + a.ld + kk, rb);
     }
     for (int c = 1; c < a.nsum; ++c) {  // partials of the layer chunks, summed in order
-      const cx<T>* sc = src + c * a.in_cs;
+      const cx<T>* part = src + c * a.in_cs;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = t + i * TPF;
         const int kk = k <= N / 2 ? k : N - k;
-        if (ra) ha[i] = cadd(ha[i], sc[kk]);
-        if (rb) hb[i] = cadd(hb[i], sc[a.ld + kk]);
+        if (ra) ha[i] = cadd(ha[i], gload(part + kk));
+        if (rb) hb[i] = cadd(hb[i], gload(part + a.ld + kk));
       }
     }
 #pragma unroll
@@ -243,8 +281,10 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     for (int it = 0; it < ITER; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
       const int k2 = idx / RT, rr = idx - k2 * RT;
-      hv[it] = (idx < K2 * RT && rr < rows) ? src[(long long)k2 * a.ld + rr] : cx<T>{T(0), T(0)};
+      hv[it] = gload_or(src, (long long)k2 * a.ld + rr, idx < K2 * RT && rr < rows);
     }
+    // the Gramian scalars' partials, loaded while the spectra are in flight
+    if constexpr (MODE == FUSE_GRAD) gram_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lead && pid == 0, gg);
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
@@ -269,12 +309,20 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   }
   gsync();
   F.template run<true>(v, buf, t, gsync);
-  const long long lofs = (long long)l * a.nrows * a.ncols;
   T* dst = reinterpret_cast<T*>(a.out) + b * a.out_bs + lofs;
-  const T* sc = a.scale ? a.scale + lofs : nullptr;
   if constexpr (MODE == FUSE_GRAD) {
-    const double al = fz.sc[S_ALPHA + fz.self], lam = fz.self == 0 ? fz.lam[0] : fz.lam[1];
+    const bool s0 = fz.self == 0;
+    const double al = gload(fz.sc + S_ALPHA + fz.self), lam = s0 ? fz.lam[0] : fz.lam[1];
     const double g11 = gg[0], g22 = gg[1], g12 = gg[2];
+    const T* m0p = fz.m[0] + lofs;
+    const T* m1p = fz.m[1] + lofs;
+    const T* wsp = (s0 ? fz.w[0] : fz.w[1]) + lofs;
+    const T* wop = (s0 ? fz.w[1] : fz.w[0]) + lofs;
+    const T* map = fz.ma ? fz.ma + lofs : nullptr;
+    auto grad_at = [&](long long o, T zt) -> T {
+      return grad_value<T>(s0, fz.gram_w, zt, gload(m0p + o), gload(m1p + o), gload(wsp + o),
+                           fz.gram_w ? gload(wop + o) : T(0), map ? gload(map + o) : T(0), al, lam, g11, g22, g12);
+    };
     double acc[1] = {0.0};
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -282,13 +330,13 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       if (q < a.ncols) {
         const long long o = (long long)r0 * a.ncols + q;
         if (ra) {
-          const T g = grad_element(fz, lofs + o, v[i].re * sc[o], al, lam, g11, g22, g12);
-          dst[o] = g;
+          const T g = grad_at(o, v[i].re * gload(sc + o));
+          gstore(dst + o, g);
           acc[0] += (double)g * (double)g;
         }
         if (rb) {
-          const T g = grad_element(fz, lofs + o + a.ncols, v[i].im * sc[o + a.ncols], al, lam, g11, g22, g12);
-          dst[o + a.ncols] = g;
+          const T g = grad_at(o + a.ncols, v[i].im * gload(sc + o + a.ncols));
+          gstore(dst + o + a.ncols, g);
           acc[0] += (double)g * (double)g;
         }
       }
@@ -303,13 +351,13 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     if (q < a.ncols) {
       const long long o = (long long)r0 * a.ncols + q;
       if (ra) {
-        const T y = sc ? v[i].re * sc[o] : v[i].re;
-        dst[o] = y;
+        const T y = sc ? v[i].re * gload(sc + o) : v[i].re;
+        gstore(dst + o, y);
         if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
       }
       if (rb) {
-        const T y = sc ? v[i].im * sc[o + a.ncols] : v[i].im;
-        dst[o + a.ncols] = y;
+        const T y = sc ? v[i].im * gload(sc + o + a.ncols) : v[i].im;
+        gstore(dst + o + a.ncols, y);
         if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
       }
     }
@@ -360,10 +408,18 @@ struct AccPair {
   A x, y;
 };
 
+// One layer's prefetched operands of a column pass.
+template <typename T, bool COL, bool PACKED>
+struct ColBuf {
+  cx<T> un[COL ? 8 : 1], en[8], enN[PACKED ? 8 : 1];
+};
+
 // Layer loop of the forward column pass for one group: acc += eig_l . FFT_x(column_l)
 // (PACKED: eig0 . X0 + i eigN . XN from the packed pair of real columns).  The next
 // layer's eigenvalues (and in FP32 its column) are loaded while the current one is
-// transformed; FP64 keeps the column load in place to stay within 256 registers.
+// transformed; FP64 keeps the column load in place to stay within 256 registers.  (A second
+// layer in flight was measured slower: the extra registers cost more than the latency they
+// hide.)
 template <typename T, int N, bool PACKED>
 __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
                                            int G, int k2, int l0, int l1, int b,
@@ -380,34 +436,35 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
   const cx<T>* egN = a.eig + (long long)kN * N;
   const long long lstride_in = (long long)a.K2 * a.ldin, lstride_e = (long long)a.K2 * N;
   const int nit = (l1 - l0 + G - 1) / G;
-  cx<T> un[PF_IN ? 8 : 1], en[8], enN[PACKED ? 8 : 1];
+  using Buf = ColBuf<T, PF_IN, PACKED>;
   auto load_col = [&](int l, int i) -> cx<T> {
     const int n = t + i * TPF;
-    if (l >= l1 || n >= a.nin) return cx<T>{T(0), T(0)};
-    if constexpr (PACKED) return cx<T>{src[l * lstride_in + n].re, srcN[l * lstride_in + n].re};
-    return src[l * lstride_in + n];
+    const bool ok = l < l1 && n < a.nin;
+    if constexpr (PACKED)  // the real parts only
+      return cx<T>{gload_or(reinterpret_cast<const T*>(src), 2 * (l * lstride_in + n), ok),
+                   gload_or(reinterpret_cast<const T*>(srcN), 2 * (l * lstride_in + n), ok)};
+    return gload_or(src, l * lstride_in + n, ok);
   };
-  auto fetch = [&](int l) {
+  auto fetch = [&](Buf& B, int l) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      if constexpr (PF_IN) un[i] = load_col(l, i);
-      en[i] = l < l1 ? eg[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
-      if constexpr (PACKED) enN[i] = l < l1 ? egN[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
+      if constexpr (PF_IN) B.un[i] = load_col(l, i);
+      B.en[i] = gload_or(eg, l * lstride_e + t + i * TPF, l < l1);
+      if constexpr (PACKED) B.enN[i] = gload_or(egN, l * lstride_e + t + i * TPF, l < l1);
     }
   };
-  fetch(l0 + f);
-  for (int it = 0; it < nit; ++it) {
+  auto layer = [&](int it, Buf& B) {
     const int l = l0 + it * G + f;
     const bool act = l < l1;
     cx<T> v[8], e[8], eN[PACKED ? 8 : 1];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      if constexpr (PF_IN) v[i] = un[i];
+      if constexpr (PF_IN) v[i] = B.un[i];
       else v[i] = load_col(l, i);
-      e[i] = en[i];
-      if constexpr (PACKED) eN[i] = enN[i];
+      e[i] = B.en[i];
+      if constexpr (PACKED) eN[i] = B.enN[i];
     }
-    if (it + 1 < nit) fetch(l + G);
+    if (it + 1 < nit) fetch(B, l + G);
     F.template run<false>(v, buf, t, gsync);
     if constexpr (PACKED) {
 #pragma unroll
@@ -438,7 +495,10 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
         ai[i] += wr * xi + wi * xr;
       }
     }
-  }
+  };
+  Buf B;
+  fetch(B, l0 + f);
+  for (int it = 0; it < nit; ++it) layer(it, B);
 }
 
 // Forward: partial over the layers of chunk c of sum_l eig_l . FFT_x(U_l column), then the
@@ -499,10 +559,10 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
         const int p = t + i * TPF;
         if (p < a.nout) {
           if (packed) {
-            dst[(long long)p * a.ldout] = cx<T>{v[i].re, T(0)};
-            dst[(long long)p * a.ldout + kN] = cx<T>{v[i].im, T(0)};
+            gstore(dst + (long long)p * a.ldout, cx<T>{v[i].re, T(0)});
+            gstore(dst + (long long)p * a.ldout + kN, cx<T>{v[i].im, T(0)});
           } else {
-            dst[(long long)p * a.ldout + k2] = v[i];
+            gstore(dst + (long long)p * a.ldout + k2, v[i]);
           }
         }
       }
@@ -517,7 +577,8 @@ __global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_fwd(FColArgs<T>
 }
 
 // Layer loop of the transpose column pass for one group: per layer conj(eig_l) R (PACKED:
-// conj(eig0) R0 + i conj(eigN) RN), inverse FFT_x, rows a < nout stored.
+// conj(eig0) R0 + i conj(eigN) RN), inverse FFT_x, rows a < nout stored.  The next layer's
+// eigenvalues are loaded while the current one is transformed.
 template <typename T, int N, bool PACKED>
 __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
                                            int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8],
@@ -531,16 +592,15 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
   cx<T>* dstN = a.out + b * a.out_bs + (long long)kN * a.ldout;
   const long long lstride_out = (long long)a.K2 * a.ldout, lstride_e = (long long)a.K2 * N;
   const int nit = (l1 - l0 + G - 1) / G;
-  cx<T> en[8], enN[PACKED ? 8 : 1];
-  auto fetch = [&](int l) {
+  using Buf = ColBuf<T, false, PACKED>;
+  auto fetch = [&](Buf& B, int l) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      en[i] = l < l1 ? eg[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
-      if constexpr (PACKED) enN[i] = l < l1 ? egN[l * lstride_e + t + i * TPF] : cx<T>{T(0), T(0)};
+      B.en[i] = gload_or(eg, l * lstride_e + t + i * TPF, l < l1);
+      if constexpr (PACKED) B.enN[i] = gload_or(egN, l * lstride_e + t + i * TPF, l < l1);
     }
   };
-  fetch(l0 + f);
-  for (int it = 0; it < nit; ++it) {
+  auto layer = [&](int it, Buf& B) {
     const int l = l0 + it * G + f;
     const bool act = l < l1;
     cx<T> v[8];
@@ -552,14 +612,14 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
         const T h = T(0.5);
         const cx<T> r0{h * (A.re + C.re), h * (A.im - C.im)};
         const cx<T> rn{h * (A.im + C.im), h * (C.re - A.re)};
-        const cx<T> p0 = cmulc(r0, en[i]), pn = cmulc(rn, enN[i]);
+        const cx<T> p0 = cmulc(r0, B.en[i]), pn = cmulc(rn, B.enN[i]);
         v[i] = cx<T>{p0.re - pn.im, p0.im + pn.re};
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], en[i]);
+      for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], B.en[i]);
     }
-    if (it + 1 < nit) fetch(l + G);
+    if (it + 1 < nit) fetch(B, l + G);
     F.template run<true>(v, buf, t, gsync);
     if (act) {
 #pragma unroll
@@ -567,15 +627,18 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
         const int p = t + i * TPF;
         if (p < a.nout) {
           if constexpr (PACKED) {
-            dst[l * lstride_out + p] = cx<T>{v[i].re, T(0)};
-            dstN[l * lstride_out + p] = cx<T>{v[i].im, T(0)};
+            gstore(dst + l * lstride_out + p, cx<T>{v[i].re, T(0)});
+            gstore(dstN + l * lstride_out + p, cx<T>{v[i].im, T(0)});
           } else {
-            dst[l * lstride_out + p] = v[i];
+            gstore(dst + l * lstride_out + p, v[i]);
           }
         }
       }
     }
-  }
+  };
+  Buf B;
+  fetch(B, l0 + f);
+  for (int it = 0; it < nit; ++it) layer(it, B);
 }
 
 // Transpose: R = FFT_x(Rrow column) once per block (group 0, shared through LDS), then for
@@ -603,7 +666,10 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int
     for (int i = 0; i < 8; ++i) {
       const int n = t + i * TPF;
       const long long o = (long long)n * a.ldin;
-      R[i] = n >= a.nin ? cx<T>{T(0), T(0)} : (packed ? cx<T>{col[o].re, col[o + kN].re} : col[o + k2]);
+      R[i] = n >= a.nin ? cx<T>{T(0), T(0)}
+                        : (packed ? cx<T>{gload(reinterpret_cast<const T*>(col + o)),
+                                          gload(reinterpret_cast<const T*>(col + o + kN))}
+                                  : gload(col + o + k2));
     }
     F.template run<false>(R, buf, t, gsync);
     if (f == 0) {

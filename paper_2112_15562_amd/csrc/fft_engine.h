@@ -21,6 +21,46 @@ struct cx {
   T re, im;
 };
 
+// Loads and stores through the global address space.  Most kernel pointers arrive through
+// descriptor tables, which leaves the compiler unable to tell them from LDS pointers; it
+// would then use flat instructions, which count against the LDS / scalar-load counter as
+// well, so that every LDS exchange or scalar wait would also wait for them.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  const v2 x = *(const __attribute__((address_space(1))) v2*)p;
+  return cx<T>{x.x, x.y};
+}
+// p[i] when ok, else z, without a branch: a lane that is out of range loads p[0] (which
+// exists) and discards it, so a thread's guarded loads issue back to back instead of one
+// exec-masked block each, with the conversions the compiler would place inside them.
+template <typename T>
+__device__ __forceinline__ T gload_or(const T* p, long long i, bool ok, T z = T(0)) {
+  const T x = gload(p + (ok ? i : 0));
+  return ok ? x : z;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> gload_or(const cx<T>* p, long long i, bool ok) {
+  const cx<T> x = gload(p + (ok ? i : 0));
+  return ok ? x : cx<T>{T(0), T(0)};
+}
+template <typename T>
+__device__ __forceinline__ void gstore(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  v2 x;
+  x.x = v.re;
+  x.y = v.im;
+  *(__attribute__((address_space(1))) v2*)p = x;
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <typename T>

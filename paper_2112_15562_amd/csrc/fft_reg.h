@@ -62,7 +62,7 @@ struct RegFFT {
       for (int b = 0; b < BPT; ++b) {
         const int k = (t + b * TPF) & (NS - 1);
 #pragma unroll
-        for (int r = 1; r < R; ++r) w[OFF + b * (R - 1) + r - 1] = tab[r * k * (N / (NS * R))];
+        for (int r = 1; r < R; ++r) w[OFF + b * (R - 1) + r - 1] = gload(tab + r * k * (N / (NS * R)));
       }
       init_pass<PS + 1>(tab, t);
     }

@@ -29,7 +29,7 @@ __device__ __forceinline__ int group_member(const int* start, int count, int blk
 
 template <typename T, int MODE>
 __device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
-  if constexpr (MODE != FUSE_NONE) return g.fz[i];
+  if constexpr (MODE != FUSE_NONE) return launch_const(g.fz + i);
   return Fuse<T>{};
 }
 
@@ -38,19 +38,19 @@ __device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
 template <typename T, int N, bool ROWOUT, int MODE>
 __global__ void __launch_bounds__(512) k_grow_r2c(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int k = group_member(g.start, g.count, blockIdx.x);
-  const int i = g.idx[k];
-  const GMember<T>& M = g.mem[i];
+  const int k = uniform(group_member(g.start, g.count, blockIdx.x));
+  const int i = uniform(g.idx[k]);
+  const GMember<T> M = launch_const(g.mem + i);
   const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
   constexpr int G1 = N / 8;
   const int G = g.bt / G1;
-  const T* in = g.in[i];
+  const T* in = launch_const(g.in + i);
   FRowArgs<T> a;
   if constexpr (!ROWOUT) {
-    a = FRowArgs<T>{in, 0, g.winv ? g.winv[i] : nullptr, M.U, 0, 0, 1, M.nz, M.nx, M.ny, M.ldx, M.K2, G,
+    a = FRowArgs<T>{in, 0, g.winv ? launch_const(g.winv + i) : nullptr, M.U, 0, 0, 1, M.nz, M.nx, M.ny, M.ldx, M.K2, G,
                     (M.nx + 2 * G - 1) / (2 * G), M.twy};
   } else {
-    a = FRowArgs<T>{in, 0, g.wd ? g.wd[i] : nullptr, M.V, 0, 0, 1, 1, M.sx, M.sy, M.ldk, M.K2, G,
+    a = FRowArgs<T>{in, 0, g.wd ? launch_const(g.wd + i) : nullptr, M.V, 0, 0, 1, 1, M.sx, M.sy, M.ldk, M.K2, G,
                     (M.sx + 2 * G - 1) / (2 * G), M.twy};
   }
   const Fuse<T> fz = member_fuse<T, MODE>(g, i);
@@ -62,18 +62,18 @@ __global__ void __launch_bounds__(512) k_grow_r2c(GLaunch<T> g) {
 template <typename T, int N, bool ROWIN, int MODE>
 __global__ void __launch_bounds__(512) k_grow_c2r(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int k = group_member(g.start, g.count, blockIdx.x);
-  const int i = g.idx[k];
-  const GMember<T>& M = g.mem[i];
+  const int k = uniform(group_member(g.start, g.count, blockIdx.x));
+  const int i = uniform(g.idx[k]);
+  const GMember<T> M = launch_const(g.mem + i);
   const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
   const int G = g.bt / (N / 8);
-  T* out = g.out[i];
+  T* out = launch_const(g.out + i);
   FRowArgs<T> a;
   if constexpr (ROWIN) {
-    a = FRowArgs<T>{reinterpret_cast<const T*>(M.V), 0, g.wd ? g.wd[i] : nullptr, reinterpret_cast<cx<T>*>(out), 0,
+    a = FRowArgs<T>{reinterpret_cast<const T*>(M.V), 0, g.wd ? launch_const(g.wd + i) : nullptr, reinterpret_cast<cx<T>*>(out), 0,
                     M.V_fcs, M.nchunk, 1, M.sx, M.sy, M.ldk, M.K2, G, (M.sx + 2 * G - 1) / (2 * G), M.twy};
   } else {
-    a = FRowArgs<T>{reinterpret_cast<const T*>(M.U), 0, g.winv ? g.winv[i] : nullptr,
+    a = FRowArgs<T>{reinterpret_cast<const T*>(M.U), 0, g.winv ? launch_const(g.winv + i) : nullptr,
                     reinterpret_cast<cx<T>*>(out), 0, 0, 1, M.nz, M.nx, M.ny, M.ldx, M.K2, G,
                     (M.nx + 2 * G - 1) / (2 * G), M.twy};
   }
@@ -86,9 +86,9 @@ __global__ void __launch_bounds__(512) k_grow_c2r(GLaunch<T> g) {
 template <typename T, int N, bool FWD>
 __global__ void __launch_bounds__(col_threads(sizeof(T))) k_gcol(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int k = group_member(g.start, g.count, blockIdx.x);
-  const int i = g.idx[k];
-  const GMember<T>& M = g.mem[i];
+  const int k = uniform(group_member(g.start, g.count, blockIdx.x));
+  const int i = uniform(g.idx[k]);
+  const GMember<T> M = launch_const(g.mem + i);
   const int local = blockIdx.x - g.start[k];
   const int jobs = M.K2 - 1;
   const int c = local / jobs, job = local - c * jobs;

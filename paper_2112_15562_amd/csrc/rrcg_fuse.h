@@ -75,8 +75,8 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* 
     for (int k = 0; k < K; ++k) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += sh[k][w];
-      pb[(slot0 + k) * pbs + bid] = s;
-      if (bid == 0) pbn[slot0 + k] = nb;
+      gstore(pb + (slot0 + k) * pbs + bid, s);
+      if (bid == 0) gstore(pbn + slot0 + k, nb);
     }
   }
 }
@@ -117,10 +117,10 @@ __device__ __forceinline__ void slot_totals(const double* pb, const int* pbn, in
                                             double (&out)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int n = pbn[slot[k]];
+    const int n = gload(pbn + slot[k]);
     const double* src = pb + (long long)slot[k] * pbs;
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += src[i];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += gload(src + i);
     out[k] = s;
   }
   block_allreduce<K>(out);
@@ -131,7 +131,7 @@ __device__ __forceinline__ void beta_from(const double* sc, const double* pb, co
                                           int restart, int coupled, double (&beta)[2], double (&L)[2]) {
   const int sl[2] = {PB_L0, PB_L1};
   slot_totals<2>(pb, pbn, pbs, sl, L);
-  const double P0 = sc[S_LPREV], P1 = sc[S_LPREV + 1];
+  const double P0 = gload(sc + S_LPREV), P1 = gload(sc + S_LPREV + 1);
   if (coupled) {
     const double Lp = P0 + P1;
     beta[0] = beta[1] = (restart || Lp == 0.0) ? 0.0 : (L[0] + L[1]) / Lp;
@@ -142,11 +142,11 @@ __device__ __forceinline__ void beta_from(const double* sc, const double* pb, co
 }
 
 __device__ __forceinline__ void record_beta(double* sc, const double (&beta)[2], const double (&L)[2]) {
-  sc[S_L] = L[0];
-  sc[S_L + 1] = L[1];
-  sc[S_BETA] = beta[0];
-  sc[S_BETA + 1] = beta[1];
-  if (!isfinite(L[0]) || !isfinite(L[1])) sc[S_NONFIN] = 1.0;
+  gstore(sc + S_L, L[0]);
+  gstore(sc + S_L + 1, L[1]);
+  gstore(sc + S_BETA, beta[0]);
+  gstore(sc + S_BETA + 1, beta[1]);
+  if (!isfinite(L[0]) || !isfinite(L[1])) gstore(sc + S_NONFIN, 1.0);
 }
 
 // RRCG:6: s = sum (p,l) / sum (||A~ p||^2 + (alpha + lambda) ||p||^2), joint when coupled.
@@ -157,8 +157,8 @@ __device__ __forceinline__ void step_from(double* sc, const double* pb, const in
   const int sl[6] = {PB_PL0, PB_PL1, PB_PP0, PB_PP1, PB_Q0, PB_Q1};
   double t[6];
   slot_totals<6>(pb, pbn, pbs, sl, t);
-  const double den0 = t[4] + (sc[S_ALPHA] + lam0) * t[2];
-  const double den1 = t[5] + (sc[S_ALPHA + 1] + lam1) * t[3];
+  const double den0 = t[4] + (gload(sc + S_ALPHA) + lam0) * t[2];
+  const double den1 = t[5] + (gload(sc + S_ALPHA + 1) + lam1) * t[3];
   if (coupled) {
     s[0] = s[1] = (t[0] + t[1]) / (den0 + den1);
   } else {
@@ -166,14 +166,17 @@ __device__ __forceinline__ void step_from(double* sc, const double* pb, const in
     s[1] = t[1] / den1;
   }
   if (record && threadIdx.x == 0) {
-    sc[S_STEP] = s[0];
-    sc[S_STEP + 1] = s[1];
-    sc[S_PL] = t[0]; sc[S_PL + 1] = t[1];
-    sc[S_PP] = t[2]; sc[S_PP + 1] = t[3];
-    sc[S_QQ] = t[4]; sc[S_QQ + 1] = t[5];
-    sc[S_LPREV] = sc[S_L];
-    sc[S_LPREV + 1] = sc[S_L + 1];
-    if (!isfinite(s[0]) || !isfinite(s[1])) sc[S_NONFIN] = 1.0;
+    gstore(sc + S_STEP, s[0]);
+    gstore(sc + S_STEP + 1, s[1]);
+    gstore(sc + S_PL, t[0]);
+    gstore(sc + S_PL + 1, t[1]);
+    gstore(sc + S_PP, t[2]);
+    gstore(sc + S_PP + 1, t[3]);
+    gstore(sc + S_QQ, t[4]);
+    gstore(sc + S_QQ + 1, t[5]);
+    gstore(sc + S_LPREV, gload(sc + S_L));
+    gstore(sc + S_LPREV + 1, gload(sc + S_L + 1));
+    if (!isfinite(s[0]) || !isfinite(s[1])) gstore(sc + S_NONFIN, 1.0);
   }
 }
 
@@ -183,35 +186,30 @@ __device__ __forceinline__ void gram_from(double* sc, const double* pb, const in
   const int sl[3] = {PB_G11, PB_G22, PB_G12};
   slot_totals<3>(pb, pbn, pbs, sl, g);
   if (record && threadIdx.x == 0) {
-    sc[S_G11] = g[0];
-    sc[S_G22] = g[1];
-    sc[S_G12] = g[2];
-    if (!isfinite(g[0]) || !isfinite(g[1]) || !isfinite(g[2])) sc[S_NONFIN] = 1.0;
+    gstore(sc + S_G11, g[0]);
+    gstore(sc + S_G22, g[1]);
+    gstore(sc + S_G12, g[2]);
+    if (!isfinite(g[0]) || !isfinite(g[1]) || !isfinite(g[2])) gstore(sc + S_NONFIN, 1.0);
   }
 }
 
-// RRCG:4 for element j of data set `self`, given z~ = (A~^T r~)_j:
+// RRCG:4 for one element of data set `self`, given z~ = (A~^T r~)_j, the models a = m1_j,
+// b = m2_j, the weights ws (this data set) and wo (the other; read only when gram_w) and
+// ma = m_apr of this data set (0 when there is none):
 //   l = z~ + alpha (w m - w m_apr) + lambda l_G,
 //   l_G = (m2,m2) m1 - (m1,m2) m2 for data set 0, (m1,m1) m2 - (m1,m2) m1 for data set 1
 // (on w m instead of m when gram_w).
 template <typename T>
-__device__ __forceinline__ T grad_element(const Fuse<T>& fz, long long j, T zt, double al, double lam, double g11,
-                                          double g22, double g12) {
-  // pointers selected by condition, not by a run-time array index (which would put a
-  // private copy of the arguments in scratch memory)
-  const bool s0 = fz.self == 0;
-  const T* wself = s0 ? fz.w[0] : fz.w[1];
-  const double a = fz.m[0][j], b = fz.m[1][j];
-  const double Ws = wself[j];
+__device__ __forceinline__ T grad_value(bool s0, int gram_w, T zt, double a, double b, double Ws, double Wo,
+                                        double ma, double al, double lam, double g11, double g22, double g12) {
   double u0 = a, u1 = b;
-  if (fz.gram_w) {
-    const double Wo = (s0 ? fz.w[1] : fz.w[0])[j];
+  if (gram_w) {
     u0 = s0 ? Ws * a : Wo * a;
     u1 = s0 ? Wo * b : Ws * b;
   }
   const double lg = s0 ? g22 * u0 - g12 * u1 : g11 * u1 - g12 * u0;
   const double ms = s0 ? a : b;
-  const double mt = Ws * ms, mta = fz.ma ? Ws * (double)fz.ma[j] : 0.0;
+  const double mt = Ws * ms, mta = Ws * ma;
   return (T)((double)zt + al * (mt - mta) + lam * lg);
 }
 

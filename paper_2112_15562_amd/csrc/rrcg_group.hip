@@ -60,9 +60,9 @@ __device__ __forceinline__ int inversion_of(const GStart& st, int blk) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(RB) k_gweights(const GInv<T>* inv, GStart st) {
-  const int i = inversion_of(st, blockIdx.x);
-  const GInv<T>& v = inv[i];
+__global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gweights(const GInv<T>* inv, GStart st) {
+  const int i = uniform(inversion_of(st, blockIdx.x));
+  const GInv<T> v = launch_const(inv + i);
   const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
   weights_body<T>(v.n, v.m[0], v.m[1], v.mapr[0], v.mapr[1], v.wdepth[0], v.wdepth[1], v.whard[0], v.whard[1],
                   v.eps2, v.p_norm, v.gram_w, v.w[0], v.w[1], v.wi[0], v.wi[1], v.sc, Red{v.pb, v.pbn, v.pbs},
@@ -70,18 +70,18 @@ __global__ void __launch_bounds__(RB) k_gweights(const GInv<T>* inv, GStart st) 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(RB) k_gupdate(const GInv<T>* inv, GStart st) {
-  const int i = inversion_of(st, blockIdx.x);
-  const GInv<T>& v = inv[i];
+__global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gupdate(const GInv<T>* inv, GStart st) {
+  const int i = uniform(inversion_of(st, blockIdx.x));
+  const GInv<T> v = launch_const(inv + i);
   const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
   update_body<T>(v.n, v.nd, v.m[0], v.m[1], v.p[0], v.p[1], v.w[0], v.w[1], v.rt[0], v.rt[1], v.qv[0], v.qv[1],
                  v.sc, v.lam[0], v.lam[1], v.coupled, v.gram_w, Red{v.pb, v.pbn, v.pbs}, local, nb);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(RB) k_gclip(const GInv<T>* inv, GStart st, int advance) {
-  const int i = inversion_of(st, blockIdx.x);
-  const GInv<T>& v = inv[i];
+__global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gclip(const GInv<T>* inv, GStart st, int advance) {
+  const int i = uniform(inversion_of(st, blockIdx.x));
+  const GInv<T> v = launch_const(inv + i);
   const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
   if (advance)
     clip_body<T>(v.n, v.m[0], v.m[1], v.lo[0], v.hi[0], v.lo[1], v.hi[1], Red{v.pb, v.pbn, v.pbs}, local, nb);
@@ -90,16 +90,16 @@ __global__ void __launch_bounds__(RB) k_gclip(const GInv<T>* inv, GStart st, int
 }
 
 template <typename T>
-__global__ void __launch_bounds__(RB) k_gresid(const GInv<T>* inv, GStart st) {
-  const int i = inversion_of(st, blockIdx.x);
-  const GInv<T>& v = inv[i];
+__global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gresid(const GInv<T>* inv, GStart st) {
+  const int i = uniform(inversion_of(st, blockIdx.x));
+  const GInv<T> v = launch_const(inv + i);
   const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
   resid_body<T>(v.nd, v.rt[0], v.rt[1], v.dobs[0], v.dobs[1], v.wd[0], v.wd[1], Red{v.pb, v.pbn, v.pbs}, local, nb);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(RB) k_gfin_outer(const GInv<T>* inv, int advance) {  // one block per inversion
-  const GInv<T>& v = inv[blockIdx.x];
+  const GInv<T> v = launch_const(inv + blockIdx.x);
   fin_outer_body(v.sc, Red{v.pb, v.pbn, v.pbs}, v.q[0], v.q[1], v.amin[0], v.amin[1], advance, 0, 1);
 }
 
@@ -135,12 +135,12 @@ template <typename T>
 static int g_outer(RrcgGroup* h, hipStream_t s, int advance) {
   const GInv<T>* inv = static_cast<const GInv<T>*>(h->inv);
   const int nb = h->est.start[h->count];
-  hipLaunchKernelGGL(k_gclip<T>, dim3(nb), dim3(RB), 0, s, inv, h->est, advance);
+  hipLaunchKernelGGL(k_gclip<T>, dim3(nb), dim3(eb_threads(sizeof(T))), 0, s, inv, h->est, advance);
   BTTB_LAUNCHED("k_gclip");
   int rc = group_apply_impl<T>(h->grp, BTTB_OP_FORWARD, pa(h, PA_M), const_cast<void* const*>(pa(h, PA_RT)),
                                nullptr, nullptr, nullptr, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_gresid<T>, dim3(nb), dim3(RB), 0, s, inv, h->est);
+  hipLaunchKernelGGL(k_gresid<T>, dim3(nb), dim3(eb_threads(sizeof(T))), 0, s, inv, h->est);
   BTTB_LAUNCHED("k_gresid");
   hipLaunchKernelGGL(k_gfin_outer<T>, dim3(h->count), dim3(RB), 0, s, inv, advance);
   BTTB_LAUNCHED("k_gfin_outer");
@@ -149,7 +149,7 @@ static int g_outer(RrcgGroup* h, hipStream_t s, int advance) {
 
 template <typename T>
 static int g_weights(RrcgGroup* h, hipStream_t s) {
-  hipLaunchKernelGGL(k_gweights<T>, dim3(h->est.start[h->count]), dim3(RB), 0, s,
+  hipLaunchKernelGGL(k_gweights<T>, dim3(h->est.start[h->count]), dim3(eb_threads(sizeof(T))), 0, s,
                      static_cast<const GInv<T>*>(h->inv), h->est);
   BTTB_LAUNCHED("k_gweights");
   return BTTB_OK;
@@ -164,7 +164,7 @@ static int g_inner(RrcgGroup* h, int restart_now, hipStream_t s) {
   rc = group_apply_impl<T>(h->grp, BTTB_OP_FORWARD, pa(h, PA_P), const_cast<void* const*>(pa(h, PA_QV)),
                            pa(h, PA_WI), pa(h, PA_WD), fz, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_gupdate<T>, dim3(h->est.start[h->count]), dim3(RB), 0, s,
+  hipLaunchKernelGGL(k_gupdate<T>, dim3(h->est.start[h->count]), dim3(eb_threads(sizeof(T))), 0, s,
                      static_cast<const GInv<T>*>(h->inv), h->est);
   BTTB_LAUNCHED("k_gupdate");
   return BTTB_OK;
@@ -384,12 +384,13 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
 }
 
 static void elementwise_blocks(RrcgGroup* h) {
+  const int eb = eb_threads(h->precision == BTTB_F64 ? 8 : 4);
   h->est.count = h->count;
   h->est.start[0] = 0;
   for (int i = 0; i < h->count; ++i) {
     const long long top = std::max(h->n[i], h->nd[i]);
     const long long nb = std::min<long long>(RGRID, std::max<long long>(1, ceil_div((int)std::min<long long>(
-                                                                                top, 1LL << 30), RB * EW_UNROLL)));
+                                                                                top, 1LL << 30), eb * EW_UNROLL)));
     h->est.start[i + 1] = h->est.start[i] + (int)nb;
   }
 }

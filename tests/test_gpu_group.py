@@ -88,11 +88,14 @@ def test_group_products_match_oracle(pk, dtype, tol):
         assert rel(host(zs[i]), c[6]) <= tol, (i, "transpose")
         assert rel(host(yw[i]), c[7]) <= tol, (i, "weighted forward")
         assert rel(host(zw[i]), c[8]) <= tol, (i, "weighted transpose")
-    # the same plans one at a time: the transposes do the same arithmetic per element; the
-    # forward layer sums may group differently
+    # the same plans one at a time: the same operations per element, but the one-plan and the
+    # group kernels are separate instantiations, in which the compiler may fuse different
+    # products of a sum into an FMA (and the forward layer sums may group differently), so
+    # they agree to a few units in the last place, not bit for bit
+    same = 1e-14 if dtype == torch.float64 else 1e-6
     for i, op in enumerate(ops):
-        assert rel(host(op.matvec(xs[i])), host(ys[i])) <= (1e-14 if dtype == torch.float64 else 1e-6)
-        assert np.array_equal(host(op.rmatvec(rs[i])), host(zs[i]))
+        assert rel(host(op.matvec(xs[i])), host(ys[i])) <= same
+        assert rel(host(op.rmatvec(rs[i])), host(zs[i])) <= same
     grp.close()
     for op in ops:
         op.close()
