@@ -230,13 +230,14 @@ def traffic_for(kernel):
 def kernel_bytes(info, esz, weighted=True):
     """Bytes each product kernel must move per launch (batch 1): its inputs once and its
     outputs once, including the diagonal weights the weighted products (the solve's) read.
-    Complex values are 2 esz bytes."""
+    Complex values are 2 esz bytes; the eigenvalues are the plan's stored ones (real and
+    x-even for a symmetric operator)."""
     nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
-    Px, Py = info["Px"], info["Py"]
+    Py = info["Py"]
     K2 = Py // 2 + 1
     c = 2 * esz
     nch = info["layer_chunks"]
-    eig = nz * K2 * Px * c
+    eig = info["eig_bytes"]
     w = 2 if weighted else 1
     return {
         "fwd_row_r2c": w * nz * nx * ny * esz + nz * K2 * nx * c,
@@ -248,27 +249,31 @@ def kernel_bytes(info, esz, weighted=True):
     }
 
 
-def group_kernel_bytes(info, esz, members=2):
-    """Bytes each launch of the solver's product group must move (all members): as
-    kernel_bytes, plus the vectors the fused CG pieces read and write -- the direction
-    update in the forward row transform (reads l, p, 1/w, writes p) and the gradient in the
-    transpose's inverse row transform (reads m of both data sets, w, 1/w; writes l)."""
-    nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
-    Px, Py = info["Px"], info["Py"]
-    K2 = Py // 2 + 1
-    c = 2 * esz
-    n, nd = nz * nx * ny, sx * sy
-    eig = nz * K2 * Px * c
-    U = nz * K2 * nx * c
-    per = {
-        "fwd_row_r2c": 4 * n * esz + U,
-        "fwd_col_eig_sum": eig + U + K2 * sx * c,
-        "fwd_row_c2r": K2 * sx * c + 2 * nd * esz,
-        "adj_row_r2c": 2 * nd * esz + K2 * sx * c,
-        "adj_col_conj_eig": eig + K2 * sx * c + U,
-        "adj_row_c2r": U + 5 * n * esz,
-    }
-    return {k: members * v for k, v in per.items()}
+def group_kernel_bytes(infos, esz):
+    """Bytes each launch of the solver's product group must move (all members, one plan
+    info each): as kernel_bytes, plus the vectors the fused CG pieces read and write -- the
+    direction update in the forward row transform (reads l, p, 1/w, writes p) and the
+    gradient in the transpose's inverse row transform (reads m of both data sets, w, 1/w;
+    writes l)."""
+    tot = {}
+    for info in infos:
+        nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
+        K2 = info["Py"] // 2 + 1
+        c = 2 * esz
+        n, nd = nz * nx * ny, sx * sy
+        eig = info["eig_bytes"]
+        U = nz * K2 * nx * c
+        per = {
+            "fwd_row_r2c": 4 * n * esz + U,
+            "fwd_col_eig_sum": eig + U + K2 * sx * c,
+            "fwd_row_c2r": K2 * sx * c + 2 * nd * esz,
+            "adj_row_r2c": 2 * nd * esz + K2 * sx * c,
+            "adj_col_conj_eig": eig + K2 * sx * c + U,
+            "adj_row_c2r": U + 5 * n * esz,
+        }
+        for k, v in per.items():
+            tot[k] = tot.get(k, 0) + v
+    return tot
 
 
 def group_pair_rate(pk, torch, ops, pairs):
@@ -296,12 +301,12 @@ def group_pair_rate(pk, torch, ops, pairs):
     return n / (e0.elapsed_time(e1) / 1e3)
 
 
-def pair_bytes(info, esz):
-    """Algorithmic bytes of one operator pair: the eigenvalues read by both products,
-    the model read and written, the data written and read."""
-    nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
-    K2 = info["Py"] // 2 + 1
-    return 2 * nz * info["Px"] * K2 * 2 * esz + 2 * nx * ny * nz * esz + 2 * sx * sy * esz
+def pair_bytes(infos, esz):
+    """Algorithmic bytes of one operator pair, averaged over the operators: the stored
+    eigenvalues read by both products, the model read and written, the data written and
+    read."""
+    b = [2 * i["eig_bytes"] + 2 * i["nx"] * i["ny"] * i["nz"] * esz + 2 * i["sx"] * i["sy"] * esz for i in infos]
+    return sum(b) / len(b)
 
 
 def cpu_baseline(g, budget_s=12.0):
@@ -370,6 +375,7 @@ def main():
     sc32 = s32.scalars()
     s32.close()
     info32 = ops32[0].info()
+    infos32 = [op.info() for op in ops32]
     pairs = 2 * N_INNER * args.steps
     value = pairs / t32
 
@@ -400,7 +406,7 @@ def main():
             a[1] += n
     dom = max(tot, key=lambda k: tot[k][0])
     avg_ms = tot[dom][0] / max(tot[dom][1], 1)
-    gkb = group_kernel_bytes(info32, 4)
+    gkb = group_kernel_bytes(infos32, 4)
     kb = gkb[dom]
     achieved = kb / (avg_ms * 1e-3) / 1e9
     kernel_table = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "bytes": gkb[k],
@@ -418,6 +424,7 @@ def main():
         op.close()
     ops64 = [pk.Operator.from_geometry(k, g, dtype=torch.float64) for k in (pk.GRAVITY, pk.MAGNETIC)]
     info64 = ops64[0].info()
+    infos64 = [op.info() for op in ops64]
     rate64 = product_rate(torch, ops64, args.pairs)
     grate64 = group_pair_rate(pk, torch, ops64, args.pairs)
 
@@ -452,7 +459,7 @@ def main():
         log("bench: cpu oracle baseline")
         cpu = cpu_baseline(g)
 
-    b32, b64 = pair_bytes(info32, 4), pair_bytes(info64, 8)
+    b32, b64 = pair_bytes(infos32, 4), pair_bytes(infos64, 8)
     out = {
         "metric": METRIC,
         "value": value,

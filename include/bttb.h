@@ -75,6 +75,14 @@ typedef enum { BTTB_F64 = 0, BTTB_F32 = 1 } bttb_precision;
  * smallest 5-smooth multiples of 8, so that the plan takes the register-FFT kernels and
  * can join a group. */
 #define BTTB_PAD_POW2 0x10
+/* Flag or-ed into bttb_setup's precision: keep the full complex eigenvalues even when the
+ * operator is symmetric.  Without it, a power-of-two plan whose eigenvalues are real and
+ * even along x to 1e-14 (FP64) / 1e-6 (FP32) of their largest magnitude -- the case of a
+ * kernel even in both lags, e.g. gravity with the stations above the prism centres, in FP32
+ * (in FP64 its closed forms are symmetric only to their evaluation noise) --
+ * stores only Re lambda[0 .. Px/2] of each column (eig_real_even in bttb_plan_desc),
+ * which the column passes read instead of the complex array. */
+#define BTTB_EIG_FULL 0x20
 typedef enum { BTTB_GRAVITY = 0, BTTB_MAGNETIC = 1 } bttb_kind;
 typedef enum { BTTB_OP_FORWARD = 0, BTTB_OP_ADJOINT = 1 } bttb_op;
 
@@ -95,11 +103,13 @@ typedef struct {
   int Px, Py;              /* padded BCCB transform sizes (5-smooth multiples of 8) */
   int precision;           /* bttb_precision */
   int max_batch;
-  size_t eig_bytes;        /* bytes of the stored eigenvalues */
+  size_t eig_bytes;        /* bytes of the stored eigenvalues (see eig_real_even) */
   size_t scratch_bytes;    /* bytes of the product scratch */
   int col_fft_per_block;   /* launch shape in use (see bttb_set_launch) */
   int row_fft_per_block;
   int layer_chunks;
+  int eig_real_even;       /* 1: stored as real [nz][Py/2+1][Px/2+1] (symmetric operator,
+                              see BTTB_EIG_FULL); 0: complex [nz][Py/2+1][Px] */
 } bttb_plan_desc;
 
 /* Kernel array of eq. (d=gm) for one operator, computed on the GPU in FP64 from the
@@ -140,9 +150,9 @@ BTTB_API int bttb_set_launch(bttb_plan plan, int col_fft_per_block, int row_fft_
 
 BTTB_API int bttb_plan_info(bttb_plan plan, bttb_plan_desc* out);
 
-/* Copy the plan's eigenvalues (complex [nz][Py/2+1][Px] of the plan's type, interleaved
- * re, im, already scaled by 1/(Px Py); eig_bytes of bttb_plan_info) into the dev buffer
- * `out`, enqueued on `stream`.  For inspection and tests. */
+/* Copy the plan's eigenvalues as complex [nz][Py/2+1][Px] of the plan's type, interleaved
+ * re, im, already scaled by 1/(Px Py), into the dev buffer `out` (nz (Py/2+1) Px complex
+ * values; a real-even store is expanded), enqueued on `stream`.  For inspection and tests. */
 BTTB_API int bttb_plan_eigenvalues(bttb_plan plan, void* out, void* stream);
 
 BTTB_API int bttb_destroy(bttb_plan plan);

@@ -16,6 +16,7 @@ BTTB_F64, BTTB_F32 = 0, 1
 BTTB_GRAVITY, BTTB_MAGNETIC = 0, 1
 BTTB_OP_FORWARD, BTTB_OP_ADJOINT = 0, 1
 BTTB_PAD_POW2 = 0x10
+BTTB_EIG_FULL = 0x20
 MAX_TRANSFORM = 2048
 
 EXPORTED = [
@@ -50,7 +51,7 @@ class PlanDesc(C.Structure):
     _fields_ = [("sx", C.c_int), ("sy", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("Px", C.c_int), ("Py", C.c_int), ("precision", C.c_int), ("max_batch", C.c_int),
                 ("eig_bytes", C.c_size_t), ("scratch_bytes", C.c_size_t), ("col_fft_per_block", C.c_int),
-                ("row_fft_per_block", C.c_int), ("layer_chunks", C.c_int)]
+                ("row_fft_per_block", C.c_int), ("layer_chunks", C.c_int), ("eig_real_even", C.c_int)]
 
 
 class GroupDesc(C.Structure):

@@ -34,6 +34,12 @@ __device__ __forceinline__ S launch_const(const S* p) {
 
 // A value that is the same in every lane, kept in a scalar register.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // Records `msg` as the calling thread's last error and returns `status`.
 int fail(int status, const std::string& msg);
@@ -82,7 +88,9 @@ struct Plan {
   int nchunk_max;
   bool fast;        // both transform sizes are powers of two: register-resident kernels
   FFTDesc fx, fy;
-  void* eig;        // complex [nz][K2][Px] of the plan's type, scaled by 1/(Px Py)
+  void* eig;        // complex [nz][K2][Px] of the plan's type, scaled by 1/(Px Py); with
+                    // eig_even: real [nz][K2][Px/2 + 1]
+  int eig_even;     // the operator is symmetric: its eigenvalues are real and even along x
   void* twx;        // complex [Px] of the plan's type
   void* twy;        // complex [Py]
   void* U;          // complex [max_batch][nz][K2][ldx]
@@ -107,7 +115,7 @@ int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, 
                  const T* scale, int L, int nrows, int ncols, int ld, int N, int G, const cx<T>* tw, int batch,
                  hipStream_t s);
 template <typename T>
-int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs,
+int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, int eig_even, cx<T>* out, long long out_bs,
              long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
              const cx<T>* tw, int batch, hipStream_t s);
 

@@ -33,6 +33,25 @@ constexpr int row_buf() {  // per-group LDS elements of the row kernels (exchang
   return Pow2<N>::BUF > N + 2 ? Pow2<N>::BUF : N + 2;
 }
 
+#ifndef BTTB_ROW_WAVES32
+#define BTTB_ROW_WAVES32 8
+#endif
+#ifndef BTTB_GRAD_WAVES32
+#define BTTB_GRAD_WAVES32 6
+#endif
+// Waves per SIMD the row kernels are compiled for: in FP32 up to 512 points, eight, so that the
+// registers (at most 64) let four blocks of 512 threads share a CU and a whole product's row
+// blocks are resident at once.  Longer transforms hold more twiddles and keep the default.
+template <typename T, int N>
+constexpr int row_waves() { return sizeof(T) == 4 && N <= 512 ? BTTB_ROW_WAVES32 : 2; }
+// The inverse row transforms: the model-row ones as above, except the gradient form in the
+// full form, which needs more than 64 registers (six waves, three blocks per CU); the data-row
+// ones launch few blocks and keep their registers.
+template <typename T, int N, bool ROWIN, int MODE, bool HALF>
+constexpr int c2r_waves() {
+  return sizeof(T) != 4 || N > 512 || ROWIN ? 2 : MODE == FUSE_GRAD && !HALF ? BTTB_GRAD_WAVES32 : BTTB_ROW_WAVES32;
+}
+
 // ------------------------------------------------------------------------------------
 // Row transforms
 // ------------------------------------------------------------------------------------
@@ -56,10 +75,14 @@ struct FRowArgs {
 // written back, and the block partials of (p, l) and ||p||^2 are stored for the step length.
 // Block (bx, by) of the launch: bx = layer * tiles + tile, by = batch entry; pid and pcount
 // are this block's index and the block count for the partial sums of the fused form.
-template <typename T, int N, bool ROWOUT, int MODE>
+// HALF (a.ncols <= N/2): a lane's upper four inputs (index >= N/2) are zero padding, known
+// at compile time, so the first radix-8 pass folds them away.
+template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
 __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T>& fz, int bx, int by, int pid,
                                               int pcount, unsigned char* smem_raw) {
   static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT), "fused form");
+  // (the direction form takes the full form: with the half one it needs more than 64 registers)
+  static_assert(!(MODE == FUSE_DIR && HALF), "direction form in the half form");
   using P = Pow2<N>;
   constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
@@ -71,7 +94,6 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
   cx<T>* buf = smem + f * BS;
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
-  F.init(a.tw, t);
   const long long lofs = (long long)l * a.nrows * a.ncols;
   const T* src = a.in + b * a.in_bs + lofs;
   const T* sc = a.scale ? a.scale + lofs : nullptr;
@@ -142,7 +164,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     for (int i = 0; i < 8; ++i) {
       const int n = t + i * TPF;
       T xa = T(0), xb = T(0);
-      if (n < a.ncols) {
+      if ((!HALF || i < 4) && n < a.ncols) {
         const long long oa = (long long)r0 * a.ncols + n;
         if (ra) xa = sc ? gload(src + oa) * gload(sc + oa) : gload(src + oa);
         if (rb) xb = sc ? gload(src + oa + a.ncols) * gload(sc + oa + a.ncols) : gload(src + oa + a.ncols);
@@ -150,6 +172,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
       v[i] = cx<T>{xa, xb};
     }
   }
+  F.init(a.tw, t);  // twiddles loaded here: not live during the prologue
   F.template run<false>(v, buf, t, gsync);
   // X_a[k] = (Z[k] + conj Z[N-k]) / 2,  X_b[k] = (Z[k] - conj Z[N-k]) / (2i),  k <= N/2
 #pragma unroll
@@ -199,11 +222,11 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
   if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0, pid, pcount);
 }
 
-template <typename T, int N, bool ROWOUT, int MODE>
-__global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
+template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
+__global__ void __launch_bounds__(512, (row_waves<T, N>())) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  frow_r2c_body<T, N, ROWOUT, MODE>(a, fz, blockIdx.x, blockIdx.y, blockIdx.x + gridDim.x * blockIdx.y,
-                                    gridDim.x * gridDim.y, smem_raw);
+  frow_r2c_body<T, N, ROWOUT, MODE, HALF>(a, fz, blockIdx.x, blockIdx.y, blockIdx.x + gridDim.x * blockIdx.y,
+                                          gridDim.x * gridDim.y, smem_raw);
 }
 
 // ROWIN = false: half spectra read column-major in[l][k2][row] (ld = padded rows, nsum = 1)
@@ -214,7 +237,9 @@ __global__ void __launch_bounds__(512) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
 // MODE = FUSE_GRAD (ROWIN = false, the transpose product inside the CG step): the output is the
 // gradient l of RRCG:4, from the Gramian scalars summed at the start, with its block partials
 // of ||l||^2 (for beta of RRCG:5).
-template <typename T, int N, bool ROWIN, int MODE>
+// HALF (a.ncols <= N/2): a lane's upper four outputs are never stored, known at compile time,
+// so the last pass does not compute them.
+template <typename T, int N, bool ROWIN, int MODE, bool HALF>
 __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T>& fz, int bx, int by, int pid,
                                               int pcount, unsigned char* smem_raw) {
   static_assert(MODE == FUSE_NONE || (MODE == FUSE_QQ && ROWIN) || (MODE == FUSE_GRAD && !ROWIN), "fused form");
@@ -228,7 +253,6 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   cx<T>* buf = smem + f * BS;
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
-  F.init(a.tw, t);
   double gg[3] = {0.0, 0.0, 0.0};  // Gramian scalars for the gradient form
   const int r0 = tile * RT + 2 * f;
   const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
@@ -284,7 +308,11 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       hv[it] = gload_or(src, (long long)k2 * a.ld + rr, idx < K2 * RT && rr < rows);
     }
     // the Gramian scalars' partials, loaded while the spectra are in flight
-    if constexpr (MODE == FUSE_GRAD) gram_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lead && pid == 0, gg);
+    if constexpr (MODE == FUSE_GRAD) {
+      gram_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lead && pid == 0, gg);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gg[k] = uniform(gg[k]);  // scalar registers across the transform
+    }
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
@@ -308,11 +336,13 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     }
   }
   gsync();
+  F.init(a.tw, t);  // twiddles loaded here: not live while the input is staged
   F.template run<true>(v, buf, t, gsync);
   T* dst = reinterpret_cast<T*>(a.out) + b * a.out_bs + lofs;
   if constexpr (MODE == FUSE_GRAD) {
     const bool s0 = fz.self == 0;
-    const double al = gload(fz.sc + S_ALPHA + fz.self), lam = s0 ? fz.lam[0] : fz.lam[1];
+    // block-wide scalars, in scalar registers
+    const double al = uniform(gload(fz.sc + S_ALPHA + fz.self)), lam = uniform(s0 ? fz.lam[0] : fz.lam[1]);
     const double g11 = gg[0], g22 = gg[1], g12 = gg[2];
     const T* m0p = fz.m[0] + lofs;
     const T* m1p = fz.m[1] + lofs;
@@ -325,7 +355,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     };
     double acc[1] = {0.0};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < (HALF ? 4 : 8); ++i) {
       const int q = t + i * TPF;
       if (q < a.ncols) {
         const long long o = (long long)r0 * a.ncols + q;
@@ -346,7 +376,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   }
   double acc[1] = {0.0};
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < (HALF ? 4 : 8); ++i) {
     const int q = t + i * TPF;
     if (q < a.ncols) {
       const long long o = (long long)r0 * a.ncols + q;
@@ -365,11 +395,11 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   if constexpr (MODE == FUSE_QQ) block_partials<1>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_Q1 : PB_Q0, pid, pcount);
 }
 
-template <typename T, int N, bool ROWIN, int MODE>
-__global__ void __launch_bounds__(512) k_frow_c2r(FRowArgs<T> a, Fuse<T> fz) {
+template <typename T, int N, bool ROWIN, int MODE, bool HALF>
+__global__ void __launch_bounds__(512, (c2r_waves<T, N, ROWIN, MODE, HALF>())) k_frow_c2r(FRowArgs<T> a, Fuse<T> fz) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  frow_c2r_body<T, N, ROWIN, MODE>(a, fz, blockIdx.x, blockIdx.y, blockIdx.x + gridDim.x * blockIdx.y,
-                                   gridDim.x * gridDim.y, smem_raw);
+  frow_c2r_body<T, N, ROWIN, MODE, HALF>(a, fz, blockIdx.x, blockIdx.y, blockIdx.x + gridDim.x * blockIdx.y,
+                                         gridDim.x * gridDim.y, smem_raw);
 }
 
 // ------------------------------------------------------------------------------------
@@ -379,13 +409,28 @@ template <typename T>
 struct FColArgs {
   const cx<T>* in;
   long long in_bs;
-  const cx<T>* eig;
+  const cx<T>* eig;  // complex [L][K2][N], or with eig_even real [L][K2][N/2 + 1]
   cx<T>* out;
   long long out_bs;
   long long out_cs;  // forward: stride between layer-chunk partials
   int L, nin, nout, ldin, ldout, K2, fpb, nchunk;
   const cx<T>* tw;
+  int eig_even;  // the eigenvalues are real and even along x: lambda[N - k] = lambda[k]
 };
+
+// Eigenvalue k of a column of length N starting at `col` (EVEN: real and even, stored for
+// k <= N/2 only; else complex, interleaved), or zero when !ok.
+template <typename T, int N, bool EVEN>
+__device__ __forceinline__ cx<T> eig_or(const T* col, int k, bool ok) {
+  if constexpr (EVEN) return cx<T>{gload_or(col, k <= N / 2 ? k : N - k, ok), T(0)};
+  return gload_or(reinterpret_cast<const cx<T>*>(col), k, ok);
+}
+// Start of the stored eigenvalue column k2 of layer l.
+template <typename T, int N, bool EVEN>
+__device__ __forceinline__ const T* eig_col(const cx<T>* eig, int K2, int l, int k2) {
+  constexpr int R = EVEN ? N / 2 + 1 : 2 * N;  // reals per column
+  return reinterpret_cast<const T*>(eig) + ((long long)l * K2 + k2) * R;
+}
 
 // Column jobs: job j in [1, Py/2) is column k2 = j; job 0 carries the two columns whose
 // row spectra are real, k2 = 0 and k2 = Py/2 (= K2-1), packed as one complex transform
@@ -420,7 +465,7 @@ struct ColBuf {
 // transformed; FP64 keeps the column load in place to stay within 256 registers.  (A second
 // layer in flight was measured slower: the extra registers cost more than the latency they
 // hide.)
-template <typename T, int N, bool PACKED>
+template <typename T, int N, bool PACKED, bool EVEN, bool HALF>
 __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
                                            int G, int k2, int l0, int l1, int b,
                                            typename LayerAcc<T>::type (&ar)[8],
@@ -432,13 +477,12 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
   const int kN = a.K2 - 1;
   const cx<T>* src = a.in + b * a.in_bs + (long long)k2 * a.ldin;
   const cx<T>* srcN = a.in + b * a.in_bs + (long long)kN * a.ldin;
-  const cx<T>* eg = a.eig + (long long)k2 * N;
-  const cx<T>* egN = a.eig + (long long)kN * N;
-  const long long lstride_in = (long long)a.K2 * a.ldin, lstride_e = (long long)a.K2 * N;
+  const long long lstride_in = (long long)a.K2 * a.ldin;
   const int nit = (l1 - l0 + G - 1) / G;
   using Buf = ColBuf<T, PF_IN, PACKED>;
   auto load_col = [&](int l, int i) -> cx<T> {
     const int n = t + i * TPF;
+    if (HALF && i >= 4) return cx<T>{T(0), T(0)};  // zero padding, known at compile time
     const bool ok = l < l1 && n < a.nin;
     if constexpr (PACKED)  // the real parts only
       return cx<T>{gload_or(reinterpret_cast<const T*>(src), 2 * (l * lstride_in + n), ok),
@@ -449,8 +493,10 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if constexpr (PF_IN) B.un[i] = load_col(l, i);
-      B.en[i] = gload_or(eg, l * lstride_e + t + i * TPF, l < l1);
-      if constexpr (PACKED) B.enN[i] = gload_or(egN, l * lstride_e + t + i * TPF, l < l1);
+      const int le = l < l1 ? l : l0;  // a layer that exists, for the discarded loads
+      B.en[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, k2), t + i * TPF, l < l1);
+      if constexpr (PACKED)
+        B.enN[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, kN), t + i * TPF, l < l1);
     }
   };
   auto layer = [&](int it, Buf& B) {
@@ -508,7 +554,9 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
 constexpr int col_threads(int esz) { return esz == 4 ? 512 : 256; }
 
 // Block of column job `job`, layer chunk c, batch entry b.
-template <typename T, int N>
+// HALF (nin, nout <= N/2): the upper four inputs of a lane are zero padding and its upper four
+// outputs are not stored, both known at compile time.
+template <typename T, int N, bool HALF>
 __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int c, int b, unsigned char* smem_raw) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF;
@@ -526,8 +574,13 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
   Acc ar[8], ai[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) ar[i] = ai[i] = Acc(0);
-  if (packed) fwd_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-  else fwd_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+  if (a.eig_even) {
+    if (packed) fwd_layers<T, N, true, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+    else fwd_layers<T, N, false, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+  } else {
+    if (packed) fwd_layers<T, N, true, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+    else fwd_layers<T, N, false, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+  }
   // tree reduction of the groups' accumulators (G is a power of two)
   AccPair<Acc>* red = reinterpret_cast<AccPair<Acc>*>(smem_raw);
   for (int half = G >> 1; half >= 1; half >>= 1) {
@@ -555,7 +608,7 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
     if (f == 0) {
       cx<T>* dst = a.out + b * a.out_bs + c * a.out_cs;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < (HALF ? 4 : 8); ++i) {
         const int p = t + i * TPF;
         if (p < a.nout) {
           if (packed) {
@@ -570,34 +623,34 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, bool HALF>
 __global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_fwd(FColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  fcol_fwd_body<T, N>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
+  fcol_fwd_body<T, N, HALF>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
 }
 
 // Layer loop of the transpose column pass for one group: per layer conj(eig_l) R (PACKED:
 // conj(eig0) R0 + i conj(eigN) RN), inverse FFT_x, rows a < nout stored.  The next layer's
 // eigenvalues are loaded while the current one is transformed.
-template <typename T, int N, bool PACKED>
+template <typename T, int N, bool PACKED, bool EVEN, bool HALF>
 __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
                                            int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8],
                                            const cx<T> (&Rm)[8]) {
   constexpr int TPF = N / 8;
   GroupSync<TPF> gsync;
   const int kN = a.K2 - 1;
-  const cx<T>* eg = a.eig + (long long)k2 * N;
-  const cx<T>* egN = a.eig + (long long)kN * N;
   cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
   cx<T>* dstN = a.out + b * a.out_bs + (long long)kN * a.ldout;
-  const long long lstride_out = (long long)a.K2 * a.ldout, lstride_e = (long long)a.K2 * N;
+  const long long lstride_out = (long long)a.K2 * a.ldout;
   const int nit = (l1 - l0 + G - 1) / G;
   using Buf = ColBuf<T, false, PACKED>;
   auto fetch = [&](Buf& B, int l) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      B.en[i] = gload_or(eg, l * lstride_e + t + i * TPF, l < l1);
-      if constexpr (PACKED) B.enN[i] = gload_or(egN, l * lstride_e + t + i * TPF, l < l1);
+      const int le = l < l1 ? l : l0;  // a layer that exists, for the discarded loads
+      B.en[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, k2), t + i * TPF, l < l1);
+      if constexpr (PACKED)
+        B.enN[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, kN), t + i * TPF, l < l1);
     }
   };
   auto layer = [&](int it, Buf& B) {
@@ -623,7 +676,7 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
     F.template run<true>(v, buf, t, gsync);
     if (act) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < (HALF ? 4 : 8); ++i) {
         const int p = t + i * TPF;
         if (p < a.nout) {
           if constexpr (PACKED) {
@@ -644,7 +697,7 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
 // Transpose: R = FFT_x(Rrow column) once per block (group 0, shared through LDS), then for
 // each layer of chunk c, conj(eig_l) R and the inverse FFT_x; rows a < nout are written
 // to out[l][k2][a] (ldout = padded rows).  Rrow is row-major Rrow[p][k2] (ldin = padded K2).
-template <typename T, int N>
+template <typename T, int N, bool HALF>
 __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int c, int b, unsigned char* smem_raw) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF;
@@ -666,7 +719,7 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int
     for (int i = 0; i < 8; ++i) {
       const int n = t + i * TPF;
       const long long o = (long long)n * a.ldin;
-      R[i] = n >= a.nin ? cx<T>{T(0), T(0)}
+      R[i] = (HALF && i >= 4) || n >= a.nin ? cx<T>{T(0), T(0)}
                         : (packed ? cx<T>{gload(reinterpret_cast<const T*>(col + o)),
                                           gload(reinterpret_cast<const T*>(col + o + kN))}
                                   : gload(col + o + k2));
@@ -685,14 +738,19 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int
     R[i] = Rs[k];
     if (packed) Rm[i] = Rs[(N - k) & (N - 1)];
   }
-  if (packed) adj_layers<T, N, true>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-  else adj_layers<T, N, false>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
+  if (a.eig_even) {
+    if (packed) adj_layers<T, N, true, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
+    else adj_layers<T, N, false, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
+  } else {
+    if (packed) adj_layers<T, N, true, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
+    else adj_layers<T, N, false, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
+  }
 }
 
-template <typename T, int N>
+template <typename T, int N, bool HALF>
 __global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_adj(FColArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  fcol_adj_body<T, N>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
+  fcol_adj_body<T, N, HALF>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
 }
 
 }  // namespace bttb

@@ -21,6 +21,8 @@ struct GMember {
   cx<T>* U;
   cx<T>* V;
   long long V_fcs;  // elements between layer-chunk partials of the data spectrum
+  int eig_even;     // eigenvalues stored real and even along x
+  int pad_;
 };
 
 // Arguments of one group launch (by value): the members of one transform size.
@@ -38,15 +40,15 @@ struct GLaunch {
   int start[GMAX + 1];   // first block of each; start[count] = blocks of the launch
 };
 
-// The members of one stage that share a transform size (one launch).
+// The members of one stage that share a transform size and its half form (one launch).
 struct GClass {
-  int N, count;
+  int N, half, count;
   int idx[GMAX];
   int start[GMAX + 1];
   size_t lds;
 };
 
-constexpr int GSIZES = 7;  // transform sizes 32 .. 2048
+constexpr int GSIZES = 14;  // transform sizes 32 .. 2048, each in the half form or not
 
 struct Group {
   int count, precision;

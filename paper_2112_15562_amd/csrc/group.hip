@@ -35,8 +35,8 @@ __device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
 
 // Row transform R2C of transform size N.  ROWOUT = false: model rows into U (forward, first
 // stage); ROWOUT = true: data rows into V (transpose, first stage).
-template <typename T, int N, bool ROWOUT, int MODE>
-__global__ void __launch_bounds__(512) k_grow_r2c(GLaunch<T> g) {
+template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
+__global__ void __launch_bounds__(512, (row_waves<T, N>())) k_grow_r2c(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = uniform(group_member(g.start, g.count, blockIdx.x));
   const int i = uniform(g.idx[k]);
@@ -54,13 +54,13 @@ __global__ void __launch_bounds__(512) k_grow_r2c(GLaunch<T> g) {
                     (M.sx + 2 * G - 1) / (2 * G), M.twy};
   }
   const Fuse<T> fz = member_fuse<T, MODE>(g, i);
-  frow_r2c_body<T, N, ROWOUT, MODE>(a, fz, local, 0, local, nb, smem_raw);
+  frow_r2c_body<T, N, ROWOUT, MODE, HALF>(a, fz, local, 0, local, nb, smem_raw);
 }
 
 // Inverse row transform C2R of size N.  ROWIN = true: data rows from V (forward, last
 // stage, sums the layer-chunk partials); ROWIN = false: model rows from U (transpose, last).
-template <typename T, int N, bool ROWIN, int MODE>
-__global__ void __launch_bounds__(512) k_grow_c2r(GLaunch<T> g) {
+template <typename T, int N, bool ROWIN, int MODE, bool HALF>
+__global__ void __launch_bounds__(512, (c2r_waves<T, N, ROWIN, MODE, HALF>())) k_grow_c2r(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = uniform(group_member(g.start, g.count, blockIdx.x));
   const int i = uniform(g.idx[k]);
@@ -78,12 +78,12 @@ __global__ void __launch_bounds__(512) k_grow_c2r(GLaunch<T> g) {
                     (M.nx + 2 * G - 1) / (2 * G), M.twy};
   }
   const Fuse<T> fz = member_fuse<T, MODE>(g, i);
-  frow_c2r_body<T, N, ROWIN, MODE>(a, fz, local, 0, local, nb, smem_raw);
+  frow_c2r_body<T, N, ROWIN, MODE, HALF>(a, fz, local, 0, local, nb, smem_raw);
 }
 
 // Column pass of size N: forward (eigenvalue multiply and layer sum into V partials) or
 // transpose (conjugate eigenvalue multiply per layer into U).
-template <typename T, int N, bool FWD>
+template <typename T, int N, bool FWD, bool HALF>
 __global__ void __launch_bounds__(col_threads(sizeof(T))) k_gcol(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = uniform(group_member(g.start, g.count, blockIdx.x));
@@ -94,11 +94,13 @@ __global__ void __launch_bounds__(col_threads(sizeof(T))) k_gcol(GLaunch<T> g) {
   const int c = local / jobs, job = local - c * jobs;
   const int G = g.bt / (N / 8);
   if constexpr (FWD) {
-    const FColArgs<T> a{M.U, 0, M.eig, M.V, 0, M.V_fcs, M.nz, M.nx, M.sx, M.ldx, M.ldk, M.K2, G, M.nchunk, M.twx};
-    fcol_fwd_body<T, N>(a, job, c, 0, smem_raw);
+    const FColArgs<T> a{M.U, 0, M.eig, M.V, 0, M.V_fcs, M.nz, M.nx, M.sx, M.ldx, M.ldk, M.K2, G, M.nchunk, M.twx,
+                        M.eig_even};
+    fcol_fwd_body<T, N, HALF>(a, job, c, 0, smem_raw);
   } else {
-    const FColArgs<T> a{M.V, 0, M.eig, M.U, 0, 0, M.nz, M.sx, M.nx, M.ldk, M.ldx, M.K2, G, M.nchunk, M.twx};
-    fcol_adj_body<T, N>(a, job, c, 0, smem_raw);
+    const FColArgs<T> a{M.V, 0, M.eig, M.U, 0, 0, M.nz, M.sx, M.nx, M.ldk, M.ldx, M.K2, G, M.nchunk, M.twx,
+                        M.eig_even};
+    fcol_adj_body<T, N, HALF>(a, job, c, 0, smem_raw);
   }
 }
 
@@ -141,15 +143,20 @@ static int layout(Group* g) {
     const size_t l[GS_COUNT] = {
         fast_row_lds(P->Py, esz, Grm), fast_col_lds(P->Px, esz, Gc, true), fast_row_lds(P->Py, esz, Grd),
         fast_row_lds(P->Py, esz, Grd), fast_col_lds(P->Px, esz, Gc, false), fast_row_lds(P->Py, esz, Grm)};
+    // half forms: the rows (model ny, data sy) or the columns (nx and sx) fill at most half
+    // the transform
+    const int half[GS_COUNT] = {2 * P->ny <= P->Py, 2 * P->nx <= P->Px && 2 * P->sx <= P->Px, 2 * P->sy <= P->Py,
+                                2 * P->sy <= P->Py, 2 * P->nx <= P->Px && 2 * P->sx <= P->Px, 2 * P->ny <= P->Py};
     for (int st = 0; st < GS_COUNT; ++st) {
       const int N = (st == GS_F2 || st == GS_T2) ? P->Px : P->Py;
       int c = 0;
-      while (c < g->ncls[st] && g->cls[st][c].N != N) ++c;
+      while (c < g->ncls[st] && (g->cls[st][c].N != N || g->cls[st][c].half != half[st])) ++c;
       GClass& C = g->cls[st][c];
       if (c == g->ncls[st]) {
         if (c == GSIZES) return fail(BTTB_EINVAL, "group: too many transform sizes");
         g->ncls[st] += 1;
         C.N = N;
+        C.half = half[st];
         C.count = 0;
         C.start[0] = 0;
         C.lds = 0;
@@ -175,7 +182,7 @@ static int upload_members(Group* g, hipStream_t s) {
     h[i] = GMember<T>{P->Px, P->Py, P->K2, P->sx, P->sy, P->nx, P->ny, P->nz, P->ldx, P->ldk, g->nch[i],
                       static_cast<const cx<T>*>(P->eig), static_cast<const cx<T>*>(P->twx),
                       static_cast<const cx<T>*>(P->twy), static_cast<cx<T>*>(P->U), static_cast<cx<T>*>(P->V),
-                      (long long)P->lds * P->ldk};
+                      (long long)P->lds * P->ldk, P->eig_even, 0};
   }
   BTTB_HIP(hipMemcpyAsync(g->mem, h, sizeof(GMember<T>) * g->count, hipMemcpyHostToDevice, s));
   BTTB_HIP(hipStreamSynchronize(s));
@@ -224,16 +231,20 @@ static GLaunch<T> launch_of(const Group* g, int st, const GClass& C, const Fuse<
   }
 
 // The kernel of stage st at transform size N (in the CG step's fused form when fused).
-template <typename T, int N>
-static auto stage_kernel(int st, bool fused) -> void (*)(GLaunch<T>) {
+template <typename T, int N, bool H>
+static auto stage_kernel_h(int st, bool fused) -> void (*)(GLaunch<T>) {
   switch (st) {
-    case GS_F1: return fused ? k_grow_r2c<T, N, false, FUSE_DIR> : k_grow_r2c<T, N, false, FUSE_NONE>;
-    case GS_F2: return k_gcol<T, N, true>;
-    case GS_F3: return fused ? k_grow_c2r<T, N, true, FUSE_QQ> : k_grow_c2r<T, N, true, FUSE_NONE>;
-    case GS_T1: return k_grow_r2c<T, N, true, FUSE_NONE>;
-    case GS_T2: return k_gcol<T, N, false>;
-    default: return fused ? k_grow_c2r<T, N, false, FUSE_GRAD> : k_grow_c2r<T, N, false, FUSE_NONE>;
+    case GS_F1: return fused ? k_grow_r2c<T, N, false, FUSE_DIR, false> : k_grow_r2c<T, N, false, FUSE_NONE, H>;
+    case GS_F2: return k_gcol<T, N, true, H>;
+    case GS_F3: return fused ? k_grow_c2r<T, N, true, FUSE_QQ, H> : k_grow_c2r<T, N, true, FUSE_NONE, H>;
+    case GS_T1: return k_grow_r2c<T, N, true, FUSE_NONE, H>;
+    case GS_T2: return k_gcol<T, N, false, H>;
+    default: return fused ? k_grow_c2r<T, N, false, FUSE_GRAD, H> : k_grow_c2r<T, N, false, FUSE_NONE, H>;
   }
+}
+template <typename T, int N>
+static auto stage_kernel(int st, bool fused, bool half) -> void (*)(GLaunch<T>) {
+  return half ? stage_kernel_h<T, N, true>(st, fused) : stage_kernel_h<T, N, false>(st, fused);
 }
 
 template <typename T>
@@ -254,7 +265,7 @@ int group_apply_impl(const Group* g_, int op, const void* const* in, void* const
         const GClass& C = g->cls[st][c];
         const GLaunch<T> L = launch_of<T>(g, st, C, fz, in, out, winv, wd);
         void (*kern)(GLaunch<T>) = nullptr;
-#define BTTB_K(NN) kern = stage_kernel<T, NN>(st, fz != nullptr)
+#define BTTB_K(NN) kern = stage_kernel<T, NN>(st, fz != nullptr, C.half != 0)
         BTTB_GROUP_SIZES(C.N, BTTB_K)
 #undef BTTB_K
         hipLaunchKernelGGL(kern, dim3(C.start[C.count]), dim3(L.bt), C.lds, s, L);

@@ -393,6 +393,109 @@ __global__ void __launch_bounds__(1024) k_col_setup(const cx<double>* in, int ld
   }
 }
 
+// Symmetry test of the stored eigenvalues (complex [cols][N]): per column block, max |lambda|,
+// max |Im lambda| and max |lambda[k] - lambda[N - k]|, written to part[3 col + 0..2].
+template <typename T>
+__global__ void __launch_bounds__(256) k_eig_symmetry(const T* eig, int N, double* part) {
+  const long long col = blockIdx.x;
+  const T* e = eig + 2 * col * N;
+  double m[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const int km = k == 0 ? 0 : N - k;
+    const double re = e[2 * k], im = e[2 * k + 1];
+    const double dr = re - (double)e[2 * km], di = im - (double)e[2 * km + 1];
+    m[0] = fmax(m[0], sqrt(re * re + im * im));
+    m[1] = fmax(m[1], fabs(im));
+    m[2] = fmax(m[2], sqrt(dr * dr + di * di));
+  }
+  __shared__ double sh[3][256];
+  for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = m[k];
+  __syncthreads();
+  for (int h = blockDim.x / 2; h >= 1; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) part[3 * col + k] = sh[k][0];
+}
+
+// Real parts of lambda[0 .. N/2] of each column: the store of a symmetric operator.
+template <typename T>
+__global__ void __launch_bounds__(256) k_eig_compact(const T* eig, T* out, long long ncol, int N) {
+  const int H = N / 2 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < ncol * H;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long col = i / H;
+    const int k = (int)(i - col * H);
+    out[i] = eig[2 * (col * N + k)];
+  }
+}
+
+// The complex eigenvalues [cols][N] of a real-even store.
+template <typename T>
+__global__ void __launch_bounds__(256) k_eig_expand(const T* er, T* out, long long ncol, int N) {
+  const int H = N / 2 + 1;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < ncol * N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long col = i / N;
+    const int k = (int)(i - col * N);
+    out[2 * i] = er[col * H + (k <= N / 2 ? k : N - k)];
+    out[2 * i + 1] = T(0);
+  }
+}
+
+// A symmetric operator (kernel even in both lags, e.g. gravity with stations above the prism
+// centres) has real eigenvalues, even along x: keep only Re lambda[0 .. Px/2] of each column,
+// a quarter of the bytes the column passes stream.  Tested on the stored values: in FP32 to
+// 1e-6 of max |lambda| (ten times the storage rounding); in FP64 to 1e-14, the transforms'
+// own rounding, so that an FP64 plan changes by no more than that (the closed-form prism
+// kernels are symmetric only to their evaluation noise, 1e-12 and more of max |lambda|,
+// which FP64 plans keep).
+template <typename T>
+static int make_eig_even(Plan* P, hipStream_t s) {
+  const long long ncol = (long long)P->nz * P->K2;
+  const int N = P->Px;
+  double* part = nullptr;
+  if (hipMalloc(&part, (size_t)ncol * 3 * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BTTB_ENOMEM, "bttb_setup: device allocation failed");
+  }
+  hipLaunchKernelGGL(k_eig_symmetry<T>, dim3((unsigned)ncol), dim3(256), 0, s, static_cast<const T*>(P->eig), N,
+                     part);
+  std::vector<double> h((size_t)ncol * 3);
+  const bool ok = hipGetLastError() == hipSuccess &&
+                  hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s) == hipSuccess &&
+                  hipStreamSynchronize(s) == hipSuccess;
+  (void)hipFree(part);
+  if (!ok) return fail(BTTB_EHIP, "bttb_setup: eigenvalue symmetry test");
+  double mx = 0.0, mi = 0.0, ma = 0.0;
+  for (long long c = 0; c < ncol; ++c) {
+    mx = std::max(mx, h[3 * c]);
+    mi = std::max(mi, h[3 * c + 1]);
+    ma = std::max(ma, h[3 * c + 2]);
+  }
+  const double tol = (sizeof(T) == 8 ? 1e-14 : 1e-6) * mx;
+  if (!(mx > 0.0) || mi > tol || ma > tol) return BTTB_OK;  // not symmetric: keep the complex store
+  const size_t bytes = (size_t)ncol * (N / 2 + 1) * sizeof(T);
+  void* er = nullptr;
+  if (hipMalloc(&er, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(BTTB_ENOMEM, "bttb_setup: device allocation failed");
+  }
+  hipLaunchKernelGGL(k_eig_compact<T>, dim3(1024), dim3(256), 0, s, static_cast<const T*>(P->eig),
+                     static_cast<T*>(er), ncol, N);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(er);
+    return fail(BTTB_EHIP, "bttb_setup: eigenvalue compaction");
+  }
+  (void)hipFree(P->eig);
+  P->eig = er;
+  P->eig_bytes = bytes;
+  P->eig_even = 1;
+  return BTTB_OK;
+}
+
 // ------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------
@@ -482,7 +585,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
         });
         if (rc) return rc;
         rc = stage(KT_FWD_COL, [&]() -> int {
-          return fast_col<T>(true, U, U_bs, eig, V, V_bs, V_fcs, P->nz, P->nx, P->sx, P->ldx, P->ldk, P->K2, P->Px,
+          return fast_col<T>(true, U, U_bs, eig, P->eig_even, V, V_bs, V_fcs, P->nz, P->nx, P->sx, P->ldx, P->ldk, P->K2, P->Px,
                              P->col_fpb, P->nchunk, twx, nb, s);
         });
         if (rc) return rc;
@@ -497,7 +600,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
         });
         if (rc) return rc;
         rc = stage(KT_ADJ_COL, [&]() -> int {
-          return fast_col<T>(false, V, V_bs, eig, U, U_bs, 0, P->nz, P->sx, P->nx, P->ldk, P->ldx, P->K2, P->Px,
+          return fast_col<T>(false, V, V_bs, eig, P->eig_even, U, U_bs, 0, P->nz, P->sx, P->nx, P->ldk, P->ldx, P->K2, P->Px,
                              P->col_fpb, P->nchunk, twx, nb, s);
         });
         if (rc) return rc;
@@ -625,7 +728,8 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
   if (sx < 1 || sy < 1 || nx < 1 || ny < 1 || nz < 1 || max_batch < 1)
     return fail(BTTB_EINVAL, "bttb_setup: sizes must be >= 1");
   const bool pad_pow2 = (precision & BTTB_PAD_POW2) != 0;
-  precision &= ~BTTB_PAD_POW2;
+  const bool eig_full = (precision & BTTB_EIG_FULL) != 0;
+  precision &= ~(BTTB_PAD_POW2 | BTTB_EIG_FULL);
   if (precision != BTTB_F64 && precision != BTTB_F32) return fail(BTTB_EINVAL, "bttb_setup: bad precision");
   const long long Lx = (long long)sx + nx - 1, Ly = (long long)sy + ny - 1;
   if (Lx > BTTB_MAX_TRANSFORM || Ly > BTTB_MAX_TRANSFORM)
@@ -735,6 +839,7 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
                          static_cast<const cx<double>*>(twx64), scale);
     if (hipGetLastError() != hipSuccess) { rc = fail(BTTB_EHIP, "bttb_setup: k_col_setup launch"); break; }
     if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(BTTB_EHIP, "bttb_setup: synchronize"); break; }
+    if (P->fast && !eig_full) rc = precision == BTTB_F64 ? make_eig_even<double>(P, s) : make_eig_even<float>(P, s);
   } while (false);
   cleanup_tmp();
   if (rc != BTTB_OK) return cleanup(rc);
@@ -794,13 +899,26 @@ extern "C" int bttb_plan_info(bttb_plan plan, bttb_plan_desc* out) {
   out->Px = P->Px; out->Py = P->Py; out->precision = P->precision; out->max_batch = P->max_batch;
   out->eig_bytes = P->eig_bytes; out->scratch_bytes = P->scratch_bytes;
   out->col_fft_per_block = P->col_fpb; out->row_fft_per_block = P->row_fpb; out->layer_chunks = P->nchunk;
+  out->eig_real_even = P->eig_even;
   return BTTB_OK;
 }
 
 extern "C" int bttb_plan_eigenvalues(bttb_plan plan, void* out, void* stream) {
   Plan* P = as_plan(plan);
   if (!P || !out) return fail(BTTB_EINVAL, "bttb_plan_eigenvalues: NULL argument");
-  BTTB_HIP(hipMemcpyAsync(out, P->eig, P->eig_bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!P->eig_even) {
+    BTTB_HIP(hipMemcpyAsync(out, P->eig, P->eig_bytes, hipMemcpyDeviceToDevice, s));
+    return BTTB_OK;
+  }
+  const long long ncol = (long long)P->nz * P->K2;
+  if (P->precision == BTTB_F64)
+    hipLaunchKernelGGL(k_eig_expand<double>, dim3(1024), dim3(256), 0, s, static_cast<const double*>(P->eig),
+                       static_cast<double*>(out), ncol, P->Px);
+  else
+    hipLaunchKernelGGL(k_eig_expand<float>, dim3(1024), dim3(256), 0, s, static_cast<const float*>(P->eig),
+                       static_cast<float*>(out), ncol, P->Px);
+  BTTB_LAUNCHED("k_eig_expand");
   return BTTB_OK;
 }
 

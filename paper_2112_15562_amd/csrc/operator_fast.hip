@@ -53,12 +53,17 @@ int fast_row_r2c(bool rowout, const T* in, long long in_bs, const T* scale, cx<T
   dim3 grid(L * a.tiles, batch), block(G * (N / 8));
   const size_t sh = fast_row_lds(N, sizeof(T), G);
   const Fuse<T> f0{};
+  const bool half = 2 * ncols <= N;  // the upper half of each row is zero padding
   if (rowout) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, true, FUSE_NONE>), grid, block, sh, s, a, f0)
+#define BTTB_L(NN)                                                                           \
+  if (half) hipLaunchKernelGGL((k_frow_r2c<T, NN, true, FUSE_NONE, true>), grid, block, sh, s, a, f0); \
+  else hipLaunchKernelGGL((k_frow_r2c<T, NN, true, FUSE_NONE, false>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   } else {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_r2c<T, NN, false, FUSE_NONE>), grid, block, sh, s, a, f0)
+#define BTTB_L(NN)                                                                            \
+  if (half) hipLaunchKernelGGL((k_frow_r2c<T, NN, false, FUSE_NONE, true>), grid, block, sh, s, a, f0); \
+  else hipLaunchKernelGGL((k_frow_r2c<T, NN, false, FUSE_NONE, false>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   }
@@ -76,12 +81,17 @@ int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, 
   const size_t sh = fast_row_lds(N, sizeof(T), G);
   const Fuse<T> f0{};
   if (!rowin && nsum != 1) return fail(BTTB_EINVAL, "fast_row_c2r: column-major input takes no partial sums");
+  const bool half = 2 * ncols <= N;  // the upper half of each output row is not stored
   if (rowin) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_NONE>), grid, block, sh, s, a, f0)
+#define BTTB_L(NN)                                                                           \
+  if (half) hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_NONE, true>), grid, block, sh, s, a, f0); \
+  else hipLaunchKernelGGL((k_frow_c2r<T, NN, true, FUSE_NONE, false>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   } else {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_frow_c2r<T, NN, false, FUSE_NONE>), grid, block, sh, s, a, f0)
+#define BTTB_L(NN)                                                                            \
+  if (half) hipLaunchKernelGGL((k_frow_c2r<T, NN, false, FUSE_NONE, true>), grid, block, sh, s, a, f0); \
+  else hipLaunchKernelGGL((k_frow_c2r<T, NN, false, FUSE_NONE, false>), grid, block, sh, s, a, f0)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
   }
@@ -90,19 +100,24 @@ int fast_row_c2r(bool rowin, const cx<T>* in, long long in_bs, long long in_cs, 
 }
 
 template <typename T>
-int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, cx<T>* out, long long out_bs,
+int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, int eig_even, cx<T>* out, long long out_bs,
              long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
              const cx<T>* tw, int batch, hipStream_t s) {
-  FColArgs<T> a{in, in_bs, eig, out, out_bs, out_cs, L, nin, nout, ldin, ldout, K2, G, nchunk, tw};
+  FColArgs<T> a{in, in_bs, eig, out, out_bs, out_cs, L, nin, nout, ldin, ldout, K2, G, nchunk, tw, eig_even};
   dim3 grid(K2 - 1, nchunk, batch), block(G * (N / 8));
   const size_t sh = fast_col_lds(N, sizeof(T), G, fwd);
+  const bool half = 2 * nin <= N && 2 * nout <= N;  // zero-padded inputs, unstored outputs
   if (fwd) {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_fcol_fwd<T, NN>), grid, block, sh, s, a)
+#define BTTB_L(NN)                                                                       \
+  if (half) hipLaunchKernelGGL((k_fcol_fwd<T, NN, true>), grid, block, sh, s, a); \
+  else hipLaunchKernelGGL((k_fcol_fwd<T, NN, false>), grid, block, sh, s, a)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
     BTTB_LAUNCHED("k_fcol_fwd");
   } else {
-#define BTTB_L(NN) hipLaunchKernelGGL((k_fcol_adj<T, NN>), grid, block, sh, s, a)
+#define BTTB_L(NN)                                                                       \
+  if (half) hipLaunchKernelGGL((k_fcol_adj<T, NN, true>), grid, block, sh, s, a); \
+  else hipLaunchKernelGGL((k_fcol_adj<T, NN, false>), grid, block, sh, s, a)
     BTTB_POW2_SWITCH(N, BTTB_L)
 #undef BTTB_L
     BTTB_LAUNCHED("k_fcol_adj");
@@ -118,9 +133,9 @@ template int fast_row_c2r<float>(bool, const cx<float>*, long long, long long, i
                                  int, int, int, int, int, const cx<float>*, int, hipStream_t);
 template int fast_row_c2r<double>(bool, const cx<double>*, long long, long long, int, double*, long long, const double*,
                                   int, int, int, int, int, int, const cx<double>*, int, hipStream_t);
-template int fast_col<float>(bool, const cx<float>*, long long, const cx<float>*, cx<float>*, long long, long long,
+template int fast_col<float>(bool, const cx<float>*, long long, const cx<float>*, int, cx<float>*, long long, long long,
                              int, int, int, int, int, int, int, int, int, const cx<float>*, int, hipStream_t);
-template int fast_col<double>(bool, const cx<double>*, long long, const cx<double>*, cx<double>*, long long,
+template int fast_col<double>(bool, const cx<double>*, long long, const cx<double>*, int, cx<double>*, long long,
                               long long, int, int, int, int, int, int, int, int, int, const cx<double>*, int,
                               hipStream_t);
 

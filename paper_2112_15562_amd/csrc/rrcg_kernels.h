@@ -162,7 +162,7 @@ __device__ __forceinline__ void update_body(long long n, long long nd, T* m0, T*
   const int nt = blockDim.x;
   double st[2];
   step_from(sc, rd.pb, rd.pbn, rd.pbs, lam0, lam1, coupled, bid == 0, st);
-  const double s0 = st[0], s1 = st[1];
+  const double s0 = uniform(st[0]), s1 = uniform(st[1]);
   double v[3] = {0.0, 0.0, 0.0};
   const long long top = n > nd ? n : nd;
   const long long step = (long long)nb * nt * U;

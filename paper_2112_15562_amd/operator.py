@@ -51,10 +51,12 @@ class Operator:
     stations: (sx, sy); the prism grid follows from the kernel array's shape.
     dtype: torch.float64 (plain FP64 path) or torch.float32 (FFTs and products in FP32,
     eigenvalues computed in FP64 and rounded).
+    full_eig: keep the complex eigenvalues of a symmetric operator (by default a power-of-two
+    plan stores only the real, x-even half of them; info()["eig_real_even"]).
     """
 
     def __init__(self, kernels: torch.Tensor, stations: Sequence[int], dtype=torch.float64,
-                 max_batch: int = 1, device="cuda", pad_pow2: bool = False):
+                 max_batch: int = 1, device="cuda", pad_pow2: bool = False, full_eig: bool = False):
         if dtype not in _DT:
             raise TypeError("dtype must be torch.float32 or torch.float64")
         self.device = torch.device(device)
@@ -72,16 +74,17 @@ class Operator:
         self.dtype = dtype
         self.max_batch = int(max_batch)
         self._plan = C.c_void_p()
-        flags = _DT[dtype] | (L.BTTB_PAD_POW2 if pad_pow2 else 0)
+        flags = _DT[dtype] | (L.BTTB_PAD_POW2 if pad_pow2 else 0) | (L.BTTB_EIG_FULL if full_eig else 0)
         L.check(L.lib().bttb_setup(_ptr(k), sx, sy, nx, ny, nz, flags, self.max_batch,
                                    C.c_void_p(_stream(self.device)), C.byref(self._plan)), "bttb_setup")
 
     @classmethod
     def from_geometry(cls, kind: int, geometry, dtype=torch.float64, max_batch: int = 1, device="cuda",
-                      pad_pow2: bool = False):
+                      pad_pow2: bool = False, full_eig: bool = False):
         T = prism_kernels(kind, geometry, device)
         g = _geometry(geometry)
-        return cls(T, (g.sx, g.sy), dtype=dtype, max_batch=max_batch, device=device, pad_pow2=pad_pow2)
+        return cls(T, (g.sx, g.sy), dtype=dtype, max_batch=max_batch, device=device, pad_pow2=pad_pow2,
+                   full_eig=full_eig)
 
     # ------------------------------------------------------------------------------
     @property
@@ -129,7 +132,8 @@ class Operator:
         return {L.KERNEL_NAMES[k]: (tot[k], cnt[k]) for k in range(L.NKERNELS)}
 
     def eigenvalues(self) -> torch.Tensor:
-        """Copy of the stored eigenvalues, complex [nz][Py/2+1][Px], scaled by 1/(Px Py)."""
+        """Copy of the eigenvalues, complex [nz][Py/2+1][Px], scaled by 1/(Px Py) (a real-even
+        store expanded)."""
         info = self.info()
         K2 = info["Py"] // 2 + 1
         out = torch.empty(self.nz * K2 * info["Px"] * 2, dtype=self.dtype, device=self.device)

@@ -180,6 +180,76 @@ def test_large_grid_matches_fft_oracle(pk, dtype):
 
 
 # ------------------------------------------------------------------------------------
+# symmetric operators: the real, x-even eigenvalue store
+# ------------------------------------------------------------------------------------
+def _same_products(a, b, shape_m, shape_d, dtype, tol):
+    rng = np.random.default_rng(11)
+    x = dev(rng.uniform(0.0, 1.0, shape_m), dtype)
+    r = dev(rng.standard_normal(shape_d), dtype)
+    winv = dev(rng.uniform(0.5, 2.0, shape_m), dtype)
+    wd = dev(rng.uniform(0.5, 2.0, shape_d), dtype)
+    assert relerr(host(a.matvec(x)), host(b.matvec(x))) <= tol
+    assert relerr(host(a.rmatvec(r)), host(b.rmatvec(r))) <= tol
+    assert relerr(host(a.matvec(x, winv=winv, wd=wd)), host(b.matvec(x, winv=winv, wd=wd))) <= tol
+    assert relerr(host(a.rmatvec(r, winv=winv, wd=wd)), host(b.rmatvec(r, winv=winv, wd=wd))) <= tol
+
+
+def _store_checks(even, full, nz, dtype):
+    ie, ifu = even.info(), full.info()
+    assert (ie["eig_real_even"], ifu["eig_real_even"]) == (1, 0)
+    esz = 8 if dtype == torch.float64 else 4
+    K2, Px = ie["Py"] // 2 + 1, ie["Px"]
+    assert ie["eig_bytes"] == nz * K2 * (Px // 2 + 1) * esz
+    assert ifu["eig_bytes"] == nz * K2 * Px * 2 * esz
+    # the expanded store is the complex one to rounding: real, lambda[Px - k] = lambda[k]
+    eg, ef = even.eigenvalues().cpu().numpy(), full.eigenvalues().cpu().numpy()
+    assert np.abs(eg.imag).max() == 0.0
+    assert np.abs(eg - ef).max() <= (1e-14 if dtype == torch.float64 else 1e-6) * np.abs(ef).max()
+
+
+# Stations above the prism centres (sx = nx, sy = ny): the gravity kernel is even in both
+# lags, so its eigenvalues are real and lambda[Px - k] = lambda[k]; the magnetic kernel at
+# I = 65 deg, D = 2 deg is not.  FP32 plans take the real store (the two stores differ by the
+# FP32 rounding of Lambda[Px - k] against Lambda[k]).  FP64 plans of these kernels keep the
+# complex store: their closed forms evaluate T(i, j) and T(-i, j) with different rounding,
+# which the far-field cancellation amplifies to |Im lambda| ~ 6e-13 (16^2) .. 1e-10 (128^2) of
+# max |lambda|, above the FP64 test (1e-14).
+@pytest.mark.parametrize("g", [synth.SMALL, synth.MID])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_symmetric_gravity_operator_store(pk, g, dtype):
+    grav = pk.Operator.from_geometry(pk.GRAVITY, g, dtype=dtype)
+    full = pk.Operator.from_geometry(pk.GRAVITY, g, dtype=dtype, full_eig=True)
+    mag = pk.Operator.from_geometry(pk.MAGNETIC, g, dtype=dtype)
+    assert mag.info()["eig_real_even"] == 0
+    if dtype == torch.float64:
+        assert grav.info()["eig_real_even"] == 0
+    else:
+        _store_checks(grav, full, g.nz, dtype)
+        _same_products(grav, full, g.model_shape, g.data_shape, dtype, 1e-6)
+    for op in (grav, full, mag):
+        op.close()
+
+
+# An FP64 kernel array symmetric bit for bit, T(i, j) = T(-i, j) = T(i, -j): the FP64 plan takes
+# the real store, and its products agree with the complex store's to rounding.
+@pytest.mark.parametrize("n", [(16, 12, 3), (100, 60, 4)])
+def test_exactly_symmetric_kernel_fp64_store(pk, n):
+    sx, sy, nz = n
+    rng = np.random.default_rng(sx)
+    h = rng.standard_normal((nz, sx, sy))     # lags 0 .. s-1 in each direction
+    T = np.zeros((nz, 2 * sx - 1, 2 * sy - 1))
+    for i in range(-(sx - 1), sx):
+        for j in range(-(sy - 1), sy):
+            T[:, i + sx - 1, j + sy - 1] = h[:, abs(i), abs(j)]
+    even = pk.Operator(dev(T), (sx, sy), dtype=torch.float64, pad_pow2=True)
+    full = pk.Operator(dev(T), (sx, sy), dtype=torch.float64, pad_pow2=True, full_eig=True)
+    _store_checks(even, full, nz, torch.float64)
+    _same_products(even, full, (nz, sx, sy), (sx, sy), torch.float64, 1e-13)
+    even.close()
+    full.close()
+
+
+# ------------------------------------------------------------------------------------
 # structural properties
 # ------------------------------------------------------------------------------------
 def test_adjoint_identity_fp64(pk):
