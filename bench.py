@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "517bf161764df84313613ce30b8da468a5d9cf204da2ab0c41035e22beff30d3",
+    "csrc_sha256": "72a567cb4ed4627051b7cd4c0e9dfd902abe506c5c59dd919eafe8dcae7f2345",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50718955, 50531444), "fwd_col_eig_sum": (101298763, 4327738),
-        "fwd_row_c2r": (1817622, 532439), "adj_row_r2c": (1205003, 1064960),
-        "adj_col_conj_eig": (76279327, 33685504), "adj_row_c2r": (102735484, 16811643),
+        "fwd_row_r2c": (50656042, 50536380), "fwd_col_eig_sum": (77139130, 4696159),
+        "fwd_row_c2r": (1917565, 532211), "adj_row_r2c": (1187302, 1064960),
+        "adj_col_conj_eig": (52135872, 33685504), "adj_row_c2r": (101507131, 16814178),
     },
 }
 
