@@ -432,12 +432,10 @@ __device__ __forceinline__ const T* eig_col(const cx<T>* eig, int K2, int l, int
   return reinterpret_cast<const T*>(eig) + ((long long)l * K2 + k2) * R;
 }
 
-// Column jobs: job j in [1, Py/2) is column k2 = j; job 0 carries the two columns whose
-// row spectra are real, k2 = 0 and k2 = Py/2 (= K2-1), packed as one complex transform
-// c0 + i cN.  Their column transforms are recovered as X0[k] = (Z[k] + conj Z[-k]) / 2,
-// XN[k] = (Z[k] - conj Z[-k]) / (2i); products with eigenvalue columns of a real array
-// stay Hermitian, so the inverse of S0 + i SN returns s0 in its real and sN in its
-// imaginary part.  This gives Py/2 equal jobs.
+// Column jobs: job k2 in [0, K2) is column k2 of the row spectra.  The two real columns
+// (k2 = 0 and Py/2) are ordinary complex jobs with zero imaginary parts: combining them into
+// one transform saves one job in K2 but needs a separate path whose registers every block
+// would then reserve.
 
 // Accumulator of the forward layer sum: the plan's type (the sum is part of the product,
 // whose FFTs and multiplies run in that type), or FP64 when built with BTTB_LAYER_SUM_F64=1.
@@ -454,18 +452,17 @@ struct AccPair {
 };
 
 // One layer's prefetched operands of a column pass.
-template <typename T, bool COL, bool PACKED>
+template <typename T, bool COL>
 struct ColBuf {
-  cx<T> un[COL ? 8 : 1], en[8], enN[PACKED ? 8 : 1];
+  cx<T> un[COL ? 8 : 1], en[8];
 };
 
-// Layer loop of the forward column pass for one group: acc += eig_l . FFT_x(column_l)
-// (PACKED: eig0 . X0 + i eigN . XN from the packed pair of real columns).  The next
-// layer's eigenvalues (and in FP32 its column) are loaded while the current one is
+// Layer loop of the forward column pass for one group: acc += eig_l . FFT_x(column_l).  The
+// next layer's eigenvalues (and in FP32 its column) are loaded while the current one is
 // transformed; FP64 keeps the column load in place to stay within 256 registers.  (A second
 // layer in flight was measured slower: the extra registers cost more than the latency they
 // hide.)
-template <typename T, int N, bool PACKED, bool EVEN, bool HALF>
+template <typename T, int N, bool EVEN, bool HALF>
 __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
                                            int G, int k2, int l0, int l1, int b,
                                            typename LayerAcc<T>::type (&ar)[8],
@@ -474,20 +471,14 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
   constexpr int TPF = N / 8;
   constexpr bool PF_IN = sizeof(T) == 4;
   GroupSync<TPF> gsync;
-  const int kN = a.K2 - 1;
   const cx<T>* src = a.in + b * a.in_bs + (long long)k2 * a.ldin;
-  const cx<T>* srcN = a.in + b * a.in_bs + (long long)kN * a.ldin;
   const long long lstride_in = (long long)a.K2 * a.ldin;
   const int nit = (l1 - l0 + G - 1) / G;
-  using Buf = ColBuf<T, PF_IN, PACKED>;
+  using Buf = ColBuf<T, PF_IN>;
   auto load_col = [&](int l, int i) -> cx<T> {
-    const int n = t + i * TPF;
     if (HALF && i >= 4) return cx<T>{T(0), T(0)};  // zero padding, known at compile time
-    const bool ok = l < l1 && n < a.nin;
-    if constexpr (PACKED)  // the real parts only
-      return cx<T>{gload_or(reinterpret_cast<const T*>(src), 2 * (l * lstride_in + n), ok),
-                   gload_or(reinterpret_cast<const T*>(srcN), 2 * (l * lstride_in + n), ok)};
-    return gload_or(src, l * lstride_in + n, ok);
+    const int n = t + i * TPF;
+    return gload_or(src, l * lstride_in + n, l < l1 && n < a.nin);
   };
   auto fetch = [&](Buf& B, int l) {
 #pragma unroll
@@ -495,45 +486,21 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
       if constexpr (PF_IN) B.un[i] = load_col(l, i);
       const int le = l < l1 ? l : l0;  // a layer that exists, for the discarded loads
       B.en[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, k2), t + i * TPF, l < l1);
-      if constexpr (PACKED)
-        B.enN[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, kN), t + i * TPF, l < l1);
     }
   };
   auto layer = [&](int it, Buf& B) {
     const int l = l0 + it * G + f;
     const bool act = l < l1;
-    cx<T> v[8], e[8], eN[PACKED ? 8 : 1];
+    cx<T> v[8], e[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       if constexpr (PF_IN) v[i] = B.un[i];
       else v[i] = load_col(l, i);
       e[i] = B.en[i];
-      if constexpr (PACKED) eN[i] = B.enN[i];
     }
     if (it + 1 < nit) fetch(B, l + G);
     F.template run<false>(v, buf, t, gsync);
-    if constexpr (PACKED) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) buf[lds_pad(t + i * TPF)] = v[i];
-      gsync();
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = t + i * TPF;
-        const cx<T> A = v[i], C = buf[lds_pad((N - k) & (N - 1))];
-        const Acc h = Acc(0.5);
-        const Acc x0r = h * ((Acc)A.re + C.re), x0i = h * ((Acc)A.im - C.im);
-        const Acc xnr = h * ((Acc)A.im + C.im), xni = h * ((Acc)C.re - A.re);
-        const Acc pr = (Acc)e[i].re * x0r - (Acc)e[i].im * x0i;
-        const Acc pi = (Acc)e[i].re * x0i + (Acc)e[i].im * x0r;
-        const Acc qr = (Acc)eN[i].re * xnr - (Acc)eN[i].im * xni;
-        const Acc qi = (Acc)eN[i].re * xni + (Acc)eN[i].im * xnr;
-        if (act) {
-          ar[i] += pr - qi;
-          ai[i] += pi + qr;
-        }
-      }
-      gsync();
-    } else if (act) {
+    if (act) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const Acc xr = v[i].re, xi = v[i].im, wr = e[i].re, wi = e[i].im;
@@ -553,18 +520,16 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
 // (the accumulation registers) can hold what does not fit, instead of scratch memory.
 constexpr int col_threads(int esz) { return esz == 4 ? 512 : 256; }
 
-// Block of column job `job`, layer chunk c, batch entry b.
+// Block of column job k2, layer chunk c, batch entry b.
 // HALF (nin, nout <= N/2): the upper four inputs of a lane are zero padding and its upper four
 // outputs are not stored, both known at compile time.
 template <typename T, int N, bool HALF>
-__device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int c, int b, unsigned char* smem_raw) {
+__device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int k2, int c, int b, unsigned char* smem_raw) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
   const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
   const int G = a.fpb;
-  const bool packed = job == 0;
-  const int k2 = job, kN = a.K2 - 1;
   const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
   cx<T>* buf = smem + f * P::BUF;
   GroupSync<TPF> gsync;
@@ -574,13 +539,8 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
   Acc ar[8], ai[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) ar[i] = ai[i] = Acc(0);
-  if (a.eig_even) {
-    if (packed) fwd_layers<T, N, true, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-    else fwd_layers<T, N, false, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-  } else {
-    if (packed) fwd_layers<T, N, true, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-    else fwd_layers<T, N, false, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
-  }
+  if (a.eig_even) fwd_layers<T, N, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
+  else fwd_layers<T, N, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, ar, ai);
   // tree reduction of the groups' accumulators (G is a power of two)
   AccPair<Acc>* red = reinterpret_cast<AccPair<Acc>*>(smem_raw);
   for (int half = G >> 1; half >= 1; half >>= 1) {
@@ -610,14 +570,7 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int job, int
 #pragma unroll
       for (int i = 0; i < (HALF ? 4 : 8); ++i) {
         const int p = t + i * TPF;
-        if (p < a.nout) {
-          if (packed) {
-            gstore(dst + (long long)p * a.ldout, cx<T>{v[i].re, T(0)});
-            gstore(dst + (long long)p * a.ldout + kN, cx<T>{v[i].im, T(0)});
-          } else {
-            gstore(dst + (long long)p * a.ldout + k2, v[i]);
-          }
-        }
+        if (p < a.nout) gstore(dst + (long long)p * a.ldout + k2, v[i]);
       }
     }
   }
@@ -629,63 +582,38 @@ __global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_fwd(FColArgs<T>
   fcol_fwd_body<T, N, HALF>(a, blockIdx.x, blockIdx.y, blockIdx.z, smem_raw);
 }
 
-// Layer loop of the transpose column pass for one group: per layer conj(eig_l) R (PACKED:
-// conj(eig0) R0 + i conj(eigN) RN), inverse FFT_x, rows a < nout stored.  The next layer's
-// eigenvalues are loaded while the current one is transformed.
-template <typename T, int N, bool PACKED, bool EVEN, bool HALF>
+// Layer loop of the transpose column pass for one group: per layer conj(eig_l) R, inverse
+// FFT_x, rows a < nout stored.  The next layer's eigenvalues are loaded while the current one
+// is transformed.
+template <typename T, int N, bool EVEN, bool HALF>
 __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
-                                           int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8],
-                                           const cx<T> (&Rm)[8]) {
+                                           int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8]) {
   constexpr int TPF = N / 8;
   GroupSync<TPF> gsync;
-  const int kN = a.K2 - 1;
   cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
-  cx<T>* dstN = a.out + b * a.out_bs + (long long)kN * a.ldout;
   const long long lstride_out = (long long)a.K2 * a.ldout;
   const int nit = (l1 - l0 + G - 1) / G;
-  using Buf = ColBuf<T, false, PACKED>;
+  using Buf = ColBuf<T, false>;
   auto fetch = [&](Buf& B, int l) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int le = l < l1 ? l : l0;  // a layer that exists, for the discarded loads
       B.en[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, k2), t + i * TPF, l < l1);
-      if constexpr (PACKED)
-        B.enN[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, kN), t + i * TPF, l < l1);
     }
   };
   auto layer = [&](int it, Buf& B) {
     const int l = l0 + it * G + f;
     const bool act = l < l1;
     cx<T> v[8];
-    if constexpr (PACKED) {
-      // conj(eig0) . R0 + i conj(eigN) . RN with R0, RN split from the packed spectrum
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const cx<T> A = R[i], C = Rm[i];
-        const T h = T(0.5);
-        const cx<T> r0{h * (A.re + C.re), h * (A.im - C.im)};
-        const cx<T> rn{h * (A.im + C.im), h * (C.re - A.re)};
-        const cx<T> p0 = cmulc(r0, B.en[i]), pn = cmulc(rn, B.enN[i]);
-        v[i] = cx<T>{p0.re - pn.im, p0.im + pn.re};
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], B.en[i]);
-    }
+    for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], B.en[i]);
     if (it + 1 < nit) fetch(B, l + G);
     F.template run<true>(v, buf, t, gsync);
     if (act) {
 #pragma unroll
       for (int i = 0; i < (HALF ? 4 : 8); ++i) {
         const int p = t + i * TPF;
-        if (p < a.nout) {
-          if constexpr (PACKED) {
-            gstore(dst + l * lstride_out + p, cx<T>{v[i].re, T(0)});
-            gstore(dstN + l * lstride_out + p, cx<T>{v[i].im, T(0)});
-          } else {
-            gstore(dst + l * lstride_out + p, v[i]);
-          }
-        }
+        if (p < a.nout) gstore(dst + l * lstride_out + p, v[i]);
       }
     }
   };
@@ -698,14 +626,12 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
 // each layer of chunk c, conj(eig_l) R and the inverse FFT_x; rows a < nout are written
 // to out[l][k2][a] (ldout = padded rows).  Rrow is row-major Rrow[p][k2] (ldin = padded K2).
 template <typename T, int N, bool HALF>
-__device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int c, int b, unsigned char* smem_raw) {
+__device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int k2, int c, int b, unsigned char* smem_raw) {
   using P = Pow2<N>;
   constexpr int TPF = P::TPF;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
   const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
   const int G = a.fpb;
-  const bool packed = job == 0;
-  const int k2 = job, kN = a.K2 - 1;
   const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
   cx<T>* buf = smem + f * P::BUF;
   cx<T>* Rs = smem + G * P::BUF;  // the shared column spectrum, N values
@@ -718,11 +644,7 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int n = t + i * TPF;
-      const long long o = (long long)n * a.ldin;
-      R[i] = (HALF && i >= 4) || n >= a.nin ? cx<T>{T(0), T(0)}
-                        : (packed ? cx<T>{gload(reinterpret_cast<const T*>(col + o)),
-                                          gload(reinterpret_cast<const T*>(col + o + kN))}
-                                  : gload(col + o + k2));
+      R[i] = (HALF && i >= 4) || n >= a.nin ? cx<T>{T(0), T(0)} : gload(col + (long long)n * a.ldin + k2);
     }
     F.template run<false>(R, buf, t, gsync);
     if (f == 0) {
@@ -731,20 +653,11 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int job, int
     }
   }
   __syncthreads();
-  cx<T> R[8], Rm[8];  // Rm: the mirrored values Z[-k] of the packed job
+  cx<T> R[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int k = t + i * TPF;
-    R[i] = Rs[k];
-    if (packed) Rm[i] = Rs[(N - k) & (N - 1)];
-  }
-  if (a.eig_even) {
-    if (packed) adj_layers<T, N, true, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-    else adj_layers<T, N, false, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-  } else {
-    if (packed) adj_layers<T, N, true, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-    else adj_layers<T, N, false, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, Rm);
-  }
+  for (int i = 0; i < 8; ++i) R[i] = Rs[t + i * TPF];
+  if (a.eig_even) adj_layers<T, N, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R);
+  else adj_layers<T, N, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R);
 }
 
 template <typename T, int N, bool HALF>

@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(col_threads(sizeof(T))) k_gcol(GLaunch<T> g) {
   const int i = uniform(g.idx[k]);
   const GMember<T> M = launch_const(g.mem + i);
   const int local = blockIdx.x - g.start[k];
-  const int jobs = M.K2 - 1;
+  const int jobs = M.K2;
   const int c = local / jobs, job = local - c * jobs;
   const int G = g.bt / (N / 8);
   if constexpr (FWD) {
@@ -134,10 +134,10 @@ static int layout(Group* g) {
     g->nch[i] = nch;
     const long long b[GS_COUNT] = {
         (long long)P->nz * ceil_div(P->nx, 2 * Grm),  // F1
-        (long long)(P->K2 - 1) * nch,                 // F2
+        (long long)P->K2 * nch,                       // F2
         (long long)ceil_div(P->sx, 2 * Grd),          // F3
         (long long)ceil_div(P->sx, 2 * Grd),          // T1
-        (long long)(P->K2 - 1) * nch,                 // T2
+        (long long)P->K2 * nch,                       // T2
         (long long)P->nz * ceil_div(P->nx, 2 * Grm),  // T3
     };
     const size_t l[GS_COUNT] = {

@@ -104,7 +104,7 @@ int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, int e
              long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
              const cx<T>* tw, int batch, hipStream_t s) {
   FColArgs<T> a{in, in_bs, eig, out, out_bs, out_cs, L, nin, nout, ldin, ldout, K2, G, nchunk, tw, eig_even};
-  dim3 grid(K2 - 1, nchunk, batch), block(G * (N / 8));
+  dim3 grid(K2, nchunk, batch), block(G * (N / 8));
   const size_t sh = fast_col_lds(N, sizeof(T), G, fwd);
   const bool half = 2 * nin <= N && 2 * nout <= N;  // zero-padded inputs, unstored outputs
   if (fwd) {
