@@ -80,7 +80,7 @@ struct FRowArgs {
 template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
 __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T>& fz, int bx, int by, int pid,
                                               int pcount, unsigned char* smem_raw) {
-  static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT), "fused form");
+  static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT) || (MODE == FUSE_RUPD && ROWOUT), "fused form");
   // (the direction form takes the full form: with the half one it needs more than 64 registers)
   static_assert(!(MODE == FUSE_DIR && HALF), "direction form in the half form");
   using P = Pow2<N>;
@@ -158,6 +158,45 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
         }
         v[4 * h + i] = cx<T>{xa, xb};
       }
+    }
+  } else if constexpr (MODE == FUSE_RUPD) {
+    // The residual update of the previous CG step, r~ <- r~ - s q (RRCG:7, data space), carried
+    // by the transform of W_d r~ that starts the next step: every load first, then the step
+    // length s from its partials (RRCG:6), the stores of r~ and the transform input.
+    T RA[8], RB[8], QA[8], QB[8], ZA[8], ZB[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int n = t + i * TPF;
+      const bool ok = (!HALF || i < 4) && n < a.ncols;
+      const long long oa = (long long)r0 * a.ncols + n;
+      RA[i] = gload_or<T>(fz.r, oa, ok && ra);
+      QA[i] = gload_or(fz.q, oa, ok && ra);
+      ZA[i] = sc ? gload_or(sc, oa, ok && ra, T(1)) : T(1);
+      RB[i] = gload_or<T>(fz.r, oa + a.ncols, ok && rb);
+      QB[i] = gload_or(fz.q, oa + a.ncols, ok && rb);
+      ZB[i] = sc ? gload_or(sc, oa + a.ncols, ok && rb, T(1)) : T(1);
+    }
+    double st[2];
+    step_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lam[0], fz.lam[1], fz.coupled, fz.lead && pid == 0, st);
+    const double s = uniform(fz.self == 0 ? st[0] : st[1]);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int n = t + i * TPF;
+      T xa = T(0), xb = T(0);
+      if ((!HALF || i < 4) && n < a.ncols) {
+        const long long oa = (long long)r0 * a.ncols + n;
+        if (ra) {
+          const T rn = (T)((double)RA[i] - s * (double)QA[i]);
+          gstore(fz.r + oa, rn);
+          xa = sc ? rn * ZA[i] : rn;
+        }
+        if (rb) {
+          const T rn = (T)((double)RB[i] - s * (double)QB[i]);
+          gstore(fz.r + oa + a.ncols, rn);
+          xb = sc ? rn * ZB[i] : rn;
+        }
+      }
+      v[i] = cx<T>{xa, xb};
     }
   } else {
 #pragma unroll

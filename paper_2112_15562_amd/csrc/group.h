@@ -67,12 +67,27 @@ struct Group {
   int* t_kid;
 };
 
+// The member of a launch that block blk belongs to (start: first block of each member).
+__device__ __forceinline__ int group_member(const int* start, int count, int blk) {
+  int i = 0;
+  while (i + 1 < count && blk >= start[i + 1]) ++i;
+  return i;
+}
+
 int group_create(const bttb_plan* plans, int count, void* stream, Group** out);
 void group_destroy(Group* g);
 int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s);
 int group_autotune(Group* g, int reps, hipStream_t s, bttb_tune_result* out);
+// skip_first: leave out the first stage (its work done elsewhere).
 template <typename T>
 int group_apply_impl(const Group* g, int op, const void* const* in, void* const* out, const void* const* winv,
-                     const void* const* wd, const Fuse<T>* fz, hipStream_t s);
+                     const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first = 0);
+// One launch of stage st over all members at bt threads per block, when the members share one
+// transform size and half form: *L, its blocks, the transform size, the half form and the LDS.
+// BTTB_ESTATE when they do not.
+template <typename T>
+int group_stage_launch(const Group* g, int st, int bt, const Fuse<T>* fz, const void* const* in, void* const* out,
+                       const void* const* winv, const void* const* wd, GLaunch<T>* L, int* blocks, int* N,
+                       int* half, size_t* lds);
 
 }  // namespace bttb

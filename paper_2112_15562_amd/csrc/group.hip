@@ -21,11 +21,6 @@
 
 namespace bttb {
 
-__device__ __forceinline__ int group_member(const int* start, int count, int blk) {
-  int i = 0;
-  while (i + 1 < count && blk >= start[i + 1]) ++i;
-  return i;
-}
 
 template <typename T, int MODE>
 __device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
@@ -249,7 +244,7 @@ static auto stage_kernel(int st, bool fused, bool half) -> void (*)(GLaunch<T>) 
 
 template <typename T>
 int group_apply_impl(const Group* g_, int op, const void* const* in, void* const* out, const void* const* winv,
-                     const void* const* wd, const Fuse<T>* fz, hipStream_t s) {
+                     const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first) {
   Group* g = const_cast<Group*>(g_);  // timing state only
   auto run = [&](int st) -> int {
     if (g->blocks[st] == 0) return BTTB_OK;
@@ -275,23 +270,62 @@ int group_apply_impl(const Group* g_, int op, const void* const* in, void* const
     if (tk >= 0) (void)hipEventRecord(g->t_ev[2 * tk + 1], s);
     return BTTB_OK;
   };
-  int rc;
+  int rc = BTTB_OK;
   if (op == BTTB_OP_FORWARD) {
-    rc = run(GS_F1);
+    if (!skip_first) rc = run(GS_F1);
     if (!rc) rc = run(GS_F2);
     if (!rc) rc = run(GS_F3);
   } else {
-    rc = run(GS_T1);
+    if (!skip_first) rc = run(GS_T1);
     if (!rc) rc = run(GS_T2);
     if (!rc) rc = run(GS_T3);
   }
   return rc;
 }
 
+template <typename T>
+int group_stage_launch(const Group* g, int st, int bt, const Fuse<T>* fz, const void* const* in, void* const* out,
+                       const void* const* winv, const void* const* wd, GLaunch<T>* L, int* blocks, int* N,
+                       int* half, size_t* lds) {
+  if (g->ncls[st] != 1) return BTTB_ESTATE;  // several transform sizes or half forms
+  const GClass& C0 = g->cls[st][0];
+  const int tr = C0.N / 8;
+  if (bt < tr || bt % tr) return BTTB_ESTATE;
+  const int G = bt / tr;
+  const size_t esz = g->precision == BTTB_F64 ? 8 : 4;
+  GClass C{};
+  C.N = C0.N;
+  C.half = C0.half;
+  C.count = C0.count;
+  C.start[0] = 0;
+  if (st == GS_F2 || st == GS_T2) return BTTB_ESTATE;  // row stages only
+  for (int k = 0; k < C0.count; ++k) {
+    const Plan* P = g->P[C0.idx[k]];
+    const int rows = (st == GS_F1 || st == GS_T3) ? P->nz * ceil_div(P->nx, 2 * G) : ceil_div(P->sx, 2 * G);
+    C.idx[k] = C0.idx[k];
+    C.start[k + 1] = C.start[k] + rows;
+  }
+  C.lds = fast_row_lds(C.N, esz, G);
+  *L = launch_of<T>(g, st, C, fz, in, out, winv, wd);
+  L->bt = bt;
+  *blocks = C.start[C.count];
+  *N = C.N;
+  *half = C.half;
+  *lds = C.lds;
+  return BTTB_OK;
+}
+
+template int group_stage_launch<float>(const Group*, int, int, const Fuse<float>*, const void* const*, void* const*,
+                                       const void* const*, const void* const*, GLaunch<float>*, int*, int*, int*,
+                                       size_t*);
+template int group_stage_launch<double>(const Group*, int, int, const Fuse<double>*, const void* const*,
+                                        void* const*, const void* const*, const void* const*, GLaunch<double>*, int*,
+                                        int*, int*, size_t*);
+
 template int group_apply_impl<float>(const Group*, int, const void* const*, void* const*, const void* const*,
-                                     const void* const*, const Fuse<float>*, hipStream_t);
+                                     const void* const*, const Fuse<float>*, hipStream_t, int);
 template int group_apply_impl<double>(const Group*, int, const void* const*, void* const*, const void* const*,
-                                      const void* const*, const Fuse<double>*, hipStream_t);
+                                      const void* const*, const Fuse<double>*, hipStream_t, int);
 
 int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s) {
   const int orm = g->bt_rm, ord = g->bt_rd, oc = g->bt_c, onc = g->nchunk;

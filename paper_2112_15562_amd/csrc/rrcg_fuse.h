@@ -28,7 +28,7 @@ enum {
   PB_NSLOT = 16
 };
 // Fused forms of the row transforms.
-enum { FUSE_NONE = 0, FUSE_DIR = 1, FUSE_GRAD = 2, FUSE_QQ = 3 };
+enum { FUSE_NONE = 0, FUSE_DIR = 1, FUSE_GRAD = 2, FUSE_QQ = 3, FUSE_RUPD = 4 };
 
 template <typename T>
 struct Fuse {
@@ -43,6 +43,8 @@ struct Fuse {
   const T* m[2];  // GRAD: models of both data sets (original space)
   const T* w[2];  // GRAD: weights of both data sets
   const T* ma;    // GRAD: m_apr of this data set, or NULL for zero
+  T* r;           // RUPD: weighted residual r~ of this data set, updated in place
+  const T* q;     // RUPD: q = A~ p of this data set
   double* sc;     // scalars
   double* pb;     // [PB_NSLOT][pbs] partials
   int* pbn;       // [PB_NSLOT] number of partials in each slot

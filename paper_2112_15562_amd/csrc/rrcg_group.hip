@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fast_kernels.h"
 #include "group.h"
 #include "rrcg_fuse.h"
 #include "rrcg_kernels.h"
@@ -78,6 +79,34 @@ __global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gupdate(const GInv<T>
                  v.sc, v.lam[0], v.lam[1], v.coupled, v.gram_w, Red{v.pb, v.pbn, v.pbs}, local, nb);
 }
 
+// The update of a CG step that another step follows, in one launch: the next step's first
+// transform (the data rows of W_d r~) with the residual update r~ <- r~ - s q in its prologue,
+// in the first nt1 blocks (whose lead blocks record the step length), and the model update with
+// its Gramian partials in the elementwise blocks after them.
+template <typename T, int N, bool HALF>
+__global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gupdate_t1(const GInv<T>* inv, GStart st, GLaunch<T> g,
+                                                                     int nt1) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  if ((int)blockIdx.x < nt1) {
+    const int k = uniform(group_member(g.start, g.count, blockIdx.x));
+    const int i = uniform(g.idx[k]);
+    const GMember<T> M = launch_const(g.mem + i);
+    const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
+    const int G = g.bt / (N / 8);
+    const FRowArgs<T> a{launch_const(g.in + i), 0, g.wd ? launch_const(g.wd + i) : nullptr, M.V, 0, 0, 1, 1, M.sx,
+                        M.sy, M.ldk, M.K2, G, (M.sx + 2 * G - 1) / (2 * G), M.twy};
+    const Fuse<T> fz = launch_const(g.fz + i);
+    frow_r2c_body<T, N, true, FUSE_RUPD, HALF>(a, fz, local, 0, local, nb, smem_raw);
+    return;
+  }
+  const int b = blockIdx.x - nt1;
+  const int i = uniform(inversion_of(st, b));
+  const GInv<T> v = launch_const(inv + i);
+  const int local = b - st.start[i], nb = st.start[i + 1] - st.start[i];
+  update_body<T>(v.n, 0, v.m[0], v.m[1], v.p[0], v.p[1], v.w[0], v.w[1], v.rt[0], v.rt[1], v.qv[0], v.qv[1], v.sc,
+                 v.lam[0], v.lam[1], v.coupled, v.gram_w, Red{v.pb, v.pbn, v.pbs}, local, nb, false);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gclip(const GInv<T>* inv, GStart st, int advance) {
   const int i = uniform(inversion_of(st, blockIdx.x));
@@ -122,6 +151,7 @@ struct RrcgGroup {
   int n_graphs;
   int graph_inner[4];
   hipGraphExec_t graph[4];
+  int fuse_t1;  // the next step's first transform rides with the update (one transform size)
 };
 
 // Device pointer arrays (one entry per member) of the group products.
@@ -155,18 +185,52 @@ static int g_weights(RrcgGroup* h, hipStream_t s) {
   return BTTB_OK;
 }
 
+#define RRCG_GROUP_SIZES(N, CALL) \
+  switch (N) {                    \
+    case 32: CALL(32); break;     \
+    case 64: CALL(64); break;     \
+    case 128: CALL(128); break;   \
+    case 256: CALL(256); break;   \
+    case 512: CALL(512); break;   \
+    case 1024: CALL(1024); break; \
+    case 2048: CALL(2048); break; \
+    default: return fail(BTTB_ESIZE, "rrcg_group: transform size out of range"); \
+  }
+
+// CG step j of n_inner (RRCG:4-7): the transpose products with the gradient fused in, the
+// forward products with the direction and ||q||^2 fused in, and the update.  When the group's
+// data rows share one transform size, the update of every step but the last also carries the
+// next step's first transform (with the residual update), which that step then skips.
 template <typename T>
-static int g_inner(RrcgGroup* h, int restart_now, hipStream_t s) {
-  const Fuse<T>* fz = static_cast<const Fuse<T>*>(h->fz[restart_now ? 1 : 0]);
+static int g_inner(RrcgGroup* h, int j, int n_inner, hipStream_t s) {
+  const Fuse<T>* fz = static_cast<const Fuse<T>*>(h->fz[j == 0 ? 1 : 0]);
+  const bool t1_done = h->fuse_t1 && j > 0, fuse_next = h->fuse_t1 && j + 1 < n_inner;
   int rc = group_apply_impl<T>(h->grp, BTTB_OP_ADJOINT, pa(h, PA_RT), const_cast<void* const*>(pa(h, PA_L)),
-                               pa(h, PA_WI), pa(h, PA_WD), fz, s);
+                               pa(h, PA_WI), pa(h, PA_WD), fz, s, t1_done ? 1 : 0);
   if (rc) return rc;
   rc = group_apply_impl<T>(h->grp, BTTB_OP_FORWARD, pa(h, PA_P), const_cast<void* const*>(pa(h, PA_QV)),
                            pa(h, PA_WI), pa(h, PA_WD), fz, s);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_gupdate<T>, dim3(h->est.start[h->count]), dim3(eb_threads(sizeof(T))), 0, s,
-                     static_cast<const GInv<T>*>(h->inv), h->est);
-  BTTB_LAUNCHED("k_gupdate");
+  const GInv<T>* inv = static_cast<const GInv<T>*>(h->inv);
+  if (!fuse_next) {
+    hipLaunchKernelGGL(k_gupdate<T>, dim3(h->est.start[h->count]), dim3(eb_threads(sizeof(T))), 0, s, inv, h->est);
+    BTTB_LAUNCHED("k_gupdate");
+    return BTTB_OK;
+  }
+  GLaunch<T> L{};
+  int nt1 = 0, N = 0, half = 0;
+  size_t lds = 0;
+  rc = group_stage_launch<T>(h->grp, GS_T1, eb_threads(sizeof(T)), fz, pa(h, PA_RT), nullptr, nullptr,
+                             pa(h, PA_WD), &L, &nt1, &N, &half, &lds);
+  if (rc) return fail(rc, "rrcg_group: fused update launch");
+  const dim3 grid(nt1 + h->est.start[h->count]);
+#define RRCG_K(NN)                                                                                    \
+  if (half) hipLaunchKernelGGL((k_gupdate_t1<T, NN, true>), grid, dim3(eb_threads(sizeof(T))), lds, s, inv, \
+                               h->est, L, nt1);                                                       \
+  else hipLaunchKernelGGL((k_gupdate_t1<T, NN, false>), grid, dim3(eb_threads(sizeof(T))), lds, s, inv, h->est, L, nt1)
+  RRCG_GROUP_SIZES(N, RRCG_K)
+#undef RRCG_K
+  BTTB_LAUNCHED("k_gupdate_t1");
   return BTTB_OK;
 }
 
@@ -215,7 +279,7 @@ static int g_step_graph(RrcgGroup* h, int n_inner, hipGraphExec_t* out) {
   hipGraphExec_t e = nullptr;
   const int rc = g_capture(h, [&](hipStream_t s) {
     int r = g_weights<T>(h, s);
-    for (int j = 0; j < n_inner && !r; ++j) r = g_inner<T>(h, j == 0 ? 1 : 0, s);
+    for (int j = 0; j < n_inner && !r; ++j) r = g_inner<T>(h, j, n_inner, s);
     return r ? r : g_outer<T>(h, s, 1);
   }, &e);
   if (rc) return rc;
@@ -236,7 +300,7 @@ static int g_step(RrcgGroup* h, int n_inner, hipStream_t s) {
     return BTTB_OK;
   }
   int rc = g_weights<T>(h, s);
-  for (int j = 0; j < n_inner && !rc; ++j) rc = g_inner<T>(h, j == 0 ? 1 : 0, s);
+  for (int j = 0; j < n_inner && !rc; ++j) rc = g_inner<T>(h, j, n_inner, s);
   return rc ? rc : g_outer<T>(h, s, 1);
 }
 
@@ -358,12 +422,24 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
         f.w[0] = v.w[0];
         f.w[1] = v.w[1];
         f.ma = v.mapr[k];
+        f.r = v.rt[k];
+        f.q = v.qv[k];
         f.sc = v.sc;
         f.pb = v.pb;
         f.pbn = v.pbn;
         f.pbs = v.pbs;
       }
     }
+  }
+  {  // In FP32 the update carries the next step's first transform when the data rows share one
+     // transform size.  (The FP64 fused kernel needs 110 registers: with the transform's blocks
+     // added, a large inversion's update would no longer fit the CUs in one round.)
+    GLaunch<T> L{};
+    int nt1 = 0, N = 0, half = 0;
+    size_t lds = 0;
+    h->fuse_t1 = sizeof(T) == 4 && group_stage_launch<T>(h->grp, GS_T1, eb_threads(sizeof(T)), nullptr, nullptr,
+                                                         nullptr, nullptr, nullptr, &L, &nt1, &N, &half,
+                                                         &lds) == BTTB_OK;
   }
   BTTB_HIP(hipMemcpyAsync(h->inv, inv, sizeof(GInv<T>) * h->count, hipMemcpyHostToDevice, s));
   for (int r = 0; r < 2; ++r)
@@ -558,14 +634,15 @@ static int g_autotune(RrcgGroup* h, int reps, hipStream_t s, bttb_tune_result* o
   int cur[4] = {g->bt_rm, g->bt_rd, g->bt_c, g->nchunk};
   float best = -1.0f;
   int tried = 0;
-  // a candidate runs as the solve does: one CG step captured as a graph and replayed; the
-  // best of two rounds of `reps` replays
+  // a candidate runs as the solve does: one CG step (a middle one: its first transform done by
+  // the previous update, its update carrying the next one's) captured as a graph and replayed;
+  // the best of two rounds of `reps` replays
   auto measure = [&](float* ms) -> int {
     int r = g_weights<T>(h, s);  // valid weights for the timed steps
     if (r) return r;
     hipGraphExec_t e = nullptr;
     if (h->use_graph) {
-      r = g_capture(h, [&](hipStream_t cs) { return g_inner<T>(h, 0, cs); }, &e);
+      r = g_capture(h, [&](hipStream_t cs) { return g_inner<T>(h, 1, 3, cs); }, &e);
       if (r) return r;
     }
     auto one = [&]() -> int {
@@ -573,7 +650,7 @@ static int g_autotune(RrcgGroup* h, int reps, hipStream_t s, bttb_tune_result* o
         BTTB_HIP(hipGraphLaunch(e, s));
         return BTTB_OK;
       }
-      return g_inner<T>(h, 0, s);
+      return g_inner<T>(h, 1, 3, s);
     };
     float bestm = -1.0f;
     r = one();  // warm-up

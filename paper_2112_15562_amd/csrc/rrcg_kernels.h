@@ -150,18 +150,20 @@ __device__ __forceinline__ void sumsq2_body(long long n, const T* a0, const T* a
 }
 
 // s from the partials (RRCG:6); m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w);
-// r~ <- r~ - s q; Gramian partials of the new m (on m or on w m).  Every load of an
-// iteration goes out before its first store: vector memory operations complete in issue
-// order, so a load issued after a store could only be waited for together with it.
+// r~ <- r~ - s q (for nd > 0); Gramian partials of the new m (on m or on w m).  Block 0
+// records the step length unless `record` is off (another part of the launch records it).
+// Every load of an iteration goes out before its first store: vector memory operations
+// complete in issue order, so a load issued after a store could only be waited for together
+// with it.
 template <typename T>
 __device__ __forceinline__ void update_body(long long n, long long nd, T* m0, T* m1, const T* p0, const T* p1,
                                             const T* w0, const T* w1, T* r0, T* r1, const T* q0, const T* q1,
                                             double* sc, double lam0, double lam1, int coupled, int gram_w,
-                                            Red rd, int bid, int nb) {
+                                            Red rd, int bid, int nb, bool record = true) {
   constexpr int U = EW_UNROLL;
   const int nt = blockDim.x;
   double st[2];
-  step_from(sc, rd.pb, rd.pbn, rd.pbs, lam0, lam1, coupled, bid == 0, st);
+  step_from(sc, rd.pb, rd.pbn, rd.pbs, lam0, lam1, coupled, record && bid == 0, st);
   const double s0 = uniform(st[0]), s1 = uniform(st[1]);
   double v[3] = {0.0, 0.0, 0.0};
   const long long top = n > nd ? n : nd;
