@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "72a567cb4ed4627051b7cd4c0e9dfd902abe506c5c59dd919eafe8dcae7f2345",
+    "csrc_sha256": "d34e11d1b1afe89826486698c2fdbf575d72d7724bcd7f0f0e449a6676d08c7d",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50656042, 50536380), "fwd_col_eig_sum": (77139130, 4696159),
-        "fwd_row_c2r": (1917565, 532211), "adj_row_r2c": (1187302, 1064960),
-        "adj_col_conj_eig": (52135872, 33685504), "adj_row_c2r": (101507131, 16814178),
+        "fwd_row_r2c": (50655406, 50536392), "fwd_col_eig_sum": (77081813, 8108930),
+        "fwd_row_c2r": (1910176, 532211), "adj_row_r2c": (1062854, 1064960),
+        "adj_col_conj_eig": (52030623, 33685504), "adj_row_c2r": (103528030, 16814191),
     },
 }
 
