@@ -253,8 +253,8 @@ def group_kernel_bytes(infos, esz):
     """Bytes each launch of the solver's product group must move (all members, one plan
     info each): as kernel_bytes, plus the vectors the fused CG pieces read and write -- the
     direction update in the forward row transform (reads l, p, 1/w, writes p) and the
-    gradient in the transpose's inverse row transform (reads m of both data sets, w, 1/w;
-    writes l)."""
+    gradient in the transpose's inverse row transform (reads m of both data sets and w, which
+    also divides the transform; writes l)."""
     tot = {}
     for info in infos:
         nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
@@ -269,7 +269,7 @@ def group_kernel_bytes(infos, esz):
             "fwd_row_c2r": K2 * sx * c + 2 * nd * esz,
             "adj_row_r2c": 2 * nd * esz + K2 * sx * c,
             "adj_col_conj_eig": eig + K2 * sx * c + U,
-            "adj_row_c2r": U + 5 * n * esz,
+            "adj_row_c2r": U + 4 * n * esz,
         }
         for k, v in per.items():
             tot[k] = tot.get(k, 0) + v

@@ -388,8 +388,9 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     const T* wsp = (s0 ? fz.w[0] : fz.w[1]) + lofs;
     const T* wop = (s0 ? fz.w[1] : fz.w[0]) + lofs;
     const T* map = fz.ma ? fz.ma + lofs : nullptr;
-    auto grad_at = [&](long long o, T zt) -> T {
-      return grad_value<T>(s0, fz.gram_w, zt, gload(m0p + o), gload(m1p + o), gload(wsp + o),
+    // (the weight divides the transform here: the weights' reciprocals are not read)
+    auto grad_at = [&](long long o, T z) -> T {
+      return grad_value<T>(s0, fz.gram_w, z, gload(m0p + o), gload(m1p + o), gload(wsp + o),
                            fz.gram_w ? gload(wop + o) : T(0), map ? gload(map + o) : T(0), al, lam, g11, g22, g12);
     };
     double acc[1] = {0.0};
@@ -399,12 +400,12 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       if (q < a.ncols) {
         const long long o = (long long)r0 * a.ncols + q;
         if (ra) {
-          const T g = grad_at(o, v[i].re * gload(sc + o));
+          const T g = grad_at(o, v[i].re);
           gstore(dst + o, g);
           acc[0] += (double)g * (double)g;
         }
         if (rb) {
-          const T g = grad_at(o + a.ncols, v[i].im * gload(sc + o + a.ncols));
+          const T g = grad_at(o + a.ncols, v[i].im);
           gstore(dst + o + a.ncols, g);
           acc[0] += (double)g * (double)g;
         }

@@ -113,16 +113,35 @@ __device__ __forceinline__ void block_allreduce(double (&v)[K]) {
   __syncthreads();
 }
 
-// Fixed-order totals of K slots' partials, in every thread of the block.
+// Fixed-order totals of K slots' partials, in every thread of the block.  The counts and the
+// first two partials of each thread go out together, in one round trip: those loads do not
+// wait for the count (every index below pbs is allocated), and the ones past it are dropped.
+// Each thread adds its partials in index order, as a plain strided loop would.
 template <int K>
 __device__ __forceinline__ void slot_totals(const double* pb, const int* pbn, int pbs, const int (&slot)[K],
                                             double (&out)[K]) {
+  constexpr int U = 2;
+  const int nt = blockDim.x;
+  int n[K];
+  double x[K][U];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    const int n = gload(pbn + slot[k]);
+    n[k] = gload(pbn + slot[k]);
     const double* src = pb + (long long)slot[k] * pbs;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = threadIdx.x + u * nt;
+      x[k][u] = gload_or(src, i, i < pbs);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += gload(src + i);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if ((int)threadIdx.x + u * nt < n[k]) s += x[k][u];
+    const double* src = pb + (long long)slot[k] * pbs;
+    for (int i = threadIdx.x + U * nt; i < n[k]; i += nt) s += gload(src + i);
     out[k] = s;
   }
   block_allreduce<K>(out);
@@ -195,14 +214,14 @@ __device__ __forceinline__ void gram_from(double* sc, const double* pb, const in
   }
 }
 
-// RRCG:4 for one element of data set `self`, given z~ = (A~^T r~)_j, the models a = m1_j,
+// RRCG:4 for one element of data set `self`, given z = (A^T W_d r~)_j, the models a = m1_j,
 // b = m2_j, the weights ws (this data set) and wo (the other; read only when gram_w) and
 // ma = m_apr of this data set (0 when there is none):
-//   l = z~ + alpha (w m - w m_apr) + lambda l_G,
+//   l = z / w + alpha (w m - w m_apr) + lambda l_G,
 //   l_G = (m2,m2) m1 - (m1,m2) m2 for data set 0, (m1,m1) m2 - (m1,m2) m1 for data set 1
 // (on w m instead of m when gram_w).
 template <typename T>
-__device__ __forceinline__ T grad_value(bool s0, int gram_w, T zt, double a, double b, double Ws, double Wo,
+__device__ __forceinline__ T grad_value(bool s0, int gram_w, T z, double a, double b, double Ws, double Wo,
                                         double ma, double al, double lam, double g11, double g22, double g12) {
   double u0 = a, u1 = b;
   if (gram_w) {
@@ -212,7 +231,7 @@ __device__ __forceinline__ T grad_value(bool s0, int gram_w, T zt, double a, dou
   const double lg = s0 ? g22 * u0 - g12 * u1 : g11 * u1 - g12 * u0;
   const double ms = s0 ? a : b;
   const double mt = Ws * ms, mta = Ws * ma;
-  return (T)((double)zt + al * (mt - mta) + lam * lg);
+  return (T)((double)z / Ws + al * (mt - mta) + lam * lg);
 }
 
 }  // namespace bttb
