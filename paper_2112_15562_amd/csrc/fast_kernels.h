@@ -41,9 +41,13 @@ constexpr int row_buf() {  // per-group LDS elements of the row kernels (exchang
 #endif
 // Waves per SIMD the row kernels are compiled for: in FP32 up to 512 points, eight, so that the
 // registers (at most 64) let four blocks of 512 threads share a CU and a whole product's row
-// blocks are resident at once.  Longer transforms hold more twiddles and keep the default.
-template <typename T, int N>
-constexpr int row_waves() { return sizeof(T) == 4 && N <= 512 ? BTTB_ROW_WAVES32 : 2; }
+// blocks are resident at once, except the direction form in the full form, whose loads in
+// flight need more than 64 registers (six waves).  Longer transforms hold more twiddles and
+// keep the default.
+template <typename T, int N, int MODE, bool HALF>
+constexpr int row_waves() {
+  return sizeof(T) != 4 || N > 512 ? 2 : MODE == FUSE_DIR && !HALF ? BTTB_GRAD_WAVES32 : BTTB_ROW_WAVES32;
+}
 // The inverse row transforms: the model-row ones as above, except the gradient form in the
 // full form, which needs more than 64 registers (six waves, three blocks per CU); the data-row
 // ones launch few blocks and keep their registers.
@@ -81,8 +85,6 @@ template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
 __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T>& fz, int bx, int by, int pid,
                                               int pcount, unsigned char* smem_raw) {
   static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT) || (MODE == FUSE_RUPD && ROWOUT), "fused form");
-  // (the direction form takes the full form: with the half one it needs more than 64 registers)
-  static_assert(!(MODE == FUSE_DIR && HALF), "direction form in the half form");
   using P = Pow2<N>;
   constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
@@ -105,7 +107,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     // operations complete in issue order, so a load issued after a store could only be
     // waited for together with it), half of a thread's entries (4 h .. 4 h + 3, both rows)
     // at a time; the first half before the partial sums of beta, whose loads then overlap
-    // them.  The upper half is empty when a row fills at most half the transform.
+    // them.  The half form has no upper half: a row fills at most half the transform.
     const T* lv = fz.l + lofs;
     T* pv = fz.p + lofs;
     T LA[4], LB[4], PA[4], PB[4], SA[4], SB[4];
@@ -115,12 +117,12 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
         const int n = t + (4 * h + i) * TPF;
         const bool ok = n < a.ncols;
         const long long oa = (long long)r0 * a.ncols + n;
-        LA[i] = gload_or(lv, oa, ok && ra);
-        PA[i] = gload_or(pv, oa, ok && ra);
-        SA[i] = gload_or(sc, oa, ok && ra);
-        LB[i] = gload_or(lv, oa + a.ncols, ok && rb);
-        PB[i] = gload_or(pv, oa + a.ncols, ok && rb);
-        SB[i] = gload_or(sc, oa + a.ncols, ok && rb);
+        LA[i] = gload_or(lv, oa, ok & ra);
+        PA[i] = gload_or(pv, oa, ok & ra);
+        SA[i] = gload_or(sc, oa, ok & ra);
+        LB[i] = gload_or(lv, oa + a.ncols, ok & rb);
+        PB[i] = gload_or(pv, oa + a.ncols, ok & rb);
+        SB[i] = gload_or(sc, oa + a.ncols, ok & rb);
       }
     };
     dir_load(0);
@@ -131,6 +133,11 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (h == 1) {
+        if constexpr (HALF) {  // the upper half of the transform input is zero padding
+#pragma unroll
+          for (int i = 4; i < 8; ++i) v[i] = cx<T>{T(0), T(0)};
+          break;
+        }
         if (t + 4 * TPF < a.ncols) dir_load(1);
       }
 #pragma unroll
@@ -161,55 +168,75 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     }
   } else if constexpr (MODE == FUSE_RUPD) {
     // The residual update of the previous CG step, r~ <- r~ - s q (RRCG:7, data space), carried
-    // by the transform of W_d r~ that starts the next step: every load first, then the step
-    // length s from its partials (RRCG:6), the stores of r~ and the transform input.
-    T RA[8], RB[8], QA[8], QB[8], ZA[8], ZB[8];
+    // by the transform of W_d r~ that starts the next step: the loads of four entries per row
+    // first, then (once) the step length s from its partials (RRCG:6), the stores of r~ and
+    // the transform input; the full form takes its upper four entries the same way after.
+    // (without a scale the factors are ones, read from r~'s first entry and discarded)
+    const T* zbase = sc ? sc : fz.r;
+    const bool scaled = sc != nullptr;
+    double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      const bool ok = (!HALF || i < 4) && n < a.ncols;
-      const long long oa = (long long)r0 * a.ncols + n;
-      RA[i] = gload_or<T>(fz.r, oa, ok && ra);
-      QA[i] = gload_or(fz.q, oa, ok && ra);
-      ZA[i] = sc ? gload_or(sc, oa, ok && ra, T(1)) : T(1);
-      RB[i] = gload_or<T>(fz.r, oa + a.ncols, ok && rb);
-      QB[i] = gload_or(fz.q, oa + a.ncols, ok && rb);
-      ZB[i] = sc ? gload_or(sc, oa + a.ncols, ok && rb, T(1)) : T(1);
-    }
-    double st[2];
-    step_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lam[0], fz.lam[1], fz.coupled, fz.lead && pid == 0, st);
-    const double s = uniform(fz.self == 0 ? st[0] : st[1]);
+    for (int h = 0; h < (HALF ? 1 : 2); ++h) {
+      T RA[4], RB[4], QA[4], QB[4], ZA[4], ZB[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int n = t + i * TPF;
-      T xa = T(0), xb = T(0);
-      if ((!HALF || i < 4) && n < a.ncols) {
+      for (int i = 0; i < 4; ++i) {
+        const int n = t + (4 * h + i) * TPF;
+        const bool ok = n < a.ncols;
         const long long oa = (long long)r0 * a.ncols + n;
-        if (ra) {
-          const T rn = (T)((double)RA[i] - s * (double)QA[i]);
-          gstore(fz.r + oa, rn);
-          xa = sc ? rn * ZA[i] : rn;
-        }
-        if (rb) {
-          const T rn = (T)((double)RB[i] - s * (double)QB[i]);
-          gstore(fz.r + oa + a.ncols, rn);
-          xb = sc ? rn * ZB[i] : rn;
-        }
+        RA[i] = gload_or<T>(fz.r, oa, ok & ra);
+        QA[i] = gload_or(fz.q, oa, ok & ra);
+        ZA[i] = gload_or(zbase, oa, ok & ra & scaled, T(1));
+        RB[i] = gload_or<T>(fz.r, oa + a.ncols, ok & rb);
+        QB[i] = gload_or(fz.q, oa + a.ncols, ok & rb);
+        ZB[i] = gload_or(zbase, oa + a.ncols, ok & rb & scaled, T(1));
       }
-      v[i] = cx<T>{xa, xb};
+      if (h == 0) {
+        double st[2];
+        step_from(fz.sc, fz.pb, fz.pbn, fz.pbs, fz.lam[0], fz.lam[1], fz.coupled, fz.lead && pid == 0, st);
+        s = uniform(fz.self == 0 ? st[0] : st[1]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int n = t + (4 * h + i) * TPF;
+        T xa = T(0), xb = T(0);
+        if (n < a.ncols) {
+          const long long oa = (long long)r0 * a.ncols + n;
+          if (ra) {
+            const T rn = (T)((double)RA[i] - s * (double)QA[i]);
+            gstore(fz.r + oa, rn);
+            xa = rn * ZA[i];
+          }
+          if (rb) {
+            const T rn = (T)((double)RB[i] - s * (double)QB[i]);
+            gstore(fz.r + oa + a.ncols, rn);
+            xb = rn * ZB[i];
+          }
+        }
+        v[4 * h + i] = cx<T>{xa, xb};
+      }
+    }
+    if constexpr (HALF) {
+#pragma unroll
+      for (int i = 4; i < 8; ++i) v[i] = cx<T>{T(0), T(0)};
     }
   } else {
+    // every load first, branch-free: entries out of range read the layer's first entry and
+    // give zero; without a scale the factors are ones
+    const T* sbase = sc ? sc : src;
+    const bool scaled = sc != nullptr;
+    T XA[8], XB[8], SA[8], SB[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int n = t + i * TPF;
-      T xa = T(0), xb = T(0);
-      if ((!HALF || i < 4) && n < a.ncols) {
-        const long long oa = (long long)r0 * a.ncols + n;
-        if (ra) xa = sc ? gload(src + oa) * gload(sc + oa) : gload(src + oa);
-        if (rb) xb = sc ? gload(src + oa + a.ncols) * gload(sc + oa + a.ncols) : gload(src + oa + a.ncols);
-      }
-      v[i] = cx<T>{xa, xb};
+      const bool ok = (!HALF || i < 4) & (n < a.ncols);
+      const long long oa = (long long)r0 * a.ncols + n;
+      XA[i] = gload_or(src, oa, ok & ra);
+      SA[i] = gload_or(sbase, oa, ok & ra & scaled, T(1));
+      XB[i] = gload_or(src, oa + a.ncols, ok & rb);
+      SB[i] = gload_or(sbase, oa + a.ncols, ok & rb & scaled, T(1));
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = cx<T>{XA[i] * SA[i], XB[i] * SB[i]};
   }
   F.init(a.tw, t);  // twiddles loaded here: not live during the prologue
   F.template run<false>(v, buf, t, gsync);
@@ -262,7 +289,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
 }
 
 template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
-__global__ void __launch_bounds__(512, (row_waves<T, N>())) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
+__global__ void __launch_bounds__(512, (row_waves<T, N, MODE, HALF>())) k_frow_r2c(FRowArgs<T> a, Fuse<T> fz) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   frow_r2c_body<T, N, ROWOUT, MODE, HALF>(a, fz, blockIdx.x, blockIdx.y, blockIdx.x + gridDim.x * blockIdx.y,
                                           gridDim.x * gridDim.y, smem_raw);
@@ -292,18 +319,17 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   cx<T>* buf = smem + f * BS;
   GroupSync<TPF> gsync;
   RegFFT<T, N> F;
-  double gg[3] = {0.0, 0.0, 0.0};  // Gramian scalars for the gradient form
   const int r0 = tile * RT + 2 * f;
   const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
   const long long lofs = (long long)l * a.nrows * a.ncols;
   const T* sc = a.scale ? a.scale + lofs : nullptr;
   cx<T> v[8];
+  double gg[3] = {0.0, 0.0, 0.0};  // Gramian scalars for the gradient form
   if constexpr (ROWIN) {
     // base: the start of this batch entry (valid for every lane); rows r0, r0 + 1 may lie
     // beyond nrows, where the guarded loads read the base instead
     const cx<T>* base = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs;
     const long long off = ((long long)l * a.nrows + r0) * a.ld;
-    const cx<T>* src = base + off;
     cx<T> ha[8], hb[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -313,13 +339,19 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       hb[i] = gload_or(base, off + a.ld + kk, rb);
     }
     for (int c = 1; c < a.nsum; ++c) {  // partials of the layer chunks, summed in order
-      const cx<T>* part = src + c * a.in_cs;
+      const cx<T>* pbase = base + c * a.in_cs;  // chunk c of this batch entry
+      cx<T> pa[8], pb[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < 8; ++i) {  // every load of the chunk before the first sum
         const int k = t + i * TPF;
         const int kk = k <= N / 2 ? k : N - k;
-        if (ra) ha[i] = cadd(ha[i], gload(part + kk));
-        if (rb) hb[i] = cadd(hb[i], gload(part + a.ld + kk));
+        pa[i] = gload_or(pbase, off + kk, ra);
+        pb[i] = gload_or(pbase, off + a.ld + kk, rb);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        ha[i] = cadd(ha[i], pa[i]);
+        hb[i] = cadd(hb[i], pb[i]);
       }
     }
 #pragma unroll
@@ -344,7 +376,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     for (int it = 0; it < ITER; ++it) {
       const int idx = threadIdx.x + it * blockDim.x;
       const int k2 = idx / RT, rr = idx - k2 * RT;
-      hv[it] = gload_or(src, (long long)k2 * a.ld + rr, idx < K2 * RT && rr < rows);
+      hv[it] = gload_or(src, (long long)k2 * a.ld + rr, (idx < K2 * RT) & (rr < rows));
     }
     // the Gramian scalars' partials, loaded while the spectra are in flight
     if constexpr (MODE == FUSE_GRAD) {
@@ -394,20 +426,60 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
                            fz.gram_w ? gload(wop + o) : T(0), map ? gload(map + o) : T(0), al, lam, g11, g22, g12);
     };
     double acc[1] = {0.0};
+    if (!fz.gram_w && !map) {
+      // The common form: the operands of CH entries per row go out together before any
+      // store (a load issued after a store could only be waited for together with it); the
+      // full form takes them in smaller groups, within its registers.
+      constexpr int CH = HALF ? 4 : 2;
 #pragma unroll
-    for (int i = 0; i < (HALF ? 4 : 8); ++i) {
-      const int q = t + i * TPF;
-      if (q < a.ncols) {
-        const long long o = (long long)r0 * a.ncols + q;
-        if (ra) {
-          const T g = grad_at(o, v[i].re);
-          gstore(dst + o, g);
-          acc[0] += (double)g * (double)g;
+      for (int c = 0; c < (HALF ? 4 : 8); c += CH) {
+        T A0[CH], A1[CH], AW[CH], B0[CH], B1[CH], BW[CH];
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int q = t + (c + i) * TPF;
+          const bool ok = q < a.ncols;
+          const long long o = (long long)r0 * a.ncols + q;
+          A0[i] = gload_or(m0p, o, ok & ra);
+          A1[i] = gload_or(m1p, o, ok & ra);
+          AW[i] = gload_or(wsp, o, ok & ra, T(1));
+          B0[i] = gload_or(m0p, o + a.ncols, ok & rb);
+          B1[i] = gload_or(m1p, o + a.ncols, ok & rb);
+          BW[i] = gload_or(wsp, o + a.ncols, ok & rb, T(1));
         }
-        if (rb) {
-          const T g = grad_at(o + a.ncols, v[i].im);
-          gstore(dst + o + a.ncols, g);
-          acc[0] += (double)g * (double)g;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) {
+          const int q = t + (c + i) * TPF;
+          if (q < a.ncols) {
+            const long long o = (long long)r0 * a.ncols + q;
+            if (ra) {
+              const T g = grad_value<T>(s0, 0, v[c + i].re, A0[i], A1[i], AW[i], 0.0, 0.0, al, lam, g11, g22, g12);
+              gstore(dst + o, g);
+              acc[0] += (double)g * (double)g;
+            }
+            if (rb) {
+              const T g = grad_value<T>(s0, 0, v[c + i].im, B0[i], B1[i], BW[i], 0.0, 0.0, al, lam, g11, g22, g12);
+              gstore(dst + o + a.ncols, g);
+              acc[0] += (double)g * (double)g;
+            }
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < (HALF ? 4 : 8); ++i) {
+        const int q = t + i * TPF;
+        if (q < a.ncols) {
+          const long long o = (long long)r0 * a.ncols + q;
+          if (ra) {
+            const T g = grad_at(o, v[i].re);
+            gstore(dst + o, g);
+            acc[0] += (double)g * (double)g;
+          }
+          if (rb) {
+            const T g = grad_at(o + a.ncols, v[i].im);
+            gstore(dst + o + a.ncols, g);
+            acc[0] += (double)g * (double)g;
+          }
         }
       }
     }
@@ -415,20 +487,36 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     return;
   }
   double acc[1] = {0.0};
+  // The scale factors of four entries per row go out together before any store; without a
+  // scale they are ones, read from the output's first entry and discarded (no branch).
+  const T* sbase = sc ? sc : dst;
+  const bool scaled = sc != nullptr;
 #pragma unroll
-  for (int i = 0; i < (HALF ? 4 : 8); ++i) {
-    const int q = t + i * TPF;
-    if (q < a.ncols) {
+  for (int c = 0; c < (HALF ? 4 : 8); c += 4) {
+    T SA[4], SB[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = t + (c + i) * TPF;
+      const bool ok = (q < a.ncols) & scaled;
       const long long o = (long long)r0 * a.ncols + q;
-      if (ra) {
-        const T y = sc ? v[i].re * gload(sc + o) : v[i].re;
-        gstore(dst + o, y);
-        if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
-      }
-      if (rb) {
-        const T y = sc ? v[i].im * gload(sc + o + a.ncols) : v[i].im;
-        gstore(dst + o + a.ncols, y);
-        if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
+      SA[i] = gload_or(sbase, o, ok & ra, T(1));
+      SB[i] = gload_or(sbase, o + a.ncols, ok & rb, T(1));
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = t + (c + i) * TPF;
+      if (q < a.ncols) {
+        const long long o = (long long)r0 * a.ncols + q;
+        if (ra) {
+          const T y = v[c + i].re * SA[i];
+          gstore(dst + o, y);
+          if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
+        }
+        if (rb) {
+          const T y = v[c + i].im * SB[i];
+          gstore(dst + o + a.ncols, y);
+          if constexpr (MODE == FUSE_QQ) acc[0] += (double)y * (double)y;
+        }
       }
     }
   }
@@ -518,7 +606,7 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
   auto load_col = [&](int l, int i) -> cx<T> {
     if (HALF && i >= 4) return cx<T>{T(0), T(0)};  // zero padding, known at compile time
     const int n = t + i * TPF;
-    return gload_or(src, l * lstride_in + n, l < l1 && n < a.nin);
+    return gload_or(src, l * lstride_in + n, l < l1 && n < a.nin);  // (a branch here measures faster)
   };
   auto fetch = [&](Buf& B, int l) {
 #pragma unroll

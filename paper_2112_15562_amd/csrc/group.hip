@@ -31,7 +31,7 @@ __device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
 // Row transform R2C of transform size N.  ROWOUT = false: model rows into U (forward, first
 // stage); ROWOUT = true: data rows into V (transpose, first stage).
 template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
-__global__ void __launch_bounds__(512, (row_waves<T, N>())) k_grow_r2c(GLaunch<T> g) {
+__global__ void __launch_bounds__(512, (row_waves<T, N, MODE, HALF>())) k_grow_r2c(GLaunch<T> g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int k = uniform(group_member(g.start, g.count, blockIdx.x));
   const int i = uniform(g.idx[k]);
@@ -229,7 +229,7 @@ static GLaunch<T> launch_of(const Group* g, int st, const GClass& C, const Fuse<
 template <typename T, int N, bool H>
 static auto stage_kernel_h(int st, bool fused) -> void (*)(GLaunch<T>) {
   switch (st) {
-    case GS_F1: return fused ? k_grow_r2c<T, N, false, FUSE_DIR, false> : k_grow_r2c<T, N, false, FUSE_NONE, H>;
+    case GS_F1: return fused ? k_grow_r2c<T, N, false, FUSE_DIR, H> : k_grow_r2c<T, N, false, FUSE_NONE, H>;
     case GS_F2: return k_gcol<T, N, true, H>;
     case GS_F3: return fused ? k_grow_c2r<T, N, true, FUSE_QQ, H> : k_grow_c2r<T, N, true, FUSE_NONE, H>;
     case GS_T1: return k_grow_r2c<T, N, true, FUSE_NONE, H>;

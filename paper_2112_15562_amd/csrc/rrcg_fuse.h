@@ -113,45 +113,61 @@ __device__ __forceinline__ void block_allreduce(double (&v)[K]) {
   __syncthreads();
 }
 
-// Fixed-order totals of K slots' partials, in every thread of the block.  The counts and the
-// first two partials of each thread go out together, in one round trip: those loads do not
-// wait for the count (every index below pbs is allocated), and the ones past it are dropped.
-// Each thread adds its partials in index order, as a plain strided loop would.
+// Fixed-order totals of K slots' partials, in two stages so that a kernel can issue the
+// loads before its own bulk loads and take the totals after them.  The counts and the first
+// two partials of each thread go out together, in one round trip: those loads do not wait
+// for the count (every index below pbs is allocated), and the ones past it add zero.  Each
+// thread adds its partials in index order, as a plain strided loop would.
+template <int K>
+struct SlotSums {
+  static constexpr int U = 2;
+  const double* src[K];
+  int n[K];
+  double x[K][U];
+
+  __device__ __forceinline__ void load(const double* pb, const int* pbn, int pbs, const int (&slot)[K]) {
+    const int nt = blockDim.x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      n[k] = gload(pbn + slot[k]);
+      src[k] = pb + (long long)slot[k] * pbs;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = threadIdx.x + u * nt;
+        x[k][u] = gload_or(src[k], i, i < pbs);
+      }
+    }
+  }
+  __device__ __forceinline__ void total(double (&out)[K]) {
+    const int nt = blockDim.x;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) s += (int)threadIdx.x + u * nt < n[k] ? x[k][u] : 0.0;  // a select, not a branch
+      for (int i = threadIdx.x + U * nt; i < n[k]; i += nt) s += gload(src[k] + i);
+      out[k] = s;
+    }
+    block_allreduce<K>(out);
+  }
+};
+
 template <int K>
 __device__ __forceinline__ void slot_totals(const double* pb, const int* pbn, int pbs, const int (&slot)[K],
                                             double (&out)[K]) {
-  constexpr int U = 2;
-  const int nt = blockDim.x;
-  int n[K];
-  double x[K][U];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    n[k] = gload(pbn + slot[k]);
-    const double* src = pb + (long long)slot[k] * pbs;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = threadIdx.x + u * nt;
-      x[k][u] = gload_or(src, i, i < pbs);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double s = 0.0;
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-      if ((int)threadIdx.x + u * nt < n[k]) s += x[k][u];
-    const double* src = pb + (long long)slot[k] * pbs;
-    for (int i = threadIdx.x + U * nt; i < n[k]; i += nt) s += gload(src + i);
-    out[k] = s;
-  }
-  block_allreduce<K>(out);
+  SlotSums<K> ss;
+  ss.load(pb, pbn, pbs, slot);
+  ss.total(out);
 }
 
 // RRCG:5 from the partials of ||l_i||^2: L_i and beta (joint when coupled; 0 at a restart).
-__device__ __forceinline__ void beta_from(const double* sc, const double* pb, const int* pbn, int pbs,
-                                          int restart, int coupled, double (&beta)[2], double (&L)[2]) {
+__device__ __forceinline__ void beta_load(SlotSums<2>& ss, const double* pb, const int* pbn, int pbs) {
   const int sl[2] = {PB_L0, PB_L1};
-  slot_totals<2>(pb, pbn, pbs, sl, L);
+  ss.load(pb, pbn, pbs, sl);
+}
+__device__ __forceinline__ void beta_finish(const double* sc, SlotSums<2>& ss, int restart, int coupled,
+                                            double (&beta)[2], double (&L)[2]) {
+  ss.total(L);
   const double P0 = gload(sc + S_LPREV), P1 = gload(sc + S_LPREV + 1);
   if (coupled) {
     const double Lp = P0 + P1;
@@ -160,6 +176,12 @@ __device__ __forceinline__ void beta_from(const double* sc, const double* pb, co
     beta[0] = (restart || P0 == 0.0) ? 0.0 : L[0] / P0;
     beta[1] = (restart || P1 == 0.0) ? 0.0 : L[1] / P1;
   }
+}
+__device__ __forceinline__ void beta_from(const double* sc, const double* pb, const int* pbn, int pbs,
+                                          int restart, int coupled, double (&beta)[2], double (&L)[2]) {
+  SlotSums<2> ss;
+  beta_load(ss, pb, pbn, pbs);
+  beta_finish(sc, ss, restart, coupled, beta, L);
 }
 
 __device__ __forceinline__ void record_beta(double* sc, const double (&beta)[2], const double (&L)[2]) {
@@ -173,11 +195,14 @@ __device__ __forceinline__ void record_beta(double* sc, const double (&beta)[2],
 // RRCG:6: s = sum (p,l) / sum (||A~ p||^2 + (alpha + lambda) ||p||^2), joint when coupled.
 // The block-0 thread 0 of the consumer records it (and L_prev <- L for the next beta) when
 // `record` is set.
-__device__ __forceinline__ void step_from(double* sc, const double* pb, const int* pbn, int pbs, double lam0,
-                                          double lam1, int coupled, bool record, double (&s)[2]) {
+__device__ __forceinline__ void step_load(SlotSums<6>& ss, const double* pb, const int* pbn, int pbs) {
   const int sl[6] = {PB_PL0, PB_PL1, PB_PP0, PB_PP1, PB_Q0, PB_Q1};
+  ss.load(pb, pbn, pbs, sl);
+}
+__device__ __forceinline__ void step_finish(double* sc, SlotSums<6>& ss, double lam0, double lam1, int coupled,
+                                            bool record, double (&s)[2]) {
   double t[6];
-  slot_totals<6>(pb, pbn, pbs, sl, t);
+  ss.total(t);
   const double den0 = t[4] + (gload(sc + S_ALPHA) + lam0) * t[2];
   const double den1 = t[5] + (gload(sc + S_ALPHA + 1) + lam1) * t[3];
   if (coupled) {
@@ -200,18 +225,32 @@ __device__ __forceinline__ void step_from(double* sc, const double* pb, const in
     if (!isfinite(s[0]) || !isfinite(s[1])) gstore(sc + S_NONFIN, 1.0);
   }
 }
+__device__ __forceinline__ void step_from(double* sc, const double* pb, const int* pbn, int pbs, double lam0,
+                                          double lam1, int coupled, bool record, double (&s)[2]) {
+  SlotSums<6> ss;
+  step_load(ss, pb, pbn, pbs);
+  step_finish(sc, ss, lam0, lam1, coupled, record, s);
+}
 
 // RRCG:2-3 scalars (m1,m1), (m2,m2), (m1,m2) from their partials.
-__device__ __forceinline__ void gram_from(double* sc, const double* pb, const int* pbn, int pbs, bool record,
-                                          double (&g)[3]) {
+__device__ __forceinline__ void gram_load(SlotSums<3>& ss, const double* pb, const int* pbn, int pbs) {
   const int sl[3] = {PB_G11, PB_G22, PB_G12};
-  slot_totals<3>(pb, pbn, pbs, sl, g);
+  ss.load(pb, pbn, pbs, sl);
+}
+__device__ __forceinline__ void gram_finish(double* sc, SlotSums<3>& ss, bool record, double (&g)[3]) {
+  ss.total(g);
   if (record && threadIdx.x == 0) {
     gstore(sc + S_G11, g[0]);
     gstore(sc + S_G22, g[1]);
     gstore(sc + S_G12, g[2]);
     if (!isfinite(g[0]) || !isfinite(g[1]) || !isfinite(g[2])) gstore(sc + S_NONFIN, 1.0);
   }
+}
+__device__ __forceinline__ void gram_from(double* sc, const double* pb, const int* pbn, int pbs, bool record,
+                                          double (&g)[3]) {
+  SlotSums<3> ss;
+  gram_load(ss, pb, pbn, pbs);
+  gram_finish(sc, ss, record, g);
 }
 
 // RRCG:4 for one element of data set `self`, given z = (A^T W_d r~)_j, the models a = m1_j,
