@@ -278,14 +278,38 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     }
   }
   __syncthreads();
+  // (the direction's partial sums first: their registers are then free for the stores)
+  if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0, pid, pcount);
   // rows beyond nrows are not stored: a tile may be taller than the padded row count ld
   cx<T>* dst = a.out + b * a.out_bs + (long long)l * K2 * a.ld + tile * RT;
   const int rows = min(RT, a.nrows - tile * RT);
+  if (TPF >= 2 && 2 * (int)blockDim.x == RT * TPF) {
+    // every LDS read first, then the stores.  With blockDim = RT TPF / 2 (one transform of two
+    // rows per TPF threads, TPF >= 2) a thread keeps its row rr and steps TPF / 2 columns per
+    // pass, and ITER passes cover the K2 RT entries.
+    constexpr int ITER = (2 * K2 + TPF - 1) / TPF;
+    const int rr = threadIdx.x % RT, k0 = threadIdx.x / RT;
+    const cx<T>* srow = smem + (rr >> 1) * BS + (rr & 1) * K2;
+    cx<T> ov[ITER];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int k2 = k0 + it * (TPF / 2);
+      if (k2 < K2) ov[it] = srow[k2];
+    }
+    if (rr < rows) {
+      cx<T>* drow = dst + rr;
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int k2 = k0 + it * (TPF / 2);
+        if (k2 < K2) gstore(drow + (long long)k2 * a.ld, ov[it]);
+      }
+    }
+    return;
+  }
   for (int idx = threadIdx.x; idx < K2 * RT; idx += blockDim.x) {
     const int k2 = idx / RT, rr = idx - k2 * RT;
     if (rr < rows) gstore(dst + (long long)k2 * a.ld + rr, smem[(rr >> 1) * BS + (rr & 1) * K2 + k2]);
   }
-  if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0, pid, pcount);
 }
 
 template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
@@ -368,15 +392,28 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   } else {
     // `in` is complex [L][K2][ld] (nsum = 1).  Each thread loads its ITER values first, then
     // stages them in LDS, so the loads are in flight together.
-    constexpr int ITER = (2 * K2 + TPF - 1) / TPF;  // >= K2 * RT / blockDim, blockDim = RT * TPF / 2
+    // blockDim = RT TPF / 2, so ITER passes cover the K2 RT entries; from TPF = 2 on, a thread
+    // keeps its row rr and steps TPF / 2 columns per pass.
+    constexpr int ITER = (2 * K2 + TPF - 1) / TPF;
     const cx<T>* src = reinterpret_cast<const cx<T>*>(a.in) + b * a.in_bs + (long long)l * K2 * a.ld + tile * RT;
     const int rows = min(RT, a.nrows - tile * RT);
+    const int rr0 = threadIdx.x % RT, k0 = threadIdx.x / RT;
+    auto pos = [&](int it, int& k2, int& rr) {
+      if constexpr (TPF >= 2) {
+        k2 = k0 + it * (TPF / 2);
+        rr = rr0;
+      } else {
+        const int idx = threadIdx.x + it * blockDim.x;
+        k2 = idx / RT;
+        rr = idx - k2 * RT;
+      }
+    };
     cx<T> hv[ITER];
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      const int k2 = idx / RT, rr = idx - k2 * RT;
-      hv[it] = gload_or(src, (long long)k2 * a.ld + rr, (idx < K2 * RT) & (rr < rows));
+      int k2, rr;
+      pos(it, k2, rr);
+      hv[it] = gload_or(src, (long long)k2 * a.ld + rr, (k2 < K2) & (rr < rows));
     }
     // the Gramian scalars' partials, loaded while the spectra are in flight
     if constexpr (MODE == FUSE_GRAD) {
@@ -386,9 +423,9 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     }
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
-      const int idx = threadIdx.x + it * blockDim.x;
-      const int k2 = idx / RT, rr = idx - k2 * RT;
-      if (idx < K2 * RT) {
+      int k2, rr;
+      pos(it, k2, rr);
+      if (k2 < K2) {
         if (k2 == 0 || k2 == K2 - 1) hv[it].im = T(0);  // DC and Nyquist of a real row are real
         smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv[it];
       }
