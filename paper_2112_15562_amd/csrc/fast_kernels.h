@@ -278,8 +278,9 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     }
   }
   __syncthreads();
-  // (the direction's partial sums first: their registers are then free for the stores)
-  if constexpr (MODE == FUSE_DIR) block_partials<2>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0, pid, pcount);
+  // (the direction's partial sums first: their registers are then free for the stores; the
+  // butterfly form, with which the kernel's prologue stays within its registers)
+  if constexpr (MODE == FUSE_DIR) block_partials<2, false>(acc, fz.pb, fz.pbn, fz.pbs, fz.self ? PB_PL1 : PB_PL0, pid, pcount);
   // rows beyond nrows are not stored: a tile may be taller than the padded row count ld
   cx<T>* dst = a.out + b * a.out_bs + (long long)l * K2 * a.ld + tile * RT;
   const int rows = min(RT, a.nrows - tile * RT);

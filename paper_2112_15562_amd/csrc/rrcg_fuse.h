@@ -51,25 +51,55 @@ struct Fuse {
   int pbs;        // partials per slot (>= blocks of any reducing launch)
 };
 
+// Sum of x over the 64 lanes of a full wave, in the last lane (63): an exchange butterfly
+// inside each row of 16 lanes through DPP moves (quad swaps by 1 and 2, then the mirrors of
+// 8 and 16 lanes; both partners add the same two values), then the row sums r0..r3 carried
+// up by the row broadcasts, leaving (r3 + r2) + (r1 + r0) in lane 63.
+__device__ __forceinline__ double wave_sum_last(double x) {
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0x140, 0xF, 0xF, false);  // row_mirror
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0.0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
+// Per-wave sums of K values, each written by one lane to sh[k][wave]: with DPP and full
+// waves the DPP sum, from lane 63; otherwise an xor butterfly through lane shuffles whose
+// partners stay among the active lanes (blocks below 64 threads are a power of two), from
+// lane 0.  The DPP form is faster; the butterfly needs fewer registers where a kernel has
+// loads in flight.
+template <int K, bool DPP>
+__device__ __forceinline__ void wave_sums_to(double (&v)[K], double (&sh)[K][16]) {
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (DPP && blockDim.x >= 64) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_last(v[k]);
+    if (lane == 63) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+    }
+  } else {
+    const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      for (int off = wsz >> 1; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
+    }
+  }
+}
+
 // Sum of v over the block (every thread calls; blockDim a multiple of 64 or a power of two
 // below 64, at most 1024) stored at pb[(slot0 + k) * pbs + bid]; block 0 of the nb blocks
 // records their number.
-template <int K>
+template <int K, bool DPP = true>
 __device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* pbn, int pbs, int slot0, int bid,
                                                int nb) {
   __shared__ double sh[K][16];
-  const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;  // xor partners stay among active lanes
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double x = v[k];
-    for (int off = wsz >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[k] = x;
-  }
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
-  }
+  wave_sums_to<K, DPP>(v, sh);
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = (blockDim.x + 63) >> 6;
@@ -85,23 +115,13 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* pb, int* 
 
 // Sums of K values over the block, left in v of every thread (blockDim a multiple of 64
 // or a power of two below 64, at most 1024).  All lanes of a wave hold the same sum after
-// the xor butterfly (each level adds the same two operands), and the waves' sums are
-// added in a fixed order.
+// the wave sum, and the waves' sums are added in a fixed order.
 template <int K>
 __device__ __forceinline__ void block_allreduce(double (&v)[K]) {
   __shared__ double sh[K][16];
-  const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double x = v[k];
-    for (int off = wsz >> 1; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
-    v[k] = x;
-  }
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
-  }
+  // (the xor butterfly: this runs in kernel prologues with their loads in flight, where the
+  // DPP form's temporaries cost registers)
+  wave_sums_to<K, false>(v, sh);
   __syncthreads();
   const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
