@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "d34e11d1b1afe89826486698c2fdbf575d72d7724bcd7f0f0e449a6676d08c7d",
+    "csrc_sha256": "cbf5faf72238ae60dcc81077ec58e9ec2bf651db74ed185567016d52d3ad1ee8",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50655406, 50536392), "fwd_col_eig_sum": (77081813, 8108930),
-        "fwd_row_c2r": (1910176, 532211), "adj_row_r2c": (1062854, 1064960),
-        "adj_col_conj_eig": (52030623, 33685504), "adj_row_c2r": (103528030, 16814191),
+        "fwd_row_r2c": (50698316, 50595358), "fwd_col_eig_sum": (77098921, 4697285),
+        "fwd_row_c2r": (2785490, 532211), "adj_row_r2c": (1067398, 1064960),
+        "adj_col_conj_eig": (52129931, 33685504), "adj_row_c2r": (77065775, 16843862),
     },
 }
 
