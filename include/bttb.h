@@ -182,9 +182,10 @@ BTTB_API int bttb_timing_read(bttb_plan plan, double* total_ms, int* count);
  * gravity and magnetic operators of many inversions of uneven sizes -- as one kernel
  * launch per stage (row transform, column pass, inverse row transform), each member
  * with its own plan's eigenvalues and scratch.  Members must be power-of-two plans
- * (bttb_setup with BTTB_PAD_POW2, transforms 32..2048) of one precision.  The group
- * refers to the plans, which must outlive it and must not be used on another stream
- * while a group product runs.  Creation allocates a small device table and
+ * (bttb_setup with BTTB_PAD_POW2, transforms 32..2048) of one precision, each plan at
+ * most once (a member's intermediates live in its plan; a repeated plan is BTTB_EINVAL).
+ * The group refers to the plans, which must outlive it and must not be used on another
+ * stream while a group product runs.  Creation allocates a small device table and
  * synchronises `stream`. */
 BTTB_API int bttb_group_create(const bttb_plan* plans, int count, void* stream, bttb_group* out);
 
@@ -346,8 +347,9 @@ BTTB_API int rrcg_destroy(rrcg_handle h);
  * is one launch over all of them (the products of all their operators through one
  * product group, the CG pieces fused into the row transforms, and the elementwise
  * updates over the concatenated vectors).  All plans must be power-of-two plans
- * (BTTB_PAD_POW2) of one precision; descs[0].use_graph decides graph capture for the
- * whole group.  Creation allocates the work vectors and synchronises `stream`. */
+ * (BTTB_PAD_POW2) of one precision, each used by one inversion once (as in
+ * bttb_group_create); descs[0].use_graph decides graph capture for the whole group.
+ * Creation allocates the work vectors and synchronises `stream`. */
 BTTB_API int rrcg_group_create(const rrcg_desc* descs, int count, void* stream, rrcg_group* out);
 
 /* One outer step of every inversion (as rrcg_step).  Asynchronous.  With use_graph the whole

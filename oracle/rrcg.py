@@ -199,6 +199,44 @@ def run(ops, data: Data, prm: Params, n_outer: int, n_inner: int,
     return st, recs
 
 
+def similarity(m1: np.ndarray, m2: np.ndarray) -> float:
+    """|(m1, m2)| / (||m1|| ||m2||): the cosine between the two models in the original space,
+    the quantity the Gramian constraint drives to one (S_G = ||m1||^2 ||m2||^2 (1 - cos^2)).
+    A single number standing for the paper's cross-correlation plots (reading: the plots are
+    scatter plots of m1 against m2; aligned points give a cosine near one).  0 when a model
+    is zero."""
+    n1, n2 = dot(m1, m1), dot(m2, m2)
+    if n1 == 0.0 or n2 == 0.0:
+        return 0.0
+    return abs(dot(m1, m2)) / math.sqrt(n1 * n2)
+
+
+def select_lambda(records: Sequence[dict], sim_min: float) -> Optional[int]:
+    """The Lagrange-parameter choice of Sec. 3.1.3 and Sec. 5 (conclusions): runs with fixed
+    lambda, in increasing order; the first (smallest) pair whose run met both chi^2 tests
+    (good predictions of both data sets; a run stopped by the iteration limit is rejected,
+    as the paper rejects its non-converged large-lambda run) and whose models are similar
+    (similarity >= sim_min).  None when no run qualifies."""
+    for i, r in enumerate(records):
+        if r["converged"] and r["similarity"] >= sim_min:
+            return i
+    return None
+
+
+def lambda_scan(ops, data: Data, prm: Params, lams: Sequence, n_outer: int, n_inner: int,
+                sim_min: float = 0.9) -> dict:
+    """One run per lambda pair (stopped at the chi^2 test or after n_outer outer steps), each
+    from the initial state; returns the per-run records and the selected index."""
+    records = []
+    for lam in lams:
+        st, recs = run(ops, data, replace(prm, lam=(float(lam[0]), float(lam[1]))), n_outer, n_inner,
+                       stop_on_chi2=True)
+        records.append(dict(lam=(float(lam[0]), float(lam[1])), m=[st.m[0].copy(), st.m[1].copy()],
+                            similarity=similarity(st.m[0], st.m[1]), converged=bool(recs[-1]["converged"]),
+                            k=len(recs), phi=list(recs[-1]["phi"])))
+    return dict(records=records, selected=select_lambda(records, sim_min))
+
+
 def relative_error(m_exact: np.ndarray, m_rec: np.ndarray) -> float:
     """RE = ||m_exact - m_K|| / ||m_exact||  (eq. RE)."""
     return float(np.linalg.norm(np.ravel(m_exact - m_rec)) / np.linalg.norm(np.ravel(m_exact)))

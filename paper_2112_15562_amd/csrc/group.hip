@@ -380,6 +380,12 @@ int group_create(const bttb_plan* plans, int count, void* stream, Group** out) {
       delete g;
       return fail(BTTB_ESTATE, "bttb_group_create: members differ in precision");
     }
+    for (int j = 0; j < i; ++j) {
+      if (g->P[j] == P) {  // a member's intermediates live in its plan: two uses would share them
+        delete g;
+        return fail(BTTB_EINVAL, "bttb_group_create: a plan appears twice");
+      }
+    }
     g->P[i] = P;
   }
   g->precision = g->P[0]->precision;

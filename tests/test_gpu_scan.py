@@ -1,0 +1,74 @@
+"""The Lagrange-parameter scan on the group solver vs the oracle's scan (run on an MI355X):
+one run per pair, all in one group; each run's models, similarity, convergence and the
+choice against the FP64 oracle."""
+import pytest
+import torch
+
+import synth
+from oracle import rrcg as orrcg
+from test_gpu_rrcg import BASE, host, problem, rel
+
+pytestmark = pytest.mark.gpu
+
+LAMS = [(0.0, 0.0), (2.0, 100.0), (2e3, 1e5), (1e5, 1e7)]
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_2112_15562_amd as pk
+    assert torch.cuda.is_available()
+    return pk
+
+
+def solver_kwargs(prm):
+    return dict(lo=prm.lo, hi=prm.hi, alpha0=prm.alpha0, q=prm.q, alpha_min=prm.alpha_min, eps2=prm.eps2,
+                coupled=prm.coupled, restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian)
+
+
+@pytest.mark.parametrize("dtype,tol_m,tol_s", [(torch.float64, 1e-9, 1e-10), (torch.float32, None, 1e-4)])
+def test_scan_matches_oracle(pk, dtype, tol_m, tol_s):
+    g = synth.SMALL
+    ops, T, data, _ = problem(g, dense=True)
+    prm = orrcg.Params(**BASE)
+    sim_min = 0.8
+    ref = orrcg.lambda_scan(ops, data, prm, LAMS, n_outer=3, n_inner=3, sim_min=sim_min)
+    got = pk.lambda_scan(T, (g.sx, g.sy), data.dobs, data.wd, data.wdepth, LAMS, n_outer=3, n_inner=3,
+                         sim_min=sim_min, dtype=dtype, **solver_kwargs(prm))
+    assert len(got["records"]) == len(LAMS)
+    for a, b in zip(got["records"], ref["records"]):
+        assert a["lam"] == b["lam"]
+        assert a["converged"] == b["converged"] and a["k"] == b["k"]
+        assert a["similarity"] == pytest.approx(b["similarity"], rel=tol_s)
+        if tol_m is not None:
+            for i in range(2):
+                assert rel(host(a["m"][i]), b["m"][i]) <= tol_m
+    # the choice is the rule applied to the records (the same rule, written separately)
+    assert got["selected"] == pk.scan.choose(got["records"], sim_min)
+    assert got["selected"] == orrcg.select_lambda(got["records"], sim_min)
+    if tol_m is not None:
+        assert got["selected"] == ref["selected"]
+
+
+def test_scan_more_pairs_than_a_group(pk, monkeypatch):
+    # the scan splits into groups of at most MAX_GROUP runs; each run is independent of its group
+    g = synth.SUB
+    ops, T, data, _ = problem(g, dense=True)
+    prm = orrcg.Params(**BASE)
+    lams = [(0.5 * k, 25.0 * k) for k in range(5)]
+    kw = dict(n_outer=2, n_inner=2, dtype=torch.float64, **solver_kwargs(prm))
+    one = pk.lambda_scan(T, (g.sx, g.sy), data.dobs, data.wd, data.wdepth, lams, **kw)
+    monkeypatch.setattr(pk.scan, "MAX_GROUP", 2)
+    split = pk.lambda_scan(T, (g.sx, g.sy), data.dobs, data.wd, data.wdepth, lams, **kw)
+    for a, b in zip(one["records"], split["records"]):
+        assert a["lam"] == b["lam"] and a["k"] == b["k"]
+        for i in range(2):
+            assert rel(host(a["m"][i]), host(b["m"][i])) <= 1e-13
+
+
+def test_group_rejects_a_repeated_plan(pk):
+    g = synth.SMALL
+    _, T, _, _ = problem(g, dense=True)
+    op = pk.Operator(torch.as_tensor(T[0], device="cuda"), (g.sx, g.sy), dtype=torch.float64, pad_pow2=True)
+    with pytest.raises(pk.BTTBError):
+        pk.Group([op, op])
+    op.close()

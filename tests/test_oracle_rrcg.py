@@ -184,3 +184,33 @@ def test_standalone_equals_two_separate_inversions(ops6):
     prm2 = rrcg.Params(alpha0=(50.0, 50.0), q=(0.9, 0.9), coupled=False, lo=(0.0, 0.0), hi=(1.0, 1.0))
     st2, _ = rrcg.run([ops6[0], ops6[0]], data2, prm2, n_outer=3, n_inner=4)
     assert np.array_equal(st.m[0], st2.m[0]) and np.array_equal(st2.m[0], st2.m[1])
+
+
+# ------------------------------------------------------------------------------------
+# the Lagrange-parameter scan (Sec. 3.1.3, Sec. 5): similarity and the choice rule
+# ------------------------------------------------------------------------------------
+def test_similarity_closed_forms():
+    r = np.random.default_rng(5)
+    a = r.standard_normal((3, 4, 5))
+    assert rrcg.similarity(a, a) == pytest.approx(1.0, abs=1e-15)
+    assert rrcg.similarity(a, -3.0 * a) == pytest.approx(1.0, abs=1e-15)      # sign-blind
+    e1, e2 = np.zeros(6), np.zeros(6)
+    e1[1], e2[4] = 2.0, -5.0
+    assert rrcg.similarity(e1, e2) == 0.0                                   # orthogonal
+    assert rrcg.similarity(np.array([1.0, 0.0]), np.array([1.0, 1.0])) == pytest.approx(1 / math.sqrt(2), rel=1e-15)
+    assert rrcg.similarity(np.zeros(4), np.ones(4)) == 0.0
+    # two directions 60 degrees apart in a plane of a larger space, scaled
+    u = np.zeros(10)
+    v = np.zeros(10)
+    u[3], v[3], v[7] = 7.0, 0.5, 0.5 * math.sqrt(3.0)
+    assert rrcg.similarity(u, v) == pytest.approx(0.5, rel=1e-15)
+
+
+def test_lambda_choice_rule():
+    rec = lambda c, s: dict(converged=c, similarity=s)
+    runs = [rec(True, 0.5), rec(False, 0.95), rec(True, 0.91), rec(True, 0.99)]
+    assert rrcg.select_lambda(runs, 0.9) == 2          # smallest pair that fits and is similar
+    assert rrcg.select_lambda(runs, 0.995) is None     # none similar enough
+    assert rrcg.select_lambda(runs, 0.4) == 0
+    assert rrcg.select_lambda([rec(False, 1.0)], 0.0) is None   # a run stopped by the limit
+    assert rrcg.select_lambda([], 0.5) is None
