@@ -38,7 +38,7 @@ COPY_BYTES = 256 << 20   # one side of the calibration copy
 TIMING_REPEAT = 10
 
 # HBM traffic of the solver's product launches, from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu --no-f64 --no-batch --pairs 4` (FETCH_SIZE, then WRITE_SIZE),
+# `bench.py --steps 1 --warmup 0 --no-cpu --no-f64 --no-batch --no-scan --pairs 4` (FETCH_SIZE, then WRITE_SIZE),
 # each scaled by the same counter's reading for the calibration copy (COPY_BYTES read,
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 solve")
     ap.add_argument("--pairs", type=int, default=200, help="timed product pairs per precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-inversion batched workload")
+    ap.add_argument("--no-scan", action="store_true", help="skip the Lagrange-parameter scan")
     return ap.parse_args()
 
 
@@ -185,6 +186,47 @@ def batched_workload(pk, torch):
                        "per_inversion_latency_s": {"min": min(lat), "max": max(lat),
                                                    "mean": sum(lat) / len(lat)}},
         "phi_after": [[round(a, 1) for a in c] for c in chi],
+    }
+
+
+SCAN_LAMS = [(0.0, 0.0)] + [(10.0 ** k, 50.0 * 10.0 ** k) for k in range(1, 8)]  # lambda2 = 50 lambda1
+SCAN_OUTER, SCAN_INNER = 30, 10
+
+
+def scan_workload(pk, torch):
+    """The Lagrange-parameter scan: one joint inversion per fixed (lambda1, lambda2) pair of
+    SCAN_LAMS on the 128x128x24 random-box problem, all runs in one group solver, FP32 with FP64
+    reductions; SCAN_OUTER x SCAN_INNER steps per run (a run stops counting at its chi^2 test).
+    The time covers the whole call: plan setup for every run, the steps and the choice."""
+    import synth
+    g = synth.BATCH
+    rho, kap = synth.random_boxes(g, seed_workload=6, index=1)
+    T = [pk.prism_kernels(k, g) for k in (pk.GRAVITY, pk.MAGNETIC)]
+    d = []
+    for i, m in enumerate((rho, kap)):
+        op = pk.Operator(T[i], (g.sx, g.sy), dtype=torch.float64, pad_pow2=True)
+        d.append(op.matvec(torch.as_tensor(m, device="cuda")).cpu().numpy())
+        op.close()
+    sig = [synth.noise_sigma(d[0], 0.02, 0.02), synth.noise_sigma(d[1], 0.02, 1.0)]
+    dobs = [d[i] + sig[i] * synth.normal_like(d[i].shape, 6, 10 + i) for i in range(2)]
+    prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.9, 0.9), eps2=1e-9,
+               coupled=True, restart=True, p_norm=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = pk.lambda_scan(T, (g.sx, g.sy), dobs, [1.0 / s_ for s_ in sig],
+                         [synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)], SCAN_LAMS,
+                         n_outer=SCAN_OUTER, n_inner=SCAN_INNER, sim_min=0.9, dtype=torch.float32, **prm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pairs = sum(2 * r["k"] * SCAN_INNER for r in res["records"])
+    return {
+        "workload": f"{len(SCAN_LAMS)} fixed Lagrange pairs, 128x128 stations over 128x128x24 prisms, "
+                    f"{SCAN_OUTER} outer x {SCAN_INNER} inner each, one group solver, FP32 with FP64 reductions",
+        "lambdas": [list(l) for l in SCAN_LAMS],
+        "scan_s": dt, "op_pairs_per_s": pairs / dt,
+        "similarity": [round(r["similarity"], 4) for r in res["records"]],
+        "converged": [r["converged"] for r in res["records"]],
+        "selected": res["selected"],
     }
 
 
@@ -454,6 +496,11 @@ def main():
         log("bench: batched uneven inversions")
         batched = batched_workload(pk, torch)
 
+    scan = None
+    if not args.no_scan:
+        log("bench: Lagrange-parameter scan")
+        scan = scan_workload(pk, torch)
+
     cpu = None
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
@@ -494,6 +541,7 @@ def main():
         "copy_probe": copy,
         "kernels": kernel_table,
         "batched": batched,
+        "lambda_scan": scan,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
