@@ -88,13 +88,16 @@ typedef enum { BTTB_OP_FORWARD = 0, BTTB_OP_ADJOINT = 1 } bttb_op;
 
 /* Station and prism grid.  x = East, y = North, z = down.  Prism (a, b, r) spans
  * [a dx,(a+1) dx] x [b dy,(b+1) dy] x [top + r dz, top + (r+1) dz]; station (p, q) sits at
- * ((p+1/2) dx, (q+1/2) dy, -height), i.e. above the prism centres (Sec. 2.7.1).
+ * ((p+ox+1/2) dx, (q+oy+1/2) dy, -height), i.e. above the centre of prism column
+ * (p+ox, q+oy) (Sec. 2.7.1; ox = oy = 0 with sx = nx, sy = ny is the paper's layout, a
+ * station grid over the interior of a padded model domain has sx < nx and an offset).
  * The inducing field has inclination incl_deg, declination decl_deg and intensity
  * field_nt (nT).  Units: metres, g/cc -> mGal, SI susceptibility -> nT. */
 typedef struct {
   int sx, sy, nx, ny, nz;
   double dx, dy, dz, height, top;
   double incl_deg, decl_deg, field_nt;
+  int ox, oy;
 } bttb_geometry;
 
 /* Plan description returned by bttb_plan_info. */

@@ -19,7 +19,10 @@ module writes both out from their definitions:
 Geometry (the paper fixes only that stations sit at prism centres on the surface,
 Sec. 2.7.1): x = East (station index p, prism index a), y = North (q, b),
 z = down; prism (a, b, r) spans [a dx,(a+1)dx] x [b dy,(b+1)dy] x
-[top + r dz, top + (r+1) dz]; station (p, q) sits at ((p+1/2)dx, (q+1/2)dy, -h).
+[top + r dz, top + (r+1) dz]; station (p, q) sits at ((p+ox+1/2)dx, (q+oy+1/2)dy, -h),
+above the centre of prism column (p+ox, q+oy).  ox = oy = 0 with sx = nx, sy = ny is the
+paper's layout; a station grid over an interior part of a larger (padded) model domain
+(Sec. 2.7.1) has sx < nx and an offset.
 
 Units: density in g/cc and gravity in mGal (C_G = 6.6743e-11 * 1e3 * 1e5), field
 and anomaly in nT, susceptibility in SI.
@@ -56,6 +59,8 @@ class Geometry:
     incl: float = 65.0      # inducing field inclination (deg)
     decl: float = 2.0       # inducing field declination (deg)
     field: float = 50000.0  # inducing field intensity (nT)
+    ox: int = 0             # prism column under station column 0
+    oy: int = 0             # prism row under station row 0
 
     @property
     def m(self) -> int:
@@ -129,7 +134,7 @@ def magnetic_prism(x0, y0, z0, xb, yb, zb, incl_deg, decl_deg, field_nt):
 
 
 def station_xyz(g: Geometry, p, q):
-    return (np.asarray(p) + 0.5) * g.dx, (np.asarray(q) + 0.5) * g.dy, -g.h
+    return (np.asarray(p) + g.ox + 0.5) * g.dx, (np.asarray(q) + g.oy + 0.5) * g.dy, -g.h
 
 
 def prism_bounds(g: Geometry, a, b, r):

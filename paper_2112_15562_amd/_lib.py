@@ -44,7 +44,7 @@ class Geometry(C.Structure):
     _fields_ = [("sx", C.c_int), ("sy", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("height", C.c_double),
                 ("top", C.c_double), ("incl_deg", C.c_double), ("decl_deg", C.c_double),
-                ("field_nt", C.c_double)]
+                ("field_nt", C.c_double), ("ox", C.c_int), ("oy", C.c_int)]
 
 
 class PlanDesc(C.Structure):

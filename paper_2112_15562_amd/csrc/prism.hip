@@ -1,8 +1,10 @@
 // Kernel arrays T_(r) of eq. (d=gm) evaluated on the GPU in FP64 (Sec. 2.1, Sec. 2.7.1).
 //
-// Entry (r, i, j) is the response at a station offset by u = i-(nx-1) cells in x and
-// v = j-(ny-1) cells in y from a unit-property prism of layer r.  With the station at
-// the prism-grid centre positions, the prism's corners relative to the station are
+// Entry (r, i, j) is the response at station index p over prism index a with p - a =
+// i-(nx-1) (and q - b = j-(ny-1)) from a unit-property prism of layer r; the station sits
+// above prism column p + ox, so it is u = i-(nx-1)+ox cells from the prism in x (and
+// v = j-(ny-1)+oy in y).  With the station at the prism-grid centre positions, the
+// prism's corners relative to the station are
 //   X in {(-u-1/2) dx, (-u+1/2) dx},  Y in {(-v-1/2) dy, (-v+1/2) dy},
 //   Z in {top + r dz + h, top + (r+1) dz + h}   (z down, station at height h),
 // and each closed form is a signed sum over the 8 corners with sign (-1)^(i+j+k)
@@ -38,7 +40,7 @@ __global__ void k_prism(int kind, bttb_geometry g, double* __restrict__ out, dou
     const long long rest = idx / Ly;
     const int i = (int)(rest % Lx);
     const int r = (int)(rest / Lx);
-    const double u = (double)(i - (g.nx - 1)), v = (double)(j - (g.ny - 1));
+    const double u = (double)(i - (g.nx - 1) + g.ox), v = (double)(j - (g.ny - 1) + g.oy);
     const double xs[2] = {(-u - 0.5) * g.dx, (-u + 0.5) * g.dx};
     const double ys[2] = {(-v - 0.5) * g.dy, (-v + 0.5) * g.dy};
     const double zs[2] = {g.top + r * g.dz + g.height, g.top + (r + 1) * g.dz + g.height};

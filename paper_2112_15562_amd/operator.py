@@ -26,16 +26,19 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def _geometry(g) -> L.Geometry:
-    get = (lambda k: g[k]) if isinstance(g, dict) else (lambda k: getattr(g, k))
+    get = (lambda k, d=None: g.get(k, d) if d is not None else g[k]) if isinstance(g, dict) else \
+        (lambda k, d=None: getattr(g, k, d) if d is not None else getattr(g, k))
     return L.Geometry(int(get("sx")), int(get("sy")), int(get("nx")), int(get("ny")), int(get("nz")),
                       float(get("dx")), float(get("dy")), float(get("dz")), float(get("h")),
-                      float(get("top")), float(get("incl")), float(get("decl")), float(get("field")))
+                      float(get("top")), float(get("incl")), float(get("decl")), float(get("field")),
+                      int(get("ox", 0)), int(get("oy", 0)))
 
 
 def prism_kernels(kind: int, geometry, device="cuda") -> torch.Tensor:
     """Kernel array T [nz][sx+nx-1][sy+ny-1] (FP64) of the gravity or magnetic operator,
     evaluated on the GPU from the closed-form prism responses (Sec. 2.1).  `geometry`
-    has sx, sy, nx, ny, nz, dx, dy, dz, h, top, incl, decl, field."""
+    has sx, sy, nx, ny, nz, dx, dy, dz, h, top, incl, decl, field and optionally the
+    station offset ox, oy (station (p, q) above prism column (p + ox, q + oy); default 0)."""
     g = _geometry(geometry)
     dev = torch.device(device)
     out = torch.empty((g.nz, g.sx + g.nx - 1, g.sy + g.ny - 1), dtype=torch.float64, device=dev)

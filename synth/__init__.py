@@ -19,7 +19,8 @@ import numpy as np
 
 @dataclass(frozen=True)
 class Grid:
-    """Stations sx x sy over prisms nx x ny x nz; stations sit above prism centres."""
+    """Stations sx x sy over prisms nx x ny x nz; station (p, q) sits above the centre of
+    prism column (p + ox, q + oy)."""
     sx: int
     sy: int
     nx: int
@@ -33,6 +34,8 @@ class Grid:
     incl: float = 65.0
     decl: float = 2.0
     field: float = 50000.0
+    ox: int = 0
+    oy: int = 0
 
     def asdict(self):
         return asdict(self)

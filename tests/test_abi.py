@@ -78,5 +78,6 @@ def test_argument_checks_fail_before_any_gpu_work(lib):
 
 def test_struct_layouts_match_header(lib):
     # sizes of the ABI structs as laid out by the C compiler on x86-64
-    assert C.sizeof(lib.Geometry) == 5 * 4 + 4 + 8 * 8
+    assert C.sizeof(lib.Geometry) == 5 * 4 + 4 + 8 * 8 + 2 * 4
+    assert lib.Geometry.ox.offset == 88 and lib.Geometry.oy.offset == 92
     assert C.sizeof(lib.RrcgScalars) == 8 * 2 * 3 + 8 + 8 * 2 * 2 + 8 + 4 * 2 + 4 * 3 + 4

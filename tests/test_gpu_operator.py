@@ -28,7 +28,8 @@ def relerr(a, b):
 
 
 def ogeom(g: synth.Grid) -> oprism.Geometry:
-    return oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+    return oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field,
+                           ox=g.ox, oy=g.oy)
 
 
 def dev(x, dtype=torch.float64):
@@ -43,6 +44,8 @@ def host(t):
 RAGGED = synth.Grid(7, 9, 11, 5, 3, 40.0, 30.0, 25.0, decl=20.0)
 TINY = synth.Grid(1, 1, 1, 1, 1, 50.0, 50.0, 50.0)
 ODD = synth.Grid(3, 5, 2, 7, 2, 30.0, 20.0, 10.0, h=2.0, top=5.0, incl=40.0, decl=-30.0)
+# a padded model domain: 6x5 stations over the interior of 10x9x3 prisms, offset (2, 3)
+PADDED = synth.Grid(6, 5, 10, 9, 3, 40.0, 30.0, 25.0, ox=2, oy=3)
 
 
 # ------------------------------------------------------------------------------------
@@ -75,7 +78,7 @@ def test_eigenvalues_equal_bruteforce_dft(pk, L):
 # ------------------------------------------------------------------------------------
 # prism kernel generator vs the oracle's closed forms
 # ------------------------------------------------------------------------------------
-@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, synth.MID])
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, PADDED, synth.MID])
 def test_prism_kernels_match_oracle(pk, g):
     for kind in (pk.GRAVITY, pk.MAGNETIC):
         got = host(pk.prism_kernels(kind, g))
@@ -89,7 +92,7 @@ def test_prism_kernels_match_oracle(pk, g):
 # ------------------------------------------------------------------------------------
 # products vs the dense oracle (small grids, GPU-generated kernels end to end)
 # ------------------------------------------------------------------------------------
-@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, TINY])
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, TINY, PADDED])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_products_match_dense_oracle(pk, g, dtype):
     og = ogeom(g)

@@ -21,7 +21,8 @@ def pk():
 
 
 def ogeom(g):
-    return oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+    return oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field,
+                           ox=g.ox, oy=g.oy)
 
 
 def rel(a, b):

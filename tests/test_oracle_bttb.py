@@ -26,6 +26,7 @@ GEOMS = [
     prism.Geometry(16, 16, 16, 16, 8, 50.0, 50.0, 50.0),        # 16x16 over 16x16x8
     prism.Geometry(12, 12, 12, 12, 6, 50.0, 50.0, 50.0),        # 12x12x6 subcase
     prism.Geometry(7, 9, 11, 5, 3, 40.0, 30.0, 25.0, decl=20.0),  # ragged, sx != nx
+    prism.Geometry(5, 4, 9, 8, 2, 40.0, 30.0, 25.0, ox=2, oy=3),  # stations over an interior part
 ]
 
 

@@ -203,3 +203,14 @@ def test_printed_storage_figures():
     tb = t["operators"] * t["nz"] * t["Lx"] * t["Ly"] * t["bytes_per_complex"]
     assert round(tb / 1e6) == t["printed_MB"]
     assert round(d2["printed_bytes"] / tb) == t["printed_reduction"]
+
+
+def test_station_offset_selects_rows_of_the_full_grid():
+    # stations over an interior part of the prism grid (offset ox, oy) see the same
+    # sensitivities as the matching stations of a station grid covering every column
+    full = prism.Geometry(8, 7, 8, 7, 2, 40.0, 30.0, 25.0, incl=55.0, decl=10.0)
+    part = prism.Geometry(4, 3, 8, 7, 2, 40.0, 30.0, 25.0, incl=55.0, decl=10.0, ox=2, oy=3)
+    for kind in (prism.GRAVITY, prism.MAGNETIC):
+        A = prism.dense_matrix(kind, full).reshape(8, 7, -1)
+        B = prism.dense_matrix(kind, part).reshape(4, 3, -1)
+        assert np.array_equal(B, A[2:6, 3:6])
