@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "cbf5faf72238ae60dcc81077ec58e9ec2bf651db74ed185567016d52d3ad1ee8",
+    "csrc_sha256": "2c7f0c072a1c55e8dbb6aae351311de1b120bea4363484bf0c8a89437156595f",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50698316, 50595358), "fwd_col_eig_sum": (77098921, 4697285),
-        "fwd_row_c2r": (2785490, 532211), "adj_row_r2c": (1067398, 1064960),
-        "adj_col_conj_eig": (52129931, 33685504), "adj_row_c2r": (77065775, 16843862),
+        "fwd_row_r2c": (50694491, 50528423), "fwd_col_eig_sum": (77080636, 8431832),
+        "fwd_row_c2r": (1929616, 526368), "adj_row_r2c": (1185728, 1064960),
+        "adj_col_conj_eig": (52021670, 33685504), "adj_row_c2r": (117263126, 16810119),
     },
 }
 
