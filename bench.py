@@ -45,9 +45,9 @@ TIMING_REPEAT = 10
 TRAFFIC = {
     "csrc_sha256": "2c7f0c072a1c55e8dbb6aae351311de1b120bea4363484bf0c8a89437156595f",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50694491, 50528423), "fwd_col_eig_sum": (77080636, 8431832),
-        "fwd_row_c2r": (1929616, 526368), "adj_row_r2c": (1185728, 1064960),
-        "adj_col_conj_eig": (52021670, 33685504), "adj_row_c2r": (117263126, 16810119),
+        "fwd_row_r2c": (50694464, 50528423), "fwd_col_eig_sum": (77080636, 4211084),
+        "fwd_row_c2r": (1787807, 532512), "adj_row_r2c": (663260, 1064960),
+        "adj_col_conj_eig": (52021670, 33685504), "adj_row_c2r": (71293817, 16810119),
     },
 }
 
