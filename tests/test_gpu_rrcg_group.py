@@ -118,7 +118,7 @@ def test_group_equals_one_inversion_solvers_and_graphs(pk):
     eager.close()
 
 
-@pytest.mark.parametrize("how", ["set_launch", "autotune"])
+@pytest.mark.parametrize("how", ["set_launch", "narrow", "autotune"])
 def test_group_launch_shape_recaptures(pk, how):
     grp, _ = build_group(pk, torch.float64)
     ref, _ = build_group(pk, torch.float64)
@@ -126,6 +126,12 @@ def test_group_launch_shape_recaptures(pk, how):
         grp.set_launch(model_row_threads=64, data_row_threads=64, col_threads=64, layer_chunks=2)
         info = grp.launch_info()
         assert (info["model_row_threads"], info["col_threads"], info["layer_chunks"]) == (64, 64, 2)
+    elif how == "narrow":
+        # blocks below one wave (8 threads): the fused forms' partial sums take the lane-shuffle
+        # butterfly instead of the full-wave DPP sum
+        grp.set_launch(model_row_threads=8, data_row_threads=8, col_threads=8, layer_chunks=1)
+        info = grp.launch_info()
+        assert (info["model_row_threads"], info["data_row_threads"], info["col_threads"]) == (8, 8, 8)
     else:
         res = grp.autotune(reps=2)
         assert res["col_threads"] == grp.launch_info()["col_threads"]
