@@ -585,11 +585,12 @@ struct FColArgs {
 };
 
 // Eigenvalue k of a column of length N starting at `col` (EVEN: real and even, stored for
-// k <= N/2 only; else complex, interleaved), or zero when !ok.
+// k <= N/2 only; else complex, interleaved), as loaded: no select on it, since a prefetched
+// value that is selected at once is waited for at once.
 template <typename T, int N, bool EVEN>
-__device__ __forceinline__ cx<T> eig_or(const T* col, int k, bool ok) {
-  if constexpr (EVEN) return cx<T>{gload_or(col, k <= N / 2 ? k : N - k, ok), T(0)};
-  return gload_or(reinterpret_cast<const cx<T>*>(col), k, ok);
+__device__ __forceinline__ cx<T> eig_at(const T* col, int k) {
+  if constexpr (EVEN) return cx<T>{gload(col + (k <= N / 2 ? k : N - k)), T(0)};
+  return gload(reinterpret_cast<const cx<T>*>(col) + k);
 }
 // Start of the stored eigenvalue column k2 of layer l.
 template <typename T, int N, bool EVEN>
@@ -646,12 +647,19 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
     const int n = t + i * TPF;
     return gload_or(src, l * lstride_in + n, l < l1 && n < a.nin);  // (a branch here measures faster)
   };
+  // The next layer's loads go into B as loaded: the zero padding past nin is applied when the
+  // layer is used (a select right after the load would wait for it there), and a layer past
+  // l1 loads layer l0 and is discarded (its products are not accumulated).
   auto fetch = [&](Buf& B, int l) {
+    const int le = l < l1 ? l : l0;
+    const T* ecol = eig_col<T, N, EVEN>(a.eig, a.K2, le, k2);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      if constexpr (PF_IN) B.un[i] = load_col(l, i);
-      const int le = l < l1 ? l : l0;  // a layer that exists, for the discarded loads
-      B.en[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, k2), t + i * TPF, l < l1);
+      const int n = t + i * TPF;
+      if constexpr (PF_IN) {
+        if (!(HALF && i >= 4)) B.un[i] = gload(src + le * lstride_in + (n < a.nin ? n : 0));
+      }
+      B.en[i] = eig_at<T, N, EVEN>(ecol, n);
     }
   };
   auto layer = [&](int it, Buf& B) {
@@ -660,8 +668,11 @@ __device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T,
     cx<T> v[8], e[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      if constexpr (PF_IN) v[i] = B.un[i];
-      else v[i] = load_col(l, i);
+      if constexpr (PF_IN) {
+        v[i] = (HALF && i >= 4) || t + i * TPF >= a.nin ? cx<T>{T(0), T(0)} : B.un[i];
+      } else {
+        v[i] = load_col(l, i);
+      }
       e[i] = B.en[i];
     }
     if (it + 1 < nit) fetch(B, l + G);
@@ -760,12 +771,11 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
   const long long lstride_out = (long long)a.K2 * a.ldout;
   const int nit = (l1 - l0 + G - 1) / G;
   using Buf = ColBuf<T, false>;
+  // the next layer's eigenvalues as loaded (a layer past l1 loads layer l0; it is not stored)
   auto fetch = [&](Buf& B, int l) {
+    const T* ecol = eig_col<T, N, EVEN>(a.eig, a.K2, l < l1 ? l : l0, k2);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int le = l < l1 ? l : l0;  // a layer that exists, for the discarded loads
-      B.en[i] = eig_or<T, N, EVEN>(eig_col<T, N, EVEN>(a.eig, a.K2, le, k2), t + i * TPF, l < l1);
-    }
+    for (int i = 0; i < 8; ++i) B.en[i] = eig_at<T, N, EVEN>(ecol, t + i * TPF);
   };
   auto layer = [&](int it, Buf& B) {
     const int l = l0 + it * G + f;
