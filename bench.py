@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "2c7f0c072a1c55e8dbb6aae351311de1b120bea4363484bf0c8a89437156595f",
+    "csrc_sha256": "be1272f2436ead2318c0b81c87f4197d6ac3163899268b4c8864aaa8eaade679",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50694464, 50528423), "fwd_col_eig_sum": (77080636, 4211084),
-        "fwd_row_c2r": (1787807, 532512), "adj_row_r2c": (663260, 1064960),
-        "adj_col_conj_eig": (52021670, 33685504), "adj_row_c2r": (71293817, 16810119),
+        "fwd_row_r2c": (50694438, 50528447), "fwd_col_eig_sum": (77048495, 4210693),
+        "fwd_row_c2r": (3409733, 528416), "adj_row_r2c": (1067398, 1064960),
+        "adj_col_conj_eig": (52012392, 33685504), "adj_row_c2r": (71403695, 16810143),
     },
 }
 
