@@ -469,19 +469,22 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       // store (a load issued after a store could only be waited for together with it); the
       // full form takes them in smaller groups, within its registers.
       constexpr int CH = HALF ? 4 : 2;
+      const T* msp = s0 ? m0p : m1p;  // this data set's model and the other's
+      const T* mop = s0 ? m1p : m0p;
+      const double gs = s0 ? g22 : g11;
 #pragma unroll
       for (int c = 0; c < (HALF ? 4 : 8); c += CH) {
-        T A0[CH], A1[CH], AW[CH], B0[CH], B1[CH], BW[CH];
+        T AS[CH], AO[CH], AW[CH], BS_[CH], BO[CH], BW[CH];
 #pragma unroll
         for (int i = 0; i < CH; ++i) {
           const int q = t + (c + i) * TPF;
           const bool ok = q < a.ncols;
           const long long o = (long long)r0 * a.ncols + q;
-          A0[i] = gload_or(m0p, o, ok & ra);
-          A1[i] = gload_or(m1p, o, ok & ra);
+          AS[i] = gload_or(msp, o, ok & ra);
+          AO[i] = gload_or(mop, o, ok & ra);
           AW[i] = gload_or(wsp, o, ok & ra, T(1));
-          B0[i] = gload_or(m0p, o + a.ncols, ok & rb);
-          B1[i] = gload_or(m1p, o + a.ncols, ok & rb);
+          BS_[i] = gload_or(msp, o + a.ncols, ok & rb);
+          BO[i] = gload_or(mop, o + a.ncols, ok & rb);
           BW[i] = gload_or(wsp, o + a.ncols, ok & rb, T(1));
         }
 #pragma unroll
@@ -490,12 +493,12 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
           if (q < a.ncols) {
             const long long o = (long long)r0 * a.ncols + q;
             if (ra) {
-              const T g = grad_value<T>(s0, 0, v[c + i].re, A0[i], A1[i], AW[i], 0.0, 0.0, al, lam, g11, g22, g12);
+              const T g = grad_value_plain<T>(v[c + i].re, AS[i], AO[i], AW[i], al, lam, gs, g12);
               gstore(dst + o, g);
               acc[0] += (double)g * (double)g;
             }
             if (rb) {
-              const T g = grad_value<T>(s0, 0, v[c + i].im, B0[i], B1[i], BW[i], 0.0, 0.0, al, lam, g11, g22, g12);
+              const T g = grad_value_plain<T>(v[c + i].im, BS_[i], BO[i], BW[i], al, lam, gs, g12);
               gstore(dst + o + a.ncols, g);
               acc[0] += (double)g * (double)g;
             }

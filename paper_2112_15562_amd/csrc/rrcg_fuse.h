@@ -298,4 +298,19 @@ __device__ __forceinline__ T grad_value(bool s0, int gram_w, T z, double a, doub
   return (T)(zw + al * (mt - mta) + lam * lg);
 }
 
+// The same in the common form (no m_apr, Gramian on m), with the data set's choices made once
+// per block: ms = this data set's model, mo = the other's, gs = (m2,m2) for data set 0 and
+// (m1,m1) for data set 1, so that l_G = gs ms - (m1,m2) mo.  Same operations in the same
+// order as above (w m_apr is zero), hence the same result.
+template <typename T>
+__device__ __forceinline__ T grad_value_plain(T z, double ms, double mo, double Ws, double al, double lam, double gs,
+                                              double g12) {
+  const double lg = gs * ms - g12 * mo;
+  const double mt = Ws * ms;
+  double zw;
+  if constexpr (sizeof(T) == 4) zw = (double)(z * __builtin_amdgcn_rcpf((float)Ws));
+  else zw = (double)z / Ws;
+  return (T)(zw + al * mt + lam * lg);
+}
+
 }  // namespace bttb
