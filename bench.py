@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "be1272f2436ead2318c0b81c87f4197d6ac3163899268b4c8864aaa8eaade679",
+    "csrc_sha256": "c6404326c811383a6991b4885defa06221a10004d3b834d72f08d5f1f20d95d9",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50694438, 50528447), "fwd_col_eig_sum": (77048495, 4210693),
-        "fwd_row_c2r": (3409733, 528416), "adj_row_r2c": (1067398, 1064960),
-        "adj_col_conj_eig": (52012392, 33685504), "adj_row_c2r": (71403695, 16810143),
+        "fwd_row_r2c": (50694454, 50528447), "fwd_col_eig_sum": (77056386, 4210688),
+        "fwd_row_c2r": (2313602, 528416), "adj_row_r2c": (1067398, 1064960),
+        "adj_col_conj_eig": (52012405, 33685504), "adj_row_c2r": (70379434, 16810091),
     },
 }
 

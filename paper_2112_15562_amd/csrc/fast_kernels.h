@@ -410,11 +410,22 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       }
     };
     cx<T> hv[ITER];
+    if constexpr (TPF >= 2) {
+      // k0 < TPF / 2, so only the last pass can reach past K2 (its k0 = 0 lane holds the
+      // Nyquist column); a row past `rows` reads row 0 (in range) and is zeroed when staged.
+      const bool okr = rr0 < rows;
+      const cx<T>* sp = src + (okr ? (long long)k0 * a.ld + rr0 : 0);
+      const long long st = (long long)(TPF / 2) * a.ld;
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      int k2, rr;
-      pos(it, k2, rr);
-      hv[it] = gload_or(src, (long long)k2 * a.ld + rr, (k2 < K2) & (rr < rows));
+      for (int it = 0; it < ITER - 1; ++it) hv[it] = gload(sp + it * st);
+      hv[ITER - 1] = gload_or(sp, (ITER - 1) * st, k0 == 0);
+    } else {
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        int k2, rr;
+        pos(it, k2, rr);
+        hv[it] = gload_or(src, (long long)k2 * a.ld + rr, (k2 < K2) & (rr < rows));
+      }
     }
     // the Gramian scalars' partials, loaded while the spectra are in flight
     if constexpr (MODE == FUSE_GRAD) {
@@ -427,8 +438,12 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       int k2, rr;
       pos(it, k2, rr);
       if (k2 < K2) {
-        if (k2 == 0 || k2 == K2 - 1) hv[it].im = T(0);  // DC and Nyquist of a real row are real
-        smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = hv[it];
+        cx<T> h = hv[it];
+        if constexpr (TPF >= 2) {
+          if (rr0 >= rows) h = cx<T>{T(0), T(0)};
+        }
+        if (k2 == 0 || k2 == K2 - 1) h.im = T(0);  // DC and Nyquist of a real row are real
+        smem[(rr >> 1) * BS + (rr & 1) * K2 + k2] = h;
       }
     }
     __syncthreads();
