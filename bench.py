@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "c6404326c811383a6991b4885defa06221a10004d3b834d72f08d5f1f20d95d9",
+    "csrc_sha256": "eda652b17070804f3bcdf0b4147d426c07a2d8cb158008bbf133cbe28cb38acc",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50694454, 50528447), "fwd_col_eig_sum": (77056386, 4210688),
-        "fwd_row_c2r": (2313602, 528416), "adj_row_r2c": (1067398, 1064960),
-        "adj_col_conj_eig": (52012405, 33685504), "adj_row_c2r": (70379434, 16810091),
+        "fwd_row_r2c": (50671947, 50528423), "fwd_col_eig_sum": (77057260, 4698076),
+        "fwd_row_c2r": (2268379, 532512), "adj_row_r2c": (675547, 1064960),
+        "adj_col_conj_eig": (52041137, 33685504), "adj_row_c2r": (70374215, 16810083),
     },
 }
 

@@ -291,19 +291,18 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     constexpr int ITER = (2 * K2 + TPF - 1) / TPF;
     const int rr = threadIdx.x % RT, k0 = threadIdx.x / RT;
     const cx<T>* srow = smem + (rr >> 1) * BS + (rr & 1) * K2;
+    // k0 < TPF / 2: only the last pass reaches past K2, where the k0 = 0 lane holds the
+    // Nyquist column; the others store from one per-thread base with a uniform stride.
     cx<T> ov[ITER];
 #pragma unroll
-    for (int it = 0; it < ITER; ++it) {
-      const int k2 = k0 + it * (TPF / 2);
-      if (k2 < K2) ov[it] = srow[k2];
-    }
+    for (int it = 0; it < ITER - 1; ++it) ov[it] = srow[k0 + it * (TPF / 2)];
+    if (k0 == 0) ov[ITER - 1] = srow[K2 - 1];
     if (rr < rows) {
-      cx<T>* drow = dst + rr;
+      cx<T>* dp = dst + rr + (long long)k0 * a.ld;
+      const long long st = (long long)(TPF / 2) * a.ld;
 #pragma unroll
-      for (int it = 0; it < ITER; ++it) {
-        const int k2 = k0 + it * (TPF / 2);
-        if (k2 < K2) gstore(drow + (long long)k2 * a.ld, ov[it]);
-      }
+      for (int it = 0; it < ITER - 1; ++it) gstore(dp + it * st, ov[it]);
+      if (k0 == 0) gstore(dp + (ITER - 1) * st, ov[ITER - 1]);
     }
     return;
   }
