@@ -16,7 +16,11 @@ Follows Sec. 2.2-2.6 and 2.8 of the paper in its own notation:
 
 Readings where the paper is silent or inconsistent (each listed in the design notes):
 * RRCG:4 prints alpha (m~_k - m~_{k-1}); the gradient of eq. (GlobalFunction2) is
-  alpha (m~ - m~_apr).  The oracle uses the gradient-consistent anchor m~_apr.
+  alpha (m~ - m~_apr).  The default anchor is the gradient-consistent m~_apr;
+  anchor="prev" takes the printed form, with m~_{k-1} read as W_k m_{k-1}: the model at
+  the start of the previous CG step, in the current weighted space (m_{-1} := m_0, so the
+  term vanishes at the first step).  Inside one reweighting W is fixed and the term is
+  -alpha s_{k-1} p_{k-1}.
 * The printed iteration is a single loop (one CG step per reweighting, beta carried
   over).  ``outer_step(n_inner=J)`` runs J CG steps at a frozen W, alpha, with the
   residual updated by the recurrence r~ <- r~ - s A~ p after the first, then the
@@ -32,7 +36,12 @@ l_G vanishes there, S_G >= 0, finite-difference gradient = 2 l_G, the scalar-wei
 relation S~_G = (w1 w2)^2 S_G); with lambda = 0, W fixed, no bounds, q = 1 one outer
 step of n inner steps reaches (A~^T A~ + alpha I)^-1 A~^T d~ (normal equations solved
 by numpy.linalg.solve); bounds hold after every outer step; exchanging the two data
-sets exchanges the result; the objective decreases within an inner cycle (lambda = 0).
+sets exchanges the result; the objective decreases within an inner cycle (lambda = 0);
+with non-uniform W the iteration's limit satisfies RRCG:4 with l_G the finite-difference
+half-gradient of the Gramian on m (gramian="original") or on m~ ("weighted"), and not the
+other; the printed single loop (beta carried over) reaches the Tikhonov solution in 3n
+steps; the anchor="prev" limit solves the unregularised system (A m = d on a square one)
+while the m~_apr anchor's is the Tikhonov solution.
 Full multi-step trajectories are pinned only against these properties.
 """
 from __future__ import annotations
@@ -80,6 +89,7 @@ class Params:
     restart: bool = True
     p_norm: int = 1
     gramian: str = "original"
+    anchor: str = "apr"
 
 
 @dataclass
@@ -99,17 +109,20 @@ class State:
     alpha: List[float]
     frozen: List[bool] = field(default_factory=lambda: [False, False])
     k: int = 0
+    m_prev: Optional[List[np.ndarray]] = None   # model at the start of the last CG step
 
     def copy(self) -> "State":
+        mp = None if self.m_prev is None else [x.copy() for x in self.m_prev]
         return State([x.copy() for x in self.m], [x.copy() for x in self.p],
-                     list(self.L_prev), list(self.alpha), list(self.frozen), self.k)
+                     list(self.L_prev), list(self.alpha), list(self.frozen), self.k, mp)
 
 
 def initial_state(data: Data, prm: Params, shape) -> State:
-    """m_0 = m_apr, p = 0, no previous gradient, alpha = alpha_0."""
+    """m_0 = m_apr, p = 0, no previous gradient, alpha = alpha_0, m_{-1} = m_0."""
     mapr = data.mapr or [np.zeros(shape), np.zeros(shape)]
     return State([mapr[0].copy(), mapr[1].copy()], [np.zeros(shape), np.zeros(shape)],
-                 [0.0, 0.0], [float(prm.alpha0[0]), float(prm.alpha0[1])])
+                 [0.0, 0.0], [float(prm.alpha0[0]), float(prm.alpha0[1])],
+                 m_prev=[mapr[0].copy(), mapr[1].copy()])
 
 
 def model_weight(i: int, m: np.ndarray, data: Data, prm: Params) -> np.ndarray:
@@ -133,6 +146,7 @@ def outer_step(ops, data: Data, prm: Params, st: State, n_inner: int):
     mt_apr = [W[i] * mapr[i] for i in range(2)]                # m~_apr = W m_apr
     p = [st.p[0].copy(), st.p[1].copy()]
     L_prev = list(st.L_prev)
+    m_prev = [x.copy() for x in (st.m_prev if st.m_prev is not None else st.m)]
     rt = None
     rec = dict(beta=[], s=[], L=[])
     for j in range(n_inner):
@@ -141,9 +155,10 @@ def outer_step(ops, data: Data, prm: Params, st: State, n_inner: int):
             rt = [data.wd[i] * (A[i].matvec(m[i]) - data.dobs[i]) for i in range(2)]
         u = m if prm.gramian == "original" else mt
         lG = gramian_ascent(u[0], u[1])                        # RRCG:2-3
-        # RRCG:4: l = A~^T r~ + alpha (m~ - m~_apr) + lambda l_G, A~^T r~ = W^-1 A^T W_d r~
+        # RRCG:4: l = A~^T r~ + alpha (m~ - anchor) + lambda l_G, A~^T r~ = W^-1 A^T W_d r~
+        anchor = mt_apr if prm.anchor == "apr" else [W[i] * m_prev[i] for i in range(2)]
         l = [A[i].rmatvec(data.wd[i] * rt[i]) / W[i]
-             + st.alpha[i] * (mt[i] - mt_apr[i])
+             + st.alpha[i] * (mt[i] - anchor[i])
              + prm.lam[i] * lG[i] for i in range(2)]
         L = [dot(l[i], l[i]) for i in range(2)]
         restart_now = (j == 0 and prm.restart)
@@ -164,6 +179,7 @@ def outer_step(ops, data: Data, prm: Params, st: State, n_inner: int):
             s = [s_, s_]
         else:
             s = [num[i] / den[i] for i in range(2)]
+        m_prev = m                                             # start of this CG step
         mt = [mt[i] - s[i] * p[i] for i in range(2)]           # RRCG:7
         rt = [rt[i] - s[i] * q[i] for i in range(2)]
         L_prev = L
@@ -179,7 +195,7 @@ def outer_step(ops, data: Data, prm: Params, st: State, n_inner: int):
     frozen = [st.frozen[i] or passed[i] for i in range(2)]
     alpha = [st.alpha[i] if frozen[i] else max(prm.q[i] * st.alpha[i], prm.alpha_min[i])
              for i in range(2)]                                # eq. regpara
-    new = State(m_new, p, L_prev, alpha, frozen, st.k + 1)
+    new = State(m_new, p, L_prev, alpha, frozen, st.k + 1, m_prev)
     rec.update(phi=phi, threshold=thr, converged=all(passed), frozen=frozen,
                alpha_used=list(st.alpha), alpha_next=alpha,
                gramian=gramian(m_new[0], m_new[1]))

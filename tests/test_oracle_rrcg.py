@@ -214,3 +214,131 @@ def test_lambda_choice_rule():
     assert rrcg.select_lambda(runs, 0.4) == 0
     assert rrcg.select_lambda([rec(False, 1.0)], 0.0) is None   # a run stopped by the limit
     assert rrcg.select_lambda([], 0.5) is None
+
+
+# ------------------------------------------------------------------------------------
+# branches of RRCG:4-5 that the W = I pins above cannot tell apart
+# ------------------------------------------------------------------------------------
+def _half_grad_fd(f, a, b, h=1e-5):
+    """Half the gradient of f(a, b) with respect to a and to b, by central differences
+    (written out here, independent of the oracle's ascent directions)."""
+    ga, gb = np.zeros(a.size), np.zeros(b.size)
+    for j in range(a.size):
+        e = np.zeros(a.size)
+        e[j] = h
+        e = e.reshape(a.shape)
+        ga[j] = (f(a + e, b) - f(a - e, b)) / (4 * h)
+        gb[j] = (f(a, b + e) - f(a, b - e)) / (4 * h)
+    return ga, gb
+
+
+def _gram_det(a, b):
+    a, b = a.ravel(), b.ravel()
+    return float(np.dot(a, a) * np.dot(b, b) - np.dot(a, b) ** 2)
+
+
+@pytest.mark.parametrize("branch", ["original", "weighted"])
+def test_gramian_branch_fixed_point_with_nonuniform_weights(ops6, branch):
+    # With a non-uniform, fixed W (p = 2, depth weights in [0.5, 2]) the two Gramian readings
+    # have different limits: RRCG:4 vanishes at the limit, with l_G the half-gradient of
+    # S_G(m1, m2) at m = m~/W ("original", eqs. RRCG:2-3) or of S_G(m~1, m~2) ("weighted",
+    # eqs. steepestascenta/b).  Both half-gradients are taken here by finite differences of
+    # the Gramian determinant; the other branch's equation must be far from satisfied.
+    g = G6
+    r = np.random.default_rng(3)
+    wdepth = [r.uniform(0.5, 2.0, (g.nz, g.nx, g.ny)) for _ in range(2)]
+    data, _ = _data(g, ops6, noise=0.5, wdepth=wdepth)
+    lam, alpha = (1e3, 3e2), (20.0, 5.0)
+    prm = rrcg.Params(alpha0=alpha, q=(1.0, 1.0), lam=lam, p_norm=2, restart=True, gramian=branch)
+    st = rrcg.initial_state(data, prm, (g.nz, g.nx, g.ny))
+    for _ in range(300):
+        st, _ = rrcg.outer_step(ops6, data, prm, st, n_inner=50)
+    m = st.m
+    mt = [wdepth[i] * m[i] for i in range(2)]
+    base = []
+    for i in range(2):
+        A, W, wd = ops6[i].A, wdepth[i].ravel(), data.wd[i].ravel()
+        rt = wd * (A @ m[i].ravel() - data.dobs[i].ravel())
+        base.append((A.T @ (wd * rt)) / W + alpha[i] * mt[i].ravel())
+    lg = {"weighted": _half_grad_fd(_gram_det, mt[0], mt[1]), "original": _half_grad_fd(_gram_det, m[0], m[1])}
+
+    def residual(which):
+        res = np.concatenate([base[i] + lam[i] * lg[which][i] for i in range(2)])
+        coup = np.concatenate([lam[i] * lg[which][i] for i in range(2)])
+        return np.linalg.norm(res) / np.linalg.norm(coup)
+    other = "weighted" if branch == "original" else "original"
+    assert residual(branch) <= 0.1
+    assert residual(other) >= 0.5
+
+
+def test_printed_single_loop_reaches_tikhonov_solution(ops6):
+    # The printed iteration: one CG step per reweighting, beta carried over (RRCG:5 with
+    # p_0 = l_0 only at the very start).  With lambda = 0, W fixed, q = 1 and no bounds it is
+    # CG on (A~^T A~ + alpha I) m~ = A~^T d~ with the residual taken exactly every step, so
+    # 3n steps reach the normal equations' solution (numpy.linalg.solve); the same number
+    # of steps with beta reset every step (steepest descent) stays far from it.
+    g = G6
+    r = np.random.default_rng(2)
+    wdepth = [r.uniform(0.5, 2.0, (g.nz, g.nx, g.ny)) for _ in range(2)]
+    data, _ = _data(g, ops6, noise=1.0, wdepth=wdepth)
+    alpha = (3.0, 0.5)
+    ref = []
+    for i in range(2):
+        A, W = ops6[i].A, wdepth[i].ravel()
+        At = np.diag(data.wd[i].ravel()) @ A @ np.diag(1.0 / W)
+        mt = np.linalg.solve(At.T @ At + alpha[i] * np.eye(g.n), At.T @ (data.wd[i] * data.dobs[i]).ravel())
+        ref.append(mt / W)
+    err = {}
+    for restart in (False, True):
+        prm = rrcg.Params(alpha0=alpha, q=(1.0, 1.0), lam=(0.0, 0.0), p_norm=2, restart=restart)
+        st, _ = rrcg.run(ops6, data, prm, n_outer=3 * g.n, n_inner=1)
+        err[restart] = max(np.linalg.norm(st.m[i].ravel() - ref[i]) / np.linalg.norm(ref[i]) for i in range(2))
+    assert err[False] <= 1e-8
+    assert err[True] >= 1e-3
+
+
+G81 = prism.Geometry(8, 8, 8, 8, 1, 50.0, 50.0, 50.0)   # one layer: a square, invertible system
+
+
+@pytest.mark.parametrize("n_inner,restart", [(1, False), (5, True)])
+def test_previous_iterate_anchor_limit_drops_the_regulariser(n_inner, restart):
+    # RRCG:4 as printed, alpha (m~_k - m~_{k-1}): at a limit m~_k = m~_{k-1}, so the term
+    # vanishes and the limit solves A~^T (A~ m~ - d~) = 0, i.e. A m = d for this square,
+    # invertible system with exact data; the gradient-consistent anchor m~_apr = 0 converges
+    # to the Tikhonov solution instead.
+    g = G81
+    ops = _ops(g)
+    A = [ops[i].A for i in range(2)]
+    r = np.random.default_rng(2)
+    wdepth = [r.uniform(0.8, 1.25, (g.nz, g.nx, g.ny)) for _ in range(2)]
+    rr = np.random.default_rng(0)
+    m_true = [rr.uniform(0.0, 1.0, (g.nz, g.nx, g.ny)), rr.uniform(0.0, 0.05, (g.nz, g.nx, g.ny))]
+    d = [ops[i].matvec(m_true[i]) for i in range(2)]
+    # W_d scales each A~ to unit largest singular value, so that alpha = 0.3 matters
+    wd = [np.full(d[i].shape, 1.0 / np.linalg.norm(A[i], 2)) for i in range(2)]
+    data = rrcg.Data(dobs=d, wd=wd, wdepth=wdepth)
+    exact = [np.linalg.solve(A[i], d[i].ravel()) for i in range(2)]
+    steps = 200 if n_inner == 1 else 60
+    res = {}
+    for anchor in ("prev", "apr"):
+        prm = rrcg.Params(alpha0=(0.3, 0.3), q=(1.0, 1.0), p_norm=2, restart=restart, anchor=anchor)
+        st, _ = rrcg.run(ops, data, prm, n_outer=steps, n_inner=n_inner)
+        res[anchor] = max(np.linalg.norm(st.m[i].ravel() - exact[i]) / np.linalg.norm(exact[i]) for i in range(2))
+    assert res["prev"] <= 1e-10
+    assert res["apr"] >= 0.1
+
+
+def test_previous_iterate_anchor_first_step_and_state(ops6):
+    # m_{-1} := m_0: the first CG step of a run has no anchor term, so from m_0 = 0 it equals
+    # the step of the m~_apr = 0 anchor; the state then carries the start of its last CG step.
+    g = G6
+    data, _ = _data(g, ops6, noise=1.0)
+    kw = dict(alpha0=(50.0, 20.0), q=(0.9, 0.8), lam=(1e-2, 3e-1), restart=True)
+    st_p, _ = rrcg.run(ops6, data, rrcg.Params(anchor="prev", **kw), n_outer=1, n_inner=1)
+    st_a, _ = rrcg.run(ops6, data, rrcg.Params(anchor="apr", **kw), n_outer=1, n_inner=1)
+    for i in range(2):
+        assert np.array_equal(st_p.m[i], st_a.m[i])
+        assert np.array_equal(st_p.m_prev[i], np.zeros_like(st_p.m[i]))
+    st2, _ = rrcg.outer_step(ops6, data, rrcg.Params(anchor="prev", **kw), st_p, n_inner=3)
+    st3, _ = rrcg.outer_step(ops6, data, rrcg.Params(anchor="apr", **kw), st_p, n_inner=3)
+    assert not np.array_equal(st2.m[0], st3.m[0])
