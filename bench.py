@@ -90,28 +90,39 @@ def solver(pk, torch, ops, dobs, wd, wdepth, use_graph=True):
                         use_graph=use_graph)
 
 
+def _dist(ts_ms):
+    """median, p10 and p90 of launch durations (ms) in microseconds."""
+    a = np.sort(np.asarray(ts_ms, dtype=np.float64)) * 1e3
+    return {"n": int(a.size), "median_us": float(np.median(a)), "p10_us": float(np.percentile(a, 10)),
+            "p90_us": float(np.percentile(a, 90))}
+
+
 def product_rate(torch, ops, pairs):
-    """Operator pairs per second of back-to-back products (inputs resident in HBM)."""
+    """Operator pairs per second of back-to-back products (inputs resident in HBM), and the
+    distribution of one pair's duration (HIP events on the launch stream around every pair)."""
     xs = [torch.rand(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
     rs = [torch.randn(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
     ys = [torch.empty(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
     zs = [torch.empty(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
-    for _ in range(5):
+    for _ in range(10):
         for i, op in enumerate(ops):
             op.matvec(xs[i], out=ys[i])
             op.rmatvec(rs[i], out=zs[i])
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(pairs + 1)]
     n = 0
-    e0.record()
+    ev[0].record()
     while n < pairs:
         for i, op in enumerate(ops):
+            if n >= pairs:
+                break
             op.matvec(xs[i], out=ys[i])
             op.rmatvec(rs[i], out=zs[i])
             n += 1
-    e1.record()
+            ev[n].record()
     torch.cuda.synchronize()
-    return n / (e0.elapsed_time(e1) / 1e3)
+    ts = [ev[k].elapsed_time(ev[k + 1]) for k in range(pairs)]
+    return n / (ev[0].elapsed_time(ev[pairs]) / 1e3), _dist(ts)
 
 
 BATCH_OUTER, BATCH_INNER = 5, 10
@@ -292,72 +303,119 @@ def kernel_bytes(info, esz, weighted=True):
 
 
 def group_kernel_bytes(infos, esz):
-    """Bytes each launch of the solver's product group must move (all members, one plan
-    info each): as kernel_bytes, plus the vectors the fused CG pieces read and write -- the
-    direction update in the forward row transform (reads l, p, 1/w, writes p) and the
-    gradient in the transpose's inverse row transform (reads m of both data sets and w, which
-    also divides the transform; writes l)."""
-    tot = {}
+    """Per launch of the solver's product group (all members, one plan info each): the method's
+    bytes and, apart, the intermediates.  Method bytes: the stored eigenvalues the column passes
+    read, and the vectors the launch must read or write once -- the product's input and output
+    and the RRCG vectors its fused pieces touch (direction update in the forward row transform:
+    reads l, p, 1/w, writes p; gradient in the transpose's inverse row transform: reads both
+    models and w, writes l; ||q||^2 with the forward data rows: writes q, reads W_d).
+    Intermediates: the row spectra U ([nz][Py/2+1][nx] complex) between the row transforms and the
+    column passes, and the data-side spectra V, which a fused pipeline would keep on chip."""
+    alg, inter = {}, {}
     for info in infos:
         nz, nx, ny, sx, sy = info["nz"], info["nx"], info["ny"], info["sx"], info["sy"]
         K2 = info["Py"] // 2 + 1
         c = 2 * esz
         n, nd = nz * nx * ny, sx * sy
         eig = info["eig_bytes"]
-        U = nz * K2 * nx * c
-        per = {
-            "fwd_row_r2c": 4 * n * esz + U,
-            "fwd_col_eig_sum": eig + U + K2 * sx * c,
-            "fwd_row_c2r": K2 * sx * c + 2 * nd * esz,
-            "adj_row_r2c": 2 * nd * esz + K2 * sx * c,
-            "adj_col_conj_eig": eig + K2 * sx * c + U,
-            "adj_row_c2r": U + 4 * n * esz,
-        }
-        for k, v in per.items():
-            tot[k] = tot.get(k, 0) + v
+        U, V = nz * K2 * nx * c, K2 * sx * c
+        a = {"fwd_row_r2c": 4 * n * esz, "fwd_col_eig_sum": eig, "fwd_row_c2r": 2 * nd * esz,
+             "adj_row_r2c": 2 * nd * esz, "adj_col_conj_eig": eig, "adj_row_c2r": 4 * n * esz}
+        m = {"fwd_row_r2c": U, "fwd_col_eig_sum": U + V, "fwd_row_c2r": V,
+             "adj_row_r2c": V, "adj_col_conj_eig": V + U, "adj_row_c2r": U}
+        for k in a:
+            alg[k] = alg.get(k, 0) + a[k]
+            inter[k] = inter.get(k, 0) + m[k]
+    return alg, inter
+
+
+def b_alg(info, esz):
+    """Algorithmic bytes of one operator pair (y = A m and z = A^T r of one operator): the
+    eigenvalues as a complex [nz][Px][Py/2+1] array read by both products, the model read and
+    written, the data written and read."""
+    nz, Px, K2 = info["nz"], info["Px"], info["Py"] // 2 + 1
+    return (2 * nz * Px * K2 * 2 * esz + 2 * info["nx"] * info["ny"] * nz * esz
+            + 2 * info["sx"] * info["sy"] * esz)
+
+
+def rrcg_step_bytes(infos, esz):
+    """Algorithmic bytes of one inner CG step of the joint solve (both operators): the products'
+    eigenvalue reads and the vector passes the step's launches make (direction update, gradient,
+    model update with its Gramian partials, residual update and the data-side products)."""
+    tot = 0
+    for info in infos:
+        n = info["nz"] * info["nx"] * info["ny"]
+        nd = info["sx"] * info["sy"]
+        tot += 2 * info["eig_bytes"]            # forward and transpose column passes
+        tot += 4 * n * esz                      # direction: l, p, 1/w read, p written
+        tot += 4 * n * esz                      # gradient: both models and w read, l written
+        tot += 4 * n * esz                      # update: m, p, w read, m written
+        tot += 2 * nd * esz + 3 * nd * esz      # q written, W_d read; r~, q read, r~ written
+        tot += 2 * nd * esz                     # W_d r~ into the transpose (r~ and W_d read)
     return tot
 
 
 def group_pair_rate(pk, torch, ops, pairs):
-    """Operator pairs per second when both operators' products share each launch."""
+    """Operator pairs per second when both operators' products share each launch, and the
+    distribution of one joint pair's duration (HIP events on the launch stream)."""
     grp = pk.Group(ops)
     xs = [torch.rand(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
     rs = [torch.randn(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
     ys = [torch.empty(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
     zs = [torch.empty(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
     P = [pk.pointer_array(v, "cuda") for v in (xs, ys, rs, zs)]
-    for _ in range(5):
+    for _ in range(10):
         grp.apply_ptrs(0, P[0], P[1])
         grp.apply_ptrs(1, P[2], P[3])
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    n = 0
-    e0.record()
-    while n < pairs:
+    reps = max(1, pairs // len(ops))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record()
+    for k in range(reps):
         grp.apply_ptrs(0, P[0], P[1])
         grp.apply_ptrs(1, P[2], P[3])
-        n += len(ops)
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
     grp.close()
-    return n / (e0.elapsed_time(e1) / 1e3)
+    ts = [ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]
+    return reps * len(ops) / (ev[0].elapsed_time(ev[reps]) / 1e3), _dist(ts)
 
 
-def pair_bytes(infos, esz):
-    """Algorithmic bytes of one operator pair, averaged over the operators: the stored
-    eigenvalues read by both products, the model read and written, the data written and
-    read."""
+def stored_pair_bytes(infos, esz):
+    """Bytes one operator pair moves with the eigenvalues as stored (real and x-even for a
+    symmetric operator), averaged over the operators."""
     b = [2 * i["eig_bytes"] + 2 * i["nx"] * i["ny"] * i["nz"] * esz + 2 * i["sx"] * i["sy"] * esz for i in infos]
     return sum(b) / len(b)
 
 
-def cpu_baseline(g, budget_s=12.0):
-    """FP64 oracle FFT2 products on the host cores: operator pairs per second."""
+def _cores():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_geometry(g):
+    from oracle import prism as oprism
+    return oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+
+
+def cpu_baseline(g, budget_s=10.0):
+    """The FP64 oracle's FFT2 products on the host cores, as it stands: operator pairs per
+    second on a bounded sample."""
     import synth
     from oracle import bttb as obttb
     from oracle import prism as oprism
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    og = oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+    cores = _cores()
+    og = _oracle_geometry(g)
     ops = [obttb.FFTOperator(obttb.kernel_array(k, og), g.sx, g.sy, workers=cores)
            for k in (oprism.GRAVITY, oprism.MAGNETIC)]
     rho, kap = synth.dyke_and_block(g)
@@ -374,8 +432,89 @@ def cpu_baseline(g, budget_s=12.0):
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "op-pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} operator pairs (G m and G^T r, gravity and magnetic alternating) of the "
-                      f"256x256x32 operators, scipy.fft FP64 on the unpadded 511x511 circle, "
-                      f"workers={cores}, {dt:.1f} s"}
+                      f"256x256x32 operators, the oracle's scipy.fft FP64 products on the unpadded 511x511 "
+                      f"circle (eigenvalues retaken every product), workers={cores}, {dt:.1f} s, host "
+                      f"{_cpu_model()}"}
+
+
+class CpuFFTOperator:
+    """A faster FP64 CPU product for the baseline (not the oracle): each layer's BCCB
+    eigenvalues taken once with rfft2 on a Px x Py circle (scipy's next fast lengths >=
+    sx+nx-1, sy+ny-1), then y = irfft2(sum_r E_r rfft2(x_r)) and z_r = irfft2(conj(E_r) rfft2(r))
+    over all layers in one batched call each.  Built from the oracle's kernel arrays."""
+
+    def __init__(self, T, sx, sy, workers):
+        import scipy.fft as sfft
+        self.sfft = sfft
+        nz, Lx, Ly = T.shape
+        self.sx, self.sy, self.nz = sx, sy, nz
+        self.nx, self.ny = Lx - sx + 1, Ly - sy + 1
+        self.Px, self.Py = sfft.next_fast_len(Lx, real=True), sfft.next_fast_len(Ly, real=True)
+        self.workers = workers
+        C = np.zeros((nz, self.Px, self.Py))
+        u = (np.arange(Lx) - (self.nx - 1)) % self.Px
+        v = (np.arange(Ly) - (self.ny - 1)) % self.Py
+        C[:, u[:, None], v[None, :]] = T
+        self.E = sfft.rfft2(C, workers=workers)
+
+    def matvec(self, x):
+        X = self.sfft.rfft2(x, s=(self.Px, self.Py), workers=self.workers)
+        y = self.sfft.irfft2((self.E * X).sum(axis=0), s=(self.Px, self.Py), workers=self.workers)
+        return y[:self.sx, :self.sy]
+
+    def rmatvec(self, r):
+        R = self.sfft.rfft2(r, s=(self.Px, self.Py), workers=self.workers)
+        z = self.sfft.irfft2(np.conj(self.E) * R[None], s=(self.Px, self.Py), workers=self.workers)
+        return z[:, :self.nx, :self.ny]
+
+
+def cpu_fft_baselines(grids, budget_s=3.0, rrcg_grid=None, n_inner=N_INNER):
+    """CPU FP64 products with the eigenvalues precomputed (CpuFFTOperator), on one core and on all
+    host cores, for each grid; and one RRCG outer step (the oracle's iteration driven by these
+    products, all cores) on rrcg_grid."""
+    import synth
+    from oracle import bttb as obttb
+    from oracle import prism as oprism
+    from oracle import rrcg as orrcg
+    cores = _cores()
+    out = {"cores": cores, "host": _cpu_model(), "kind": "scipy.fft rfft2/irfft2, eigenvalues precomputed"}
+    for name, g in grids:
+        og = _oracle_geometry(g)
+        T = [obttb.kernel_array(k, og) for k in (oprism.GRAVITY, oprism.MAGNETIC)]
+        rho, kap = synth.dyke_and_block(g)
+        r = synth.normal_like(g.data_shape, 3, 7)
+        row = {}
+        for w in (1, cores):
+            ops = [CpuFFTOperator(T[i], g.sx, g.sy, w) for i in range(2)]
+            n, t0 = 0, time.perf_counter()
+            while True:
+                for op, m in zip(ops, (rho, kap)):
+                    op.matvec(m)
+                    op.rmatvec(r)
+                    n += 1
+                if time.perf_counter() - t0 >= budget_s:
+                    break
+            dt = time.perf_counter() - t0
+            row[f"workers_{w}"] = {"op_pairs_per_s": n / dt, "pairs": n, "s": dt}
+        row["transform"] = [ops[0].Px, ops[0].Py]
+        out[name] = row
+        if rrcg_grid is not None and g == rrcg_grid:
+            ops = [CpuFFTOperator(T[i], g.sx, g.sy, cores) for i in range(2)]
+            d = [ops[0].matvec(rho), ops[1].matvec(kap)]
+            sig = [synth.noise_sigma(d[0], 0.02, 0.02), synth.noise_sigma(d[1], 0.02, 1.0)]
+            dobs = [d[i] + sig[i] * synth.normal_like(d[i].shape, 3, 100 + i) for i in range(2)]
+            data = orrcg.Data(dobs=dobs, wd=[1.0 / x for x in sig],
+                              wdepth=[synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)])
+            prm = orrcg.Params(alpha0=(20000.0, 20000.0), q=(0.95, 0.95), lam=(2.0, 100.0), eps2=1e-9,
+                               lo=(0.0, 0.0), hi=(1.0, 0.1), coupled=True, restart=True, p_norm=1)
+            st = orrcg.initial_state(data, prm, g.model_shape)
+            t0 = time.perf_counter()
+            orrcg.outer_step(ops, data, prm, st, n_inner)
+            dt = time.perf_counter() - t0
+            out["rrcg_outer_step"] = {"grid": name, "inner": n_inner, "s": dt, "workers": cores,
+                                      "op_pairs_per_s": 2 * n_inner / dt,
+                                      "full_solve_s_estimate": 20 * dt}
+    return out
 
 
 def main():
@@ -409,11 +548,15 @@ def main():
     s32.prepare(N_INNER)            # capture the outer-step graph before the timed region
     torch.cuda.synchronize()
     log("bench: fp32 timed solve")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for k in range(args.steps):
         s32.step(N_INNER)
+        ev[k + 1].record()
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
+    outer_ms = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
     sc32 = s32.scalars()
     s32.close()
     info32 = ops32[0].info()
@@ -421,10 +564,10 @@ def main():
     pairs = 2 * N_INNER * args.steps
     value = pairs / t32
 
-    # per-kernel HIP-event timing in the same solve, launched kernel by kernel (graphs
-    # hold no timing events); two outer steps, each product kernel launched TIMING_REPEAT
-    # times back to back between its events (idempotent: every kernel reads one buffer
-    # and writes another)
+    # per-kernel HIP-event timing in the same solve, launched kernel by kernel (graphs hold no
+    # timing events); two outer steps, each product kernel launched TIMING_REPEAT times back to
+    # back between its events (the fused direction update's repeats write to scratch, so the
+    # solver's state is that of one launch)
     log("bench: fp32 per-kernel timing")
     se = solver(pk, torch, ops32, dobs, wd, wdepth, use_graph=False)
     prod = se.products()  # both operators' products share each launch of this group
@@ -435,40 +578,42 @@ def main():
     for _ in range(2):
         se.step(N_INNER)
     torch.cuda.synchronize()
-    timings = [prod.timing_read()]
+    lst = prod.timing_list(launches)
     prod.timing_enable(0)
     se.close()
 
-    # dominant kernel and its roofline
-    tot = {}
-    for tm in timings:
-        for k, (ms, n) in tm.items():
-            a = tot.setdefault(k, [0.0, 0])
-            a[0] += ms
-            a[1] += n
-    dom = max(tot, key=lambda k: tot[k][0])
-    avg_ms = tot[dom][0] / max(tot[dom][1], 1)
-    gkb = group_kernel_bytes(infos32, 4)
-    kb = gkb[dom]
+    # dominant kernel and its roofline: the method's bytes per launch (no intermediates)
+    per = {}
+    for k, ms in lst:
+        per.setdefault(k, []).append(ms)
+    tot = {k: sum(v) for k, v in per.items()}
+    dom = max(tot, key=lambda k: tot[k])
+    avg_ms = tot[dom] / len(per[dom])
+    alg, inter = group_kernel_bytes(infos32, 4)
+    kb = alg[dom]
     achieved = kb / (avg_ms * 1e-3) / 1e9
-    kernel_table = {k: {"launches": n, "avg_us": 1e3 * ms / max(n, 1), "bytes": gkb[k],
-                        "GBps": gkb[k] / (ms / max(n, 1) * 1e-3) / 1e9 if n else None}
-                    for k, (ms, n) in tot.items()}
+    kernel_table = {k: {"launches": len(v) * TIMING_REPEAT, "avg_us": 1e3 * tot[k] / len(v), "bytes": alg[k],
+                        "intermediate_bytes": inter[k], "GBps": alg[k] / (tot[k] / len(v) * 1e-3) / 1e9,
+                        "dist": _dist(v)}
+                    for k, v in per.items()}
+    # one forward and one transpose product of both operators as the solve launches them
+    step_us = sum(kernel_table[k]["avg_us"] for k in kernel_table)
+    B32 = [b_alg(i, 4) for i in infos32]
 
     log("bench: copy calibration")
     copy = copy_probe(torch)
 
     # ---------------- product throughput ----------------
     log("bench: product rates")
-    rate32 = product_rate(torch, ops32, args.pairs)
-    grate32 = group_pair_rate(pk, torch, ops32, args.pairs)
+    rate32, dist32 = product_rate(torch, ops32, args.pairs)
+    grate32, gdist32 = group_pair_rate(pk, torch, ops32, args.pairs)
     for op in ops32:
         op.close()
     ops64 = [pk.Operator.from_geometry(k, g, dtype=torch.float64) for k in (pk.GRAVITY, pk.MAGNETIC)]
-    info64 = ops64[0].info()
     infos64 = [op.info() for op in ops64]
-    rate64 = product_rate(torch, ops64, args.pairs)
-    grate64 = group_pair_rate(pk, torch, ops64, args.pairs)
+    rate64, dist64 = product_rate(torch, ops64, args.pairs)
+    grate64, gdist64 = group_pair_rate(pk, torch, ops64, args.pairs)
+    B64 = [b_alg(i, 8) for i in infos64]
 
     # ---------------- FP64 solve ----------------
     t64 = None
@@ -491,6 +636,20 @@ def main():
     for op in ops64:
         op.close()
 
+    # ---------------- 128x128x20: FP64 and FP32 product rates ----------------
+    log("bench: 128x128x20 product rates")
+    gm = synth.MID
+    mid = {}
+    for name, dt in (("f32", torch.float32), ("f64", torch.float64)):
+        opsm = [pk.Operator.from_geometry(k, gm, dtype=dt) for k in (pk.GRAVITY, pk.MAGNETIC)]
+        r1, d1 = product_rate(torch, opsm, args.pairs)
+        r2, d2 = group_pair_rate(pk, torch, opsm, args.pairs)
+        bm = sum(b_alg(op.info(), 4 if dt == torch.float32 else 8) for op in opsm) / 2
+        mid[name] = {"op_pairs_per_s": r1, "pair_dist": d1, "both_operators_per_launch": r2,
+                     "joint_pair_dist": d2, "GBps_alg": r2 * bm / 1e9, "B_alg": bm}
+        for op in opsm:
+            op.close()
+
     batched = None
     if not args.no_batch:
         log("bench: batched uneven inversions")
@@ -501,12 +660,14 @@ def main():
         log("bench: Lagrange-parameter scan")
         scan = scan_workload(pk, torch)
 
-    cpu = None
+    cpu, cpu_fft = None, None
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
         cpu = cpu_baseline(g)
+        log("bench: cpu fft baselines")
+        cpu_fft = cpu_fft_baselines([("128x128x20", synth.MID), ("256x256x32", g)], rrcg_grid=g)
 
-    b32, b64 = pair_bytes(infos32, 4), pair_bytes(infos64, 8)
+    Bavg32, Bavg64 = sum(B32) / 2, sum(B64) / 2
     out = {
         "metric": METRIC,
         "value": value,
@@ -527,22 +688,38 @@ def main():
                    "inner_per_step": N_INNER,
                    "launch_shape": {k: tune32[k] for k in ("model_row_threads", "data_row_threads", "col_threads",
                                                            "layer_chunks")}},
+        "outer_step": _dist(outer_ms),
         "rrcg_solve_s": {"f32": t32 * 20 / args.steps, "f64": (t64 * 20 / args.steps) if t64 else None,
                          "outer": 20, "inner": N_INNER},
+        "B_alg_per_op_pair": {"f32": Bavg32, "f64": Bavg64,
+                              "stored_eigenvalues": {"f32": stored_pair_bytes(infos32, 4),
+                                                     "f64": stored_pair_bytes(infos64, 8)}},
+        "hbm_frac_B_alg": {"in_solve": value * Bavg32 / 1e9 / HBM_PEAK_GBS,
+                           "products_f32_both_operators_per_launch": grate32 * Bavg32 / 1e9 / HBM_PEAK_GBS,
+                           "products_f64_both_operators_per_launch": grate64 * Bavg64 / 1e9 / HBM_PEAK_GBS,
+                           "pipeline": sum(B32) / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                           "pipeline_us_per_cg_step_products": step_us},
+        "rrcg_bytes_per_inner_step": {"f32": rrcg_step_bytes(infos32, 4),
+                                      "GBps_in_solve": rrcg_step_bytes(infos32, 4) * value / 2 / 1e9},
         "product_pairs_per_s": {"f32": rate32, "f64": rate64, "f32_both_operators_per_launch": grate32,
-                                "f64_both_operators_per_launch": grate64},
-        "product_GBps_alg": {"f32": grate32 * b32 / 1e9, "f64": grate64 * b64 / 1e9,
-                             "bytes_per_pair": {"f32": b32, "f64": b64}},
-        "final_chi2": {"phi": sc32["phi"], "threshold": sc32["threshold"], "alpha": sc32["alpha"]},
+                                "f64_both_operators_per_launch": grate64,
+                                "pair_dist": {"f32": dist32, "f64": dist64},
+                                "joint_pair_dist": {"f32": gdist32, "f64": gdist64}},
+        "product_GBps_alg": {"f32": grate32 * Bavg32 / 1e9, "f64": grate64 * Bavg64 / 1e9},
+        "mid_128x128x20": mid,
+        "final_chi2": {"phi": sc32["phi"], "threshold": sc32["threshold"], "alpha": sc32["alpha"],
+                       "similarity": sc32["similarity"]},
         "roofline": {"bound": "hbm", "kernel": dom + " (gravity and magnetic in one launch)", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom), "bytes_per_launch": kb,
-                     "avg_launch_us": 1e3 * avg_ms, "csrc_sha256": kernel_source_digest()[:16]},
+                     "intermediate_bytes": inter[dom], "avg_launch_us": 1e3 * avg_ms,
+                     "launch_dist": kernel_table[dom]["dist"], "csrc_sha256": kernel_source_digest()[:16]},
         "copy_probe": copy,
         "kernels": kernel_table,
         "batched": batched,
         "lambda_scan": scan,
         "cpu_baseline": cpu,
+        "cpu_fft_baseline": cpu_fft,
     }
     print(json.dumps(out), flush=True)
 

@@ -220,9 +220,17 @@ BTTB_API int bttb_group_destroy(bttb_group g);
 
 /* Event timing of a group's launches, as bttb_timing_enable / bttb_timing_read for a plan
  * (kernel ids as there; each id covers every member of the launch).  Launches captured
- * into a graph are not timed. */
+ * into a graph are not timed.  In a solver's products (rrcg_products, rrcg_group_products),
+ * whose stages carry CG pieces, the repeats before the last launch of a stage write the
+ * in-place direction update (RRCG:5) to a scratch vector and record no scalars: they read
+ * what the last launch reads, so the solver's state is that of one launch. */
 BTTB_API int bttb_group_timing_enable(bttb_group g, int max_launches, int repeat);
 BTTB_API int bttb_group_timing_read(bttb_group g, double* total_ms, int* count);
+/* The timed launches since the last read, one by one, in launch order: kernel id and the
+ * milliseconds of one launch (the time between its events divided by its repeats), at most
+ * `cap` of them; *n receives how many were written.  Synchronises on the events and starts
+ * over, as bttb_group_timing_read does (call one or the other). */
+BTTB_API int bttb_group_timing_list(bttb_group g, int cap, int* kernel_id, double* ms, int* n);
 
 /* ---------------------------------------------------------------------------------- */
 /* Launch-shape autotuning                                                              */
@@ -274,7 +282,16 @@ BTTB_API int bttb_group_autotune(bttb_group g, int reps, void* stream, bttb_tune
  *        restart = 1 sets beta = 0 at the first CG step of every outer step;
  *        p_norm = 1 refreshes W_L1 from the iterate (eq. WL), 2 keeps W_L1 = I;
  *        gramian_weighted = 0 takes the Gramian directions on m (eqs. RRCG:2-3),
- *        1 on m~ (eqs. steepestascenta/b). */
+ *        1 on m~ (eqs. steepestascenta/b);
+ *        anchor: the vector the regularisation term of RRCG:4 pulls toward,
+ *        alpha (m~ - anchor): BTTB_ANCHOR_APR (0) W m_apr, the gradient of eq. (GlobalFunction2);
+ *        BTTB_ANCHOR_PREV (1) the previous iterate as printed in RRCG:4, read as W m_prev with
+ *        m_prev the model at the start of the previous CG step (inside one reweighting this is
+ *        -alpha s_{k-1} p_{k-1}; at the first step m_prev = m_0, so the term vanishes).
+ *   mprev[i]  [nz][nx][ny] state for BTTB_ANCHOR_PREV (ignored, may be NULL, otherwise): the
+ *             model at the start of the last CG step, read by the gradient and rewritten by
+ *             every update; set it equal to m for a fresh start. */
+typedef enum { BTTB_ANCHOR_APR = 0, BTTB_ANCHOR_PREV = 1 } bttb_anchor;
 typedef struct {
   bttb_plan plan[2];
   void* m[2];
@@ -291,6 +308,8 @@ typedef struct {
   int coupled, restart, p_norm, gramian_weighted;
   int use_graph;  /* 1: the step's kernel sequences are captured into HIP graphs and replayed by
                      rrcg_step (fewer launches); 0: launched one by one */
+  int anchor;     /* bttb_anchor */
+  void* mprev[2];
 } rrcg_desc;
 
 /* Scalar state (FP64) of a handle. */
@@ -306,6 +325,10 @@ typedef struct {
   int k;               /* outer steps taken */
   int converged;       /* both chi^2 tests met at the last outer step */
   int nonfinite;       /* a NaN / Inf reached a reduction */
+  double similarity;   /* |(m1, m2)| / (||m1|| ||m2||) of the current models (0 if one is zero): the
+                          cosine the Gramian S_G = ||m1||^2 ||m2||^2 (1 - cos^2) drives to one, by
+                          which a scan over fixed Lagrange parameters (Sec. 3.1.3) compares runs;
+                          computed on the device with S_G after every outer step (read only) */
 } rrcg_scalars;
 
 /* Create a solver for one inversion: the scalars start at alpha = alpha0, no previous

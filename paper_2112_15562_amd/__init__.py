@@ -19,7 +19,7 @@ if not _os.path.exists(_lib.LIB_PATH):  # no fallback path: fail loudly without 
 from .operator import GRAVITY, MAGNETIC, Group, Operator, pointer_array, prism_kernels  # noqa: E402
 from .autograd import BTTBFunction, BTTBTransposeFunction, ForwardModel  # noqa: E402
 from .rrcg import JointRRCG, JointRRCGGroup  # noqa: E402
-from .scan import lambda_scan, similarity  # noqa: E402
+from .scan import lambda_scan  # noqa: E402
 
 __all__ = ["Operator", "Group", "pointer_array", "prism_kernels", "GRAVITY", "MAGNETIC", "BTTBFunction", "BTTBTransposeFunction",
-           "ForwardModel", "JointRRCG", "JointRRCGGroup", "lambda_scan", "similarity", "BTTBError", "MAX_TRANSFORM"]
+           "ForwardModel", "JointRRCG", "JointRRCGGroup", "lambda_scan", "BTTBError", "MAX_TRANSFORM"]

@@ -15,6 +15,7 @@ BTTB_OK, BTTB_EINVAL, BTTB_ENOMEM, BTTB_EHIP, BTTB_ESIZE, BTTB_ESTATE, BTTB_ENAN
 BTTB_F64, BTTB_F32 = 0, 1
 BTTB_GRAVITY, BTTB_MAGNETIC = 0, 1
 BTTB_OP_FORWARD, BTTB_OP_ADJOINT = 0, 1
+BTTB_ANCHOR_APR, BTTB_ANCHOR_PREV = 0, 1
 BTTB_PAD_POW2 = 0x10
 BTTB_EIG_FULL = 0x20
 MAX_TRANSFORM = 2048
@@ -29,6 +30,7 @@ EXPORTED = [
     "rrcg_group_refresh", "rrcg_group_set_launch", "rrcg_group_products", "rrcg_group_destroy",
     "bttb_autotune", "bttb_group_autotune", "rrcg_group_autotune", "bttb_group_timing_enable",
     "bttb_group_timing_read", "rrcg_products", "rrcg_autotune", "rrcg_prepare", "rrcg_group_prepare",
+    "bttb_group_timing_list",
 ]
 NKERNELS = 6
 KERNEL_NAMES = ["fwd_row_r2c", "fwd_col_eig_sum", "fwd_row_c2r", "adj_row_r2c", "adj_col_conj_eig", "adj_row_c2r"]
@@ -71,14 +73,15 @@ class RrcgDesc(C.Structure):
                 ("lo", C.c_double * 2), ("hi", C.c_double * 2), ("alpha0", C.c_double * 2),
                 ("q", C.c_double * 2), ("alpha_min", C.c_double * 2), ("lambda_", C.c_double * 2),
                 ("eps2", C.c_double), ("coupled", C.c_int), ("restart", C.c_int), ("p_norm", C.c_int),
-                ("gramian_weighted", C.c_int), ("use_graph", C.c_int)]
+                ("gramian_weighted", C.c_int), ("use_graph", C.c_int), ("anchor", C.c_int),
+                ("mprev", C.c_void_p * 2)]
 
 
 class RrcgScalars(C.Structure):
     _fields_ = [("alpha", C.c_double * 2), ("L_prev", C.c_double * 2), ("phi", C.c_double * 2),
                 ("threshold", C.c_double), ("beta", C.c_double * 2), ("step", C.c_double * 2),
                 ("gramian", C.c_double), ("frozen", C.c_int * 2), ("k", C.c_int), ("converged", C.c_int),
-                ("nonfinite", C.c_int)]
+                ("nonfinite", C.c_int), ("similarity", C.c_double)]
 
 
 _lib = None
@@ -133,6 +136,7 @@ def lib() -> C.CDLL:
         "rrcg_autotune": [vp, i, vp, C.POINTER(TuneResult)],
         "rrcg_prepare": [vp, i],
         "rrcg_group_prepare": [vp, i],
+        "bttb_group_timing_list": [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_int)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

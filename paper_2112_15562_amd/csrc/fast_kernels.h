@@ -109,7 +109,8 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     // at a time; the first half before the partial sums of beta, whose loads then overlap
     // them.  The half form has no upper half: a row fills at most half the transform.
     const T* lv = fz.l + lofs;
-    T* pv = fz.p + lofs;
+    const T* pv = fz.p + lofs;
+    T* po = fz.pout + lofs;
     T LA[4], LB[4], PA[4], PB[4], SA[4], SB[4];
     auto dir_load = [&](int h) {
 #pragma unroll
@@ -149,7 +150,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
           if (ra) {
             const double lo = LA[i];
             const T pn = (T)(lo + beta * (double)PA[i]);
-            gstore(pv + oa, pn);
+            gstore(po + oa, pn);
             acc[0] += (double)pn * lo;
             acc[1] += (double)pn * (double)pn;
             xa = pn * SA[i];
@@ -157,7 +158,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
           if (rb) {
             const double lo = LB[i];
             const T pn = (T)(lo + beta * (double)PB[i]);
-            gstore(pv + oa + a.ncols, pn);
+            gstore(po + oa + a.ncols, pn);
             acc[0] += (double)pn * lo;
             acc[1] += (double)pn * (double)pn;
             xb = pn * SB[i];

@@ -65,6 +65,7 @@ struct Group {
   int t_suspend;  // > 0 while launches are being captured into a graph
   hipEvent_t* t_ev;
   int* t_kid;
+  int* t_nrep;  // launches between the two events of each timed stage
 };
 
 // The member of a launch that block blk belongs to (start: first block of each member).
@@ -78,10 +79,14 @@ int group_create(const bttb_plan* plans, int count, void* stream, Group** out);
 void group_destroy(Group* g);
 int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s);
 int group_autotune(Group* g, int reps, hipStream_t s, bttb_tune_result* out);
-// skip_first: leave out the first stage (its work done elsewhere).
+// skip_first: leave out the first stage (its work done elsewhere).  fz_rep: the fused forms'
+// table for the timing repeats (all but the last launch of a timed stage): the same reads,
+// with every in-place result sent to scratch, so that the repeats leave the state as one
+// launch does.  Without it a fused product is launched once even while timing repeats are on.
 template <typename T>
 int group_apply_impl(const Group* g, int op, const void* const* in, void* const* out, const void* const* winv,
-                     const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first = 0);
+                     const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first = 0,
+                     const Fuse<T>* fz_rep = nullptr);
 // One launch of stage st over all members at bt threads per block, when the members share one
 // transform size and half form: *L, its blocks, the transform size, the half form and the LDS.
 // BTTB_ESTATE when they do not.

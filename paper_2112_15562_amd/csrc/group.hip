@@ -244,7 +244,8 @@ static auto stage_kernel(int st, bool fused, bool half) -> void (*)(GLaunch<T>) 
 
 template <typename T>
 int group_apply_impl(const Group* g_, int op, const void* const* in, void* const* out, const void* const* winv,
-                     const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first) {
+                     const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first,
+                     const Fuse<T>* fz_rep) {
   Group* g = const_cast<Group*>(g_);  // timing state only
   auto run = [&](int st) -> int {
     if (g->blocks[st] == 0) return BTTB_OK;
@@ -254,11 +255,16 @@ int group_apply_impl(const Group* g_, int op, const void* const* in, void* const
       g->t_kid[tk] = st;
       (void)hipEventRecord(g->t_ev[2 * tk], s);
     }
-    const int reps = tk >= 0 ? g->t_repeat : 1;  // every stage reads one buffer and writes another
+    // Repeats of a timed stage: a plain stage reads one buffer and writes another, so its
+    // repeats change nothing; a fused stage's repeats (all but the last launch) use fz_rep,
+    // which sends the in-place direction update to scratch.  A fused stage without fz_rep
+    // runs once.
+    const int reps = tk >= 0 && (fz == nullptr || fz_rep != nullptr) ? g->t_repeat : 1;
     for (int r = 0; r < reps; ++r) {
+      const Fuse<T>* fzr = r + 1 < reps && fz != nullptr ? fz_rep : fz;
       for (int c = 0; c < g->ncls[st]; ++c) {
         const GClass& C = g->cls[st][c];
-        const GLaunch<T> L = launch_of<T>(g, st, C, fz, in, out, winv, wd);
+        const GLaunch<T> L = launch_of<T>(g, st, C, fzr, in, out, winv, wd);
         void (*kern)(GLaunch<T>) = nullptr;
 #define BTTB_K(NN) kern = stage_kernel<T, NN>(st, fz != nullptr, C.half != 0)
         BTTB_GROUP_SIZES(C.N, BTTB_K)
@@ -267,7 +273,10 @@ int group_apply_impl(const Group* g_, int op, const void* const* in, void* const
         BTTB_LAUNCHED("group stage");
       }
     }
-    if (tk >= 0) (void)hipEventRecord(g->t_ev[2 * tk + 1], s);
+    if (tk >= 0) {
+      (void)hipEventRecord(g->t_ev[2 * tk + 1], s);
+      g->t_nrep[tk] = reps;
+    }
     return BTTB_OK;
   };
   int rc = BTTB_OK;
@@ -323,9 +332,10 @@ template int group_stage_launch<double>(const Group*, int, int, const Fuse<doubl
                                         int*, int*, size_t*);
 
 template int group_apply_impl<float>(const Group*, int, const void* const*, void* const*, const void* const*,
-                                     const void* const*, const Fuse<float>*, hipStream_t, int);
+                                     const void* const*, const Fuse<float>*, hipStream_t, int, const Fuse<float>*);
 template int group_apply_impl<double>(const Group*, int, const void* const*, void* const*, const void* const*,
-                                      const void* const*, const Fuse<double>*, hipStream_t, int);
+                                      const void* const*, const Fuse<double>*, hipStream_t, int,
+                                      const Fuse<double>*);
 
 int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s) {
   const int orm = g->bt_rm, ord = g->bt_rd, oc = g->bt_c, onc = g->nchunk;
@@ -414,8 +424,10 @@ static void group_timing_free(Group* g) {
   }
   delete[] g->t_ev;
   delete[] g->t_kid;
+  delete[] g->t_nrep;
   g->t_ev = nullptr;
   g->t_kid = nullptr;
+  g->t_nrep = nullptr;
   g->t_cap = g->t_used = 0;
 }
 
@@ -433,7 +445,8 @@ int group_timing_enable(Group* g, int max_launches, int repeat) {
   if (max_launches == 0) return BTTB_OK;
   g->t_ev = new (std::nothrow) hipEvent_t[2 * (size_t)max_launches]();
   g->t_kid = new (std::nothrow) int[max_launches];
-  if (!g->t_ev || !g->t_kid) {
+  g->t_nrep = new (std::nothrow) int[max_launches];
+  if (!g->t_ev || !g->t_kid || !g->t_nrep) {
     group_timing_free(g);
     return fail(BTTB_ENOMEM, "group timing: host allocation failed");
   }
@@ -510,9 +523,28 @@ extern "C" int bttb_group_timing_read(bttb_group gg, double* total_ms, int* coun
     float ms = 0.0f;
     BTTB_HIP(hipEventElapsedTime(&ms, g->t_ev[2 * i], g->t_ev[2 * i + 1]));
     total_ms[g->t_kid[i]] += ms;
-    count[g->t_kid[i]] += g->t_repeat;
+    count[g->t_kid[i]] += g->t_nrep[i];
   }
   g->t_used = 0;
+  return BTTB_OK;
+}
+
+extern "C" int bttb_group_timing_list(bttb_group gg, int cap, int* kernel_id, double* ms, int* n) {
+  Group* g = reinterpret_cast<Group*>(gg);
+  if (!g || !kernel_id || !ms || !n || cap < 0) return fail(BTTB_EINVAL, "bttb_group_timing_list: bad argument");
+  int k = 0;
+  for (int i = 0; i < g->t_used; ++i) {
+    BTTB_HIP(hipEventSynchronize(g->t_ev[2 * i + 1]));
+    float t = 0.0f;
+    BTTB_HIP(hipEventElapsedTime(&t, g->t_ev[2 * i], g->t_ev[2 * i + 1]));
+    if (k < cap) {
+      kernel_id[k] = g->t_kid[i];
+      ms[k] = (double)t / g->t_nrep[i];
+      ++k;
+    }
+  }
+  g->t_used = 0;
+  *n = k;
   return BTTB_OK;
 }
 

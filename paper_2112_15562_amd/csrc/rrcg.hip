@@ -6,7 +6,8 @@
 // residual r~ = W_d (A m - d), and the scalars (FP64, device resident).  One outer step:
 //   w, winv from m (eq. WL, eq. W), Gramian scalars                       k_weights
 //   repeat n_inner times:
-//     l = A~^T r~ + alpha (w m - w m_apr) + lambda l_G                    transpose product
+//     l = A~^T r~ + alpha (w m - w a) + lambda l_G                        transpose product
+//         a = m_apr, or m_prev (the model at the start of the last CG step)
 //         l_G on m (RRCG:2-3) or on m~ = w m (steepestascenta/b)          (+ k_grad)
 //     beta = sum ||l||^2 / sum ||l_prev||^2 (0 at a restart)
 //     p = l + beta p,  q = A~ p                                            forward product
@@ -45,6 +46,8 @@ struct Rrcg {
   const void* mapr[2];
   double lo[2], hi[2], alpha0[2], q[2], amin[2], lam[2], eps2;
   int coupled, restart, p_norm, gram_w;
+  int anchor;      // bttb_anchor
+  void* mprev[2];  // caller-owned, BTTB_ANCHOR_PREV only
   rrcg_group grp;  // power-of-two plans: the step runs as a one-inversion group solver
   void* m[2];      // caller-owned
   void* p[2];      // caller-owned
@@ -94,9 +97,9 @@ template <typename T>
 __global__ void __launch_bounds__(RB) k_update(long long n, long long nd, T* m0, T* m1, const T* p0, const T* p1,
                                                const T* w0, const T* w1, T* r0, T* r1, const T* q0, const T* q1,
                                                double* sc, double lam0, double lam1, int coupled, int gram_w,
-                                               Red rd) {
-  update_body<T>(n, nd, m0, m1, p0, p1, w0, w1, r0, r1, q0, q1, sc, lam0, lam1, coupled, gram_w, rd, blockIdx.x,
-                 gridDim.x);
+                                               T* mp0, T* mp1, Red rd) {
+  update_body<T>(n, nd, m0, m1, p0, p1, w0, w1, r0, r1, q0, q1, sc, lam0, lam1, coupled, gram_w, mp0, mp1, rd,
+                 blockIdx.x, gridDim.x);
 }
 
 template <typename T>
@@ -174,8 +177,12 @@ static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
   T** wi = reinterpret_cast<T**>(h->winv);
   T** rt = reinterpret_cast<T**>(h->rt);
   T** qv = reinterpret_cast<T**>(h->qv);
-  const T* ma0 = static_cast<const T*>(h->mapr[0]);
-  const T* ma1 = static_cast<const T*>(h->mapr[1]);
+  // the regulariser's anchor (original space): m_apr, or the model at the start of the last CG step
+  T** mp = reinterpret_cast<T**>(h->mprev);
+  const T* ma0 = h->anchor == BTTB_ANCHOR_PREV ? mp[0] : static_cast<const T*>(h->mapr[0]);
+  const T* ma1 = h->anchor == BTTB_ANCHOR_PREV ? mp[1] : static_cast<const T*>(h->mapr[1]);
+  T* mpw0 = h->anchor == BTTB_ANCHOR_PREV ? mp[0] : nullptr;
+  T* mpw1 = h->anchor == BTTB_ANCHOR_PREV ? mp[1] : nullptr;
   const Red rd = red_of(h);
   {
     for (int i = 0; i < 2; ++i) {
@@ -198,7 +205,8 @@ static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {
     BTTB_LAUNCHED("k_sumsq2");
   }
   hipLaunchKernelGGL(k_update<T>, dim3(RGRID), dim3(RB), 0, s, h->n, h->nd, m[0], m[1], p[0], p[1], w[0], w[1],
-                     rt[0], rt[1], qv[0], qv[1], h->sc, h->lam[0], h->lam[1], h->coupled, h->gram_w, rd);
+                     rt[0], rt[1], qv[0], qv[1], h->sc, h->lam[0], h->lam[1], h->coupled, h->gram_w, mpw0, mpw1,
+                     rd);
   BTTB_LAUNCHED("k_update");
   return BTTB_OK;
 }
@@ -294,6 +302,13 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   }
   if (!(d->eps2 > 0)) return fail(BTTB_EINVAL, "rrcg_create: eps2 must be > 0");
   if (d->p_norm != 1 && d->p_norm != 2) return fail(BTTB_EINVAL, "rrcg_create: p_norm must be 1 or 2");
+  if (d->anchor != BTTB_ANCHOR_APR && d->anchor != BTTB_ANCHOR_PREV)
+    return fail(BTTB_EINVAL, "rrcg_create: anchor must be BTTB_ANCHOR_APR or BTTB_ANCHOR_PREV");
+  if (d->anchor == BTTB_ANCHOR_PREV) {
+    for (int i = 0; i < 2; ++i)
+      if (!d->mprev[i] || !aligned(d->mprev[i], es))
+        return fail(BTTB_EINVAL, "rrcg_create: the previous-iterate anchor needs aligned mprev vectors");
+  }
   Rrcg* h = new (std::nothrow) Rrcg{};
   if (!h) return fail(BTTB_ENOMEM, "rrcg_create: host allocation failed");
   if (P0->fast && P1->fast && P0->Px >= 32 && P0->Py >= 32) {
@@ -317,7 +332,9 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
     h->whard[i] = d->whard[i]; h->mapr[i] = d->mapr[i];
     h->lo[i] = d->lo[i]; h->hi[i] = d->hi[i]; h->alpha0[i] = d->alpha0[i]; h->q[i] = d->q[i];
     h->amin[i] = d->alpha_min[i]; h->lam[i] = d->lambda[i];
+    h->mprev[i] = d->anchor == BTTB_ANCHOR_PREV ? d->mprev[i] : nullptr;
   }
+  h->anchor = d->anchor;
   h->eps2 = d->eps2;
   h->coupled = d->coupled ? 1 : 0;
   h->restart = d->restart ? 1 : 0;
@@ -407,6 +424,7 @@ extern "C" int rrcg_read_scalars(rrcg_handle hh, rrcg_scalars* out, void* stream
   out->k = (int)sc[S_K];
   out->converged = sc[S_CONV] != 0.0;
   out->nonfinite = sc[S_NONFIN] != 0.0;
+  out->similarity = sc[S_SIM];
   return BTTB_OK;
 }
 

@@ -18,7 +18,7 @@ namespace bttb {
 enum {
   S_ALPHA = 0, S_LPREV = 2, S_PHI = 4, S_THR = 6, S_BETA = 7, S_STEP = 9, S_GRAM = 11, S_FROZEN = 12,
   S_K = 14, S_CONV = 15, S_NONFIN = 16, S_G11 = 17, S_G22 = 18, S_G12 = 19, S_L = 20, S_PL = 22,
-  S_PP = 24, S_QQ = 26, S_COUNT = 32
+  S_PP = 24, S_QQ = 26, S_SIM = 28, S_COUNT = 32
 };
 
 // Partial-sum slots: ||l_i||^2; (p_i, l_i) and ||p_i||^2; ||q_i||^2 (q = A~ p); the Gramian
@@ -39,10 +39,13 @@ struct Fuse {
   int gram_w;   // Gramian on w m instead of m
   double lam[2];
   const T* l;     // DIR: gradient of this data set
-  T* p;           // DIR: direction of this data set, updated in place
+  T* p;           // DIR: direction of this data set (the previous one, read)
+  T* pout;        // DIR: where the new direction goes: p itself in the solve; a scratch copy in
+                  //      the timing repeats, which thereby read and write the same values each time
   const T* m[2];  // GRAD: models of both data sets (original space)
   const T* w[2];  // GRAD: weights of both data sets
-  const T* ma;    // GRAD: m_apr of this data set, or NULL for zero
+  const T* ma;    // GRAD: the regulariser's anchor of this data set in the original space (m_apr,
+                  //       or m_prev for the previous-iterate anchor), or NULL for zero
   T* r;           // RUPD: weighted residual r~ of this data set, updated in place
   const T* q;     // RUPD: q = A~ p of this data set
   double* sc;     // scalars

@@ -41,6 +41,7 @@ struct GInv {
   const T* wdepth[2];
   const T* whard[2];
   const T* mapr[2];
+  T* mprev[2];  // previous-iterate anchor: the model at the start of the last CG step (else NULL)
   double lo[2], hi[2], q[2], amin[2], lam[2], eps2;
   int coupled, p_norm, gram_w;
   double* sc;
@@ -76,7 +77,8 @@ __global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gupdate(const GInv<T>
   const GInv<T> v = launch_const(inv + i);
   const int local = blockIdx.x - st.start[i], nb = st.start[i + 1] - st.start[i];
   update_body<T>(v.n, v.nd, v.m[0], v.m[1], v.p[0], v.p[1], v.w[0], v.w[1], v.rt[0], v.rt[1], v.qv[0], v.qv[1],
-                 v.sc, v.lam[0], v.lam[1], v.coupled, v.gram_w, Red{v.pb, v.pbn, v.pbs}, local, nb);
+                 v.sc, v.lam[0], v.lam[1], v.coupled, v.gram_w, v.mprev[0], v.mprev[1], Red{v.pb, v.pbn, v.pbs},
+                 local, nb);
 }
 
 // The update of a CG step that another step follows, in one launch: the next step's first
@@ -104,7 +106,8 @@ __global__ void __launch_bounds__(eb_threads(sizeof(T))) k_gupdate_t1(const GInv
   const GInv<T> v = launch_const(inv + i);
   const int local = b - st.start[i], nb = st.start[i + 1] - st.start[i];
   update_body<T>(v.n, 0, v.m[0], v.m[1], v.p[0], v.p[1], v.w[0], v.w[1], v.rt[0], v.rt[1], v.qv[0], v.qv[1], v.sc,
-                 v.lam[0], v.lam[1], v.coupled, v.gram_w, Red{v.pb, v.pbn, v.pbs}, local, nb, false);
+                 v.lam[0], v.lam[1], v.coupled, v.gram_w, v.mprev[0], v.mprev[1], Red{v.pb, v.pbn, v.pbs}, local,
+                 nb, false);
 }
 
 template <typename T>
@@ -139,11 +142,14 @@ struct RrcgGroup {
   void* inv;              // dev GInv<T>[count]
   GStart est;             // elementwise blocks
   void** ptrs;            // dev pointer arrays, PA_COUNT x (2 count)
-  void* fz[2];            // dev Fuse<T>[2 count]: [0] plain step, [1] restart step
+  void* fz[4];            // dev Fuse<T>[2 count]: [0] plain step, [1] restart step; [2], [3] the same
+                          // for timing repeats (new direction into a scratch vector, no recording)
   double* sc;             // [count][S_COUNT]
   double* pb;             // partials of all inversions
   int* pbn;               // [count][PB_NSLOT]
-  void* vec[GINV_MAX][7];  // owned: l0, l1, w0, w1, wi0, wi1, qv (qv holds both data sets)
+  void* vec[GINV_MAX][8];  // owned: l0, l1, w0, w1, wi0, wi1, qv (both data sets), timing scratch
+                           // (both data sets)
+  void* mprev[GINV_MAX][2];  // caller-owned, previous-iterate anchor only
   long long n[GINV_MAX], nd[GINV_MAX];
   double alpha0[GINV_MAX][2];
   hipStream_t cap;
@@ -204,12 +210,13 @@ static int g_weights(RrcgGroup* h, hipStream_t s) {
 template <typename T>
 static int g_inner(RrcgGroup* h, int j, int n_inner, hipStream_t s) {
   const Fuse<T>* fz = static_cast<const Fuse<T>*>(h->fz[j == 0 ? 1 : 0]);
+  const Fuse<T>* fz_rep = static_cast<const Fuse<T>*>(h->fz[j == 0 ? 3 : 2]);  // timing repeats only
   const bool t1_done = h->fuse_t1 && j > 0, fuse_next = h->fuse_t1 && j + 1 < n_inner;
   int rc = group_apply_impl<T>(h->grp, BTTB_OP_ADJOINT, pa(h, PA_RT), const_cast<void* const*>(pa(h, PA_L)),
-                               pa(h, PA_WI), pa(h, PA_WD), fz, s, t1_done ? 1 : 0);
+                               pa(h, PA_WI), pa(h, PA_WD), fz, s, t1_done ? 1 : 0, fz_rep);
   if (rc) return rc;
   rc = group_apply_impl<T>(h->grp, BTTB_OP_FORWARD, pa(h, PA_P), const_cast<void* const*>(pa(h, PA_QV)),
-                           pa(h, PA_WI), pa(h, PA_WD), fz, s);
+                           pa(h, PA_WI), pa(h, PA_WD), fz, s, 0, fz_rep);
   if (rc) return rc;
   const GInv<T>* inv = static_cast<const GInv<T>*>(h->inv);
   if (!fuse_next) {
@@ -313,8 +320,7 @@ static void g_free(RrcgGroup* h) {
     for (void* v : h->vec[i]) dfree(v);
   dfree(h->inv);
   dfree(h->ptrs);
-  dfree(h->fz[0]);
-  dfree(h->fz[1]);
+  for (void* f : h->fz) dfree(f);
   dfree(h->sc);
   dfree(h->pb);
   dfree(h->pbn);
@@ -341,6 +347,13 @@ static int check_desc(const rrcg_desc* d, size_t es) {
   }
   if (!(d->eps2 > 0)) return fail(BTTB_EINVAL, "rrcg_group_create: eps2 must be > 0");
   if (d->p_norm != 1 && d->p_norm != 2) return fail(BTTB_EINVAL, "rrcg_group_create: p_norm must be 1 or 2");
+  if (d->anchor != BTTB_ANCHOR_APR && d->anchor != BTTB_ANCHOR_PREV)
+    return fail(BTTB_EINVAL, "rrcg_group_create: anchor must be BTTB_ANCHOR_APR or BTTB_ANCHOR_PREV");
+  if (d->anchor == BTTB_ANCHOR_PREV) {
+    for (int i = 0; i < 2; ++i)
+      if (!d->mprev[i] || !aligned(d->mprev[i], es))
+        return fail(BTTB_EINVAL, "rrcg_group_create: the previous-iterate anchor needs aligned mprev vectors");
+  }
   return BTTB_OK;
 }
 
@@ -348,7 +361,7 @@ template <typename T>
 static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
   const int n2 = 2 * h->count;
   GInv<T> inv[GINV_MAX];
-  Fuse<T> fz[2][GMAX];
+  Fuse<T> fz[4][GMAX];
   const void* ptr[PA_COUNT][GMAX];
   long long pb_off = 0;
   std::vector<long long> offs(h->count);
@@ -370,6 +383,8 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
     v.n = h->n[i];
     v.nd = h->nd[i];
     T* qv = static_cast<T*>(h->vec[i][6]);
+    T* pscratch = static_cast<T*>(h->vec[i][7]);
+    const bool prev = d.anchor == BTTB_ANCHOR_PREV;
     for (int k = 0; k < 2; ++k) {
       v.m[k] = static_cast<T*>(d.m[k]);
       v.p[k] = static_cast<T*>(d.p[k]);
@@ -383,6 +398,7 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
       v.wdepth[k] = static_cast<const T*>(d.wdepth[k]);
       v.whard[k] = static_cast<const T*>(d.whard[k]);
       v.mapr[k] = static_cast<const T*>(d.mapr[k]);
+      v.mprev[k] = prev ? static_cast<T*>(d.mprev[k]) : nullptr;
       v.lo[k] = d.lo[k];
       v.hi[k] = d.hi[k];
       v.q[k] = d.q[k];
@@ -405,23 +421,25 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
       ptr[PA_P][mi] = v.p[k];
       ptr[PA_QV][mi] = v.qv[k];
       ptr[PA_M][mi] = v.m[k];
-      for (int r = 0; r < 2; ++r) {
+      for (int r = 0; r < 4; ++r) {
         Fuse<T>& f = fz[r][mi];
+        const bool rep = r >= 2;  // a timing repeat: same reads, the new direction into scratch
         f = Fuse<T>{};
         f.self = k;
-        f.lead = k == 0;
-        f.restart = r == 1 && d.restart ? 1 : 0;
+        f.lead = k == 0 && !rep;
+        f.restart = (r & 1) == 1 && d.restart ? 1 : 0;
         f.coupled = v.coupled;
         f.gram_w = v.gram_w;
         f.lam[0] = d.lambda[0];
         f.lam[1] = d.lambda[1];
         f.l = v.l[k];
         f.p = v.p[k];
+        f.pout = rep ? pscratch + k * h->n[i] : v.p[k];
         f.m[0] = v.m[0];
         f.m[1] = v.m[1];
         f.w[0] = v.w[0];
         f.w[1] = v.w[1];
-        f.ma = v.mapr[k];
+        f.ma = prev ? v.mprev[k] : v.mapr[k];  // the anchor of RRCG:4 in the original space
         f.r = v.rt[k];
         f.q = v.qv[k];
         f.sc = v.sc;
@@ -442,7 +460,7 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
                                                          &lds) == BTTB_OK;
   }
   BTTB_HIP(hipMemcpyAsync(h->inv, inv, sizeof(GInv<T>) * h->count, hipMemcpyHostToDevice, s));
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < 4; ++r)
     BTTB_HIP(hipMemcpyAsync(h->fz[r], fz[r], sizeof(Fuse<T>) * n2, hipMemcpyHostToDevice, s));
   for (int k = 0; k < PA_COUNT; ++k)
     BTTB_HIP(hipMemcpyAsync(h->ptrs + (size_t)k * n2, ptr[k], sizeof(void*) * n2, hipMemcpyHostToDevice, s));
@@ -514,11 +532,13 @@ extern "C" int rrcg_group_create(const rrcg_desc* descs, int count, void* stream
     const size_t nb = (size_t)h->n[i] * es;
     for (int k = 0; k < 6 && ok; ++k) ok = hipMalloc(&h->vec[i][k], nb) == hipSuccess;
     ok = ok && hipMalloc(&h->vec[i][6], 2 * (size_t)h->nd[i] * es) == hipSuccess;
+    ok = ok && hipMalloc(&h->vec[i][7], 2 * nb) == hipSuccess;
+    for (int k = 0; k < 2; ++k) h->mprev[i][k] = descs[i].anchor == BTTB_ANCHOR_PREV ? descs[i].mprev[k] : nullptr;
   }
   const size_t fzb = (precision == BTTB_F64 ? sizeof(Fuse<double>) : sizeof(Fuse<float>)) * 2 * count;
   const size_t invb = (precision == BTTB_F64 ? sizeof(GInv<double>) : sizeof(GInv<float>)) * count;
-  ok = ok && hipMalloc(&h->inv, invb) == hipSuccess && hipMalloc(&h->fz[0], fzb) == hipSuccess &&
-       hipMalloc(&h->fz[1], fzb) == hipSuccess &&
+  for (int r = 0; r < 4 && ok; ++r) ok = hipMalloc(&h->fz[r], fzb) == hipSuccess;
+  ok = ok && hipMalloc(&h->inv, invb) == hipSuccess &&
        hipMalloc((void**)&h->ptrs, sizeof(void*) * PA_COUNT * 2 * count) == hipSuccess &&
        hipMalloc((void**)&h->sc, sizeof(double) * S_COUNT * count) == hipSuccess &&
        hipMalloc((void**)&h->pbn, sizeof(int) * PB_NSLOT * count) == hipSuccess;
@@ -608,6 +628,7 @@ static int g_autotune(RrcgGroup* h, int reps, hipStream_t s, bttb_tune_result* o
     segs.push_back({const_cast<void*>(st[(size_t)PA_M * 2 * h->count + mi]), (size_t)h->n[i] * es});
     segs.push_back({const_cast<void*>(st[(size_t)PA_P * 2 * h->count + mi]), (size_t)h->n[i] * es});
     segs.push_back({const_cast<void*>(st[(size_t)PA_RT * 2 * h->count + mi]), (size_t)h->nd[i] * es});
+    if (h->mprev[i][mi % 2]) segs.push_back({h->mprev[i][mi % 2], (size_t)h->n[i] * es});
   }
   size_t total = 0;
   for (const Seg& g : segs) total += (g.bytes + 255) & ~(size_t)255;
@@ -752,6 +773,7 @@ extern "C" int rrcg_group_read_scalars(rrcg_group hh, int index, rrcg_scalars* o
   out->k = (int)sc[S_K];
   out->converged = sc[S_CONV] != 0.0;
   out->nonfinite = sc[S_NONFIN] != 0.0;
+  out->similarity = sc[S_SIM];
   return BTTB_OK;
 }
 

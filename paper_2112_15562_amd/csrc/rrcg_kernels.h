@@ -88,7 +88,8 @@ __device__ __forceinline__ void weights_body(long long n, const T* m0, const T* 
   block_partials<3>(v, rd.pb, rd.pbn, rd.pbs, PB_G11, bid, nb);
 }
 
-// l = A~^T r~ (already in l) + alpha (w m - w m_apr) + lambda l_G;  partials of ||l_i||^2.
+// l = A~^T r~ (already in l) + alpha (w m - w ma) + lambda l_G, ma the anchor in the original
+// space (m_apr or m_prev; NULL: zero);  partials of ||l_i||^2.
 template <typename T>
 __device__ __forceinline__ void grad_body(long long n, T* l0, T* l1, const T* m0, const T* m1, const T* w0,
                                           const T* w1, const T* ma0, const T* ma1, double* sc, double lam0,
@@ -150,7 +151,8 @@ __device__ __forceinline__ void sumsq2_body(long long n, const T* a0, const T* a
 }
 
 // s from the partials (RRCG:6); m <- m - s p / w (i.e. m~ <- m~ - s p, then m = m~ / w);
-// r~ <- r~ - s q (for nd > 0); Gramian partials of the new m (on m or on w m).  Block 0
+// r~ <- r~ - s q (for nd > 0); Gramian partials of the new m (on m or on w m); with the
+// previous-iterate anchor (mp0 non-NULL) the model before the update into mp.  Block 0
 // records the step length unless `record` is off (another part of the launch records it).
 // Every load of an iteration goes out before its first store: vector memory operations
 // complete in issue order, so a load issued after a store could only be waited for together
@@ -159,7 +161,7 @@ template <typename T>
 __device__ __forceinline__ void update_body(long long n, long long nd, T* m0, T* m1, const T* p0, const T* p1,
                                             const T* w0, const T* w1, T* r0, T* r1, const T* q0, const T* q1,
                                             double* sc, double lam0, double lam1, int coupled, int gram_w,
-                                            Red rd, int bid, int nb, bool record = true) {
+                                            T* mp0, T* mp1, Red rd, int bid, int nb, bool record = true) {
   constexpr int U = EW_UNROLL;
   const int nt = blockDim.x;
   double st[2];
@@ -200,6 +202,10 @@ __device__ __forceinline__ void update_body(long long n, long long nd, T* m0, T*
         const double W0 = V0[u], W1 = V1[u];
         const T a = (T)((W0 * (double)M0[u] - s0 * (double)P0[u]) / W0);
         const T b = (T)((W1 * (double)M1[u] - s1 * (double)P1[u]) / W1);
+        if (mp0) {
+          gstore(mp0 + j, M0[u]);
+          gstore(mp1 + j, M1[u]);
+        }
         gstore(m0 + j, a);
         gstore(m1 + j, b);
         const double u0 = gram_w ? W0 * (double)a : (double)a, u1 = gram_w ? W1 * (double)b : (double)b;
@@ -280,6 +286,8 @@ __device__ __forceinline__ void fin_outer_body(double* sc, Red rd, double q0, do
     gstore(sc + S_PHI, f0);
     gstore(sc + S_PHI + 1, f1);
     gstore(sc + S_GRAM, g11 * g22 - g12 * g12);
+    // the cosine of the two models, |(m1, m2)| / (||m1|| ||m2||), 0 when a model is zero
+    gstore(sc + S_SIM, (g11 > 0.0 && g22 > 0.0) ? fabs(g12) / sqrt(g11 * g22) : 0.0);
     if (!isfinite(f0) || !isfinite(f1) || !isfinite(g11) || !isfinite(g22)) gstore(sc + S_NONFIN, 1.0);
     if (advance) {
       const double thr = gload(sc + S_THR);

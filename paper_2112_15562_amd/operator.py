@@ -276,6 +276,15 @@ class Group:
         L.check(L.lib().bttb_group_timing_read(self.handle, tot, cnt), "bttb_group_timing_read")
         return {L.KERNEL_NAMES[k]: (tot[k], cnt[k]) for k in range(L.NKERNELS)}
 
+    def timing_list(self, cap: int = 4096) -> list:
+        """[(kernel name, ms of one launch)] of the timed launches since the last read, in
+        launch order; synchronises."""
+        kid = (C.c_int * cap)()
+        ms = (C.c_double * cap)()
+        n = C.c_int()
+        L.check(L.lib().bttb_group_timing_list(self.handle, int(cap), kid, ms, C.byref(n)), "bttb_group_timing_list")
+        return [(L.KERNEL_NAMES[kid[k]], ms[k]) for k in range(n.value)]
+
     def autotune(self, reps: int = 5) -> dict:
         """Tune the threads per block of each stage and the layer chunks by timing."""
         r = L.TuneResult()
@@ -290,13 +299,28 @@ class Group:
                                          C.c_void_p(_stream(self.device))), "bttb_group_apply")
 
     def apply(self, op: int, xs: Sequence[torch.Tensor], winv=None, wd=None, outs=None):
+        """Products of every member; xs, outs (optional) and the optional diagonals winv (model
+        shape) and wd (data shape) hold one tensor per member (winv and wd entries may be None).
+        Every tensor is checked here: the library receives bare device pointers."""
         n = len(self.ops)
-        if len(xs) != n:
-            raise ValueError("one input per member")
+        if op not in (L.BTTB_OP_FORWARD, L.BTTB_OP_ADJOINT):
+            raise ValueError("op must be BTTB_OP_FORWARD or BTTB_OP_ADJOINT")
         fwd = op == L.BTTB_OP_FORWARD
-        for o, x in zip(self.ops, xs):
-            if o._check_vec(x, o.model_shape if fwd else o.data_shape, "input") != 1:
-                raise ValueError("group products take one vector per member")
+
+        def check(vs, what, shape_of, nullable):
+            if vs is None:
+                return
+            if len(vs) != n:
+                raise ValueError(f"{what}: one tensor per member ({n}), got {len(vs)}")
+            for o, v in zip(self.ops, vs):
+                if v is None and nullable:
+                    continue
+                if v is None or o._check_vec(v, shape_of(o), what) != 1 or v.dim() != len(shape_of(o)):
+                    raise ValueError(f"{what}: one {shape_of(o)} tensor per member")
+        check(xs, "input", (lambda o: o.model_shape) if fwd else (lambda o: o.data_shape), False)
+        check(outs, "out", (lambda o: o.data_shape) if fwd else (lambda o: o.model_shape), False)
+        check(winv, "winv", lambda o: o.model_shape, True)
+        check(wd, "wd", lambda o: o.data_shape, True)
         if outs is None:
             outs = [torch.empty(o.data_shape if fwd else o.model_shape, dtype=self.dtype, device=self.device)
                     for o in self.ops]

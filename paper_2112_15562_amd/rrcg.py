@@ -26,8 +26,10 @@ class _Inversion:
 
     def __init__(self, ops: Sequence[Operator], dobs, wd, wdepth, whard=None, mapr=None, *,
                  lo=-math.inf, hi=math.inf, alpha0=20000.0, q=0.95, alpha_min=0.0, lam=0.0,
-                 eps2=1e-9, coupled=True, restart=True, p_norm=1, gramian="original", m0=None,
+                 eps2=1e-9, coupled=True, restart=True, p_norm=1, gramian="original", anchor="apr", m0=None,
                  use_graph=True):
+        if anchor not in ("apr", "prev"):
+            raise ValueError("anchor must be 'apr' or 'prev'")
         self.ops = tuple(ops)
         o = self.ops[0]
         self.dtype, self.device = o.dtype, o.device
@@ -45,6 +47,8 @@ class _Inversion:
         else:
             self.m = [torch.zeros(shape, dtype=self.dtype, device=self.device) for _ in range(2)]
         self.p = [torch.zeros(shape, dtype=self.dtype, device=self.device) for _ in range(2)]
+        # previous-iterate anchor: the model at the start of the last CG step, m_{-1} = m_0
+        self.mprev = [x.clone() for x in self.m] if anchor == "prev" else None
         self.resid = [torch.empty(o.data_shape, dtype=self.dtype, device=self.device) for _ in range(2)]
         for t in self.dobs + self.wd + self.resid:
             if tuple(t.shape) != tuple(o.data_shape):
@@ -75,13 +79,16 @@ class _Inversion:
         d.p_norm = int(p_norm)
         d.gramian_weighted = 1 if gramian == "weighted" else 0
         d.use_graph = int(bool(use_graph))
+        d.anchor = L.BTTB_ANCHOR_PREV if anchor == "prev" else L.BTTB_ANCHOR_APR
+        for i in range(2):
+            d.mprev[i] = self.mprev[i].data_ptr() if self.mprev is not None else None
         self.desc = d
 
 
 def _scalars_dict(s: L.RrcgScalars) -> dict:
     return dict(alpha=list(s.alpha), L_prev=list(s.L_prev), phi=list(s.phi), threshold=s.threshold,
                 beta=list(s.beta), step=list(s.step), gramian=s.gramian, frozen=[bool(x) for x in s.frozen],
-                k=s.k, converged=bool(s.converged), nonfinite=bool(s.nonfinite))
+                k=s.k, converged=bool(s.converged), nonfinite=bool(s.nonfinite), similarity=s.similarity)
 
 
 def _apply_scalars(s: L.RrcgScalars, kw: dict) -> None:
@@ -94,6 +101,8 @@ def _apply_scalars(s: L.RrcgScalars, kw: dict) -> None:
             setattr(s, k, int(v))
         elif k == "gramian":
             s.gramian = float(v)
+        elif k == "similarity":
+            pass  # computed on the device from the models
         else:
             raise KeyError(k)
 
@@ -104,6 +113,8 @@ class JointRRCG:
     ops: (gravity operator, magnetic operator) with the same grids and dtype.
     dobs, wd: [sx][sy] tensors per data set (wd = 1/sigma); wdepth (and optional whard,
     mapr): [nz][nx][ny].  m0: starting models (default m_apr, or zeros).
+    anchor: "apr" (alpha (m~ - W m_apr), the gradient of the objective) or "prev" (RRCG:4 as
+    printed, alpha (m~ - W m_prev), m_prev the model at the start of the last CG step).
     """
 
     def __init__(self, ops: Sequence[Operator], dobs, wd, wdepth, whard=None, mapr=None, **kw):
@@ -111,7 +122,7 @@ class JointRRCG:
         inv = self._inv
         self.ops, self.dtype, self.device = inv.ops, inv.dtype, inv.device
         self.dobs, self.wd, self.wdepth, self.whard, self.mapr = inv.dobs, inv.wd, inv.wdepth, inv.whard, inv.mapr
-        self.m, self.p, self.resid = inv.m, inv.p, inv.resid
+        self.m, self.p, self.resid, self.mprev = inv.m, inv.p, inv.resid, inv.mprev
         self._h = C.c_void_p()
         L.check(L.lib().rrcg_create(C.byref(inv.desc), C.c_void_p(self._stream()), C.byref(self._h)),
                 "rrcg_create")
@@ -173,12 +184,17 @@ class JointRRCG:
         return self.m
 
     def state_dict(self) -> dict:
-        return dict(m=[x.clone() for x in self.m], p=[x.clone() for x in self.p], scalars=self.scalars())
+        st = dict(m=[x.clone() for x in self.m], p=[x.clone() for x in self.p], scalars=self.scalars())
+        if self.mprev is not None:
+            st["mprev"] = [x.clone() for x in self.mprev]
+        return st
 
     def load_state_dict(self, st: dict) -> None:
         for i in range(2):
             self.m[i].copy_(st["m"][i])
             self.p[i].copy_(st["p"][i])
+            if self.mprev is not None:
+                self.mprev[i].copy_(st["mprev"][i])
         sc = dict(st["scalars"])
         sc.pop("threshold", None)
         self.set_scalars(**sc)

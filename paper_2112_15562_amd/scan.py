@@ -8,8 +8,9 @@ phase for all of them.
 
 Readings (the paper shows similarity only as cross-correlation plots):
 * similarity is |(m1, m2)| / (||m1|| ||m2||), the cosine in the original space that the
-  Gramian drives to one (S_G = ||m1||^2 ||m2||^2 (1 - cos^2)); a pair qualifies when it
-  reaches ``sim_min``;
+  Gramian drives to one (S_G = ||m1||^2 ||m2||^2 (1 - cos^2)), computed on the device with the
+  Gramian after every outer step (the solver's scalars); a pair qualifies when it reaches
+  ``sim_min``;
 * a run fits when it met both chi^2 tests (eq. chi2) within ``n_outer`` outer steps; a run
   stopped by the limit is rejected, as the paper rejects its non-converged run with the
   largest pair;
@@ -18,7 +19,6 @@ Readings (the paper shows similarity only as cross-correlation plots):
 """
 from __future__ import annotations
 
-import math
 from typing import Optional, Sequence
 
 import torch
@@ -27,15 +27,6 @@ from .operator import Operator
 from .rrcg import JointRRCGGroup
 
 MAX_GROUP = 32  # inversions per group solver
-
-
-def similarity(m1: torch.Tensor, m2: torch.Tensor) -> float:
-    """|(m1, m2)| / (||m1|| ||m2||) with FP64 sums on the device; 0 when a model is zero."""
-    a, b = m1.reshape(-1).double(), m2.reshape(-1).double()
-    n1, n2, c = torch.dot(a, a).item(), torch.dot(b, b).item(), torch.dot(a, b).item()
-    if n1 == 0.0 or n2 == 0.0:
-        return 0.0
-    return abs(c) / math.sqrt(n1 * n2)
 
 
 def choose(records: Sequence[dict], sim_min: float) -> Optional[int]:
@@ -82,7 +73,7 @@ def lambda_scan(kernels, data_shape, dobs, wd, wdepth, lams, *, n_outer: int, n_
                     break
             for i, lam in enumerate(part):
                 sc, m = done[i] if done[i] is not None else (grp.scalars(i), [t.clone() for t in grp.m(i)])
-                records.append(dict(lam=lam, similarity=similarity(m[0], m[1]), converged=bool(sc["converged"]),
+                records.append(dict(lam=lam, similarity=sc["similarity"], converged=bool(sc["converged"]),
                                     k=int(sc["k"]), phi=list(sc["phi"]), m=m))
         finally:
             grp.close()

@@ -76,8 +76,36 @@ def test_argument_checks_fail_before_any_gpu_work(lib):
     assert L.rrcg_destroy(None) == lib.BTTB_OK
 
 
+def _c_layouts(structs):
+    """sizeof and every field's offsetof of the header's structs, as gcc lays them out."""
+    import json
+    import subprocess
+    import tempfile
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bttb.h"', 'int main(void) {', 'printf("{");']
+    first = True
+    for cname, fields in structs:
+        for f in ["__size__"] + fields:
+            expr = f"sizeof({cname})" if f == "__size__" else f"offsetof({cname}, {f})"
+            sep = "" if first else ","
+            lines.append(f'printf("{sep}\\"{cname}.{f}\\": %zu", (size_t)({expr}));')
+            first = False
+    lines += ['printf("}\\n");', 'return 0;', '}']
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "probe.c"), os.path.join(d, "probe")
+        with open(src, "w") as fh:
+            fh.write("\n".join(lines))
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        return json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
+
+
 def test_struct_layouts_match_header(lib):
-    # sizes of the ABI structs as laid out by the C compiler on x86-64
-    assert C.sizeof(lib.Geometry) == 5 * 4 + 4 + 8 * 8 + 2 * 4
-    assert lib.Geometry.ox.offset == 88 and lib.Geometry.oy.offset == 92
-    assert C.sizeof(lib.RrcgScalars) == 8 * 2 * 3 + 8 + 8 * 2 * 2 + 8 + 4 * 2 + 4 * 3 + 4
+    # every ctypes mirror has the size and field offsets the C compiler gives the header
+    pairs = [("bttb_geometry", lib.Geometry), ("bttb_plan_desc", lib.PlanDesc), ("bttb_group_desc", lib.GroupDesc),
+             ("bttb_tune_result", lib.TuneResult), ("rrcg_desc", lib.RrcgDesc), ("rrcg_scalars", lib.RrcgScalars)]
+    cname = {"lambda_": "lambda"}
+    structs = [(c, [cname.get(f, f) for f, _ in py._fields_]) for c, py in pairs]
+    got = _c_layouts(structs)
+    for c, py in pairs:
+        assert C.sizeof(py) == got[f"{c}.__size__"], c
+        for f, _ in py._fields_:
+            assert getattr(py, f).offset == got[f"{c}.{cname.get(f, f)}"], (c, f)

@@ -5,6 +5,7 @@ import pytest
 import torch
 
 import synth
+from oracle import bttb as obttb
 from oracle import prism as oprism
 
 pytestmark = pytest.mark.gpu
@@ -61,6 +62,17 @@ def test_batched_fp32_backward_vs_fp64_finite_differences(pk):
         g64 = m64.grad
         rel = (torch.linalg.vector_norm(g32 - g64) / torch.linalg.vector_norm(g64)).item()
         assert rel <= 1e-5, rel
+        # the FP32 batched gradient of two batch members against the oracle's FP64 A^T u
+        # (FFT2 products on the host), from the oracle's own kernel array
+        og = oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl,
+                             g.field)
+        To = obttb.kernel_array((oprism.GRAVITY, oprism.MAGNETIC)[i], og)
+        for b in (0, B - 1):
+            ref = obttb.fft_rmatvec(To, u_np[b], g.sx, g.sy, workers=8)
+            got = g32[b].cpu().numpy()
+            e = float(np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel()))
+            print(f"operator {i} member {b}: FP32 gradient vs oracle rel err {e:.2e}", flush=True)
+            assert e <= 1e-5
         # central differences of f(m) = <u, A m> (FP64) along 32 unit directions of one model;
         # f is linear, so a moderate step leaves only rounding
         h = 1e-3

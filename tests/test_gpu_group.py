@@ -165,3 +165,41 @@ def test_group_rejects_bad_members_and_shapes(pk):
     grp.close()
     for op in (radix3, a, b):
         op.close()
+
+
+def test_group_apply_checks_every_vector(pk):
+    # the library gets bare device pointers per member, so the binding checks every list:
+    # one tensor per member, of that member's shape, dtype and device, contiguous
+    ops, grp = make(pk, torch.float64, [0, 2])
+    dev = "cuda"
+    x = [torch.rand(o.model_shape, dtype=torch.float64, device=dev) for o in ops]
+    r = [torch.randn(o.data_shape, dtype=torch.float64, device=dev) for o in ops]
+    wi = [torch.rand(o.model_shape, dtype=torch.float64, device=dev) + 0.5 for o in ops]
+    wd = [torch.rand(o.data_shape, dtype=torch.float64, device=dev) + 0.5 for o in ops]
+    F, A = 0, 1
+    bad = [
+        dict(op=F, xs=x[:1]),                                            # short input list
+        dict(op=F, xs=x, outs=[torch.empty(ops[0].data_shape, dtype=torch.float64, device=dev)]),
+        dict(op=F, xs=x, outs=[torch.empty(o.model_shape, dtype=torch.float64, device=dev) for o in ops]),
+        dict(op=A, xs=r, outs=[torch.empty(o.data_shape, dtype=torch.float64, device=dev) for o in ops]),
+        dict(op=F, xs=x, winv=wi[:1]),
+        dict(op=F, xs=x, winv=[wd[0], wi[1]]),                           # wrong shape
+        dict(op=F, xs=x, wd=wi),
+        dict(op=F, xs=x, wd=[w.float() for w in wd]),                    # wrong dtype
+        dict(op=F, xs=x, winv=[wi[0].cpu(), wi[1]]),                     # wrong device
+        dict(op=F, xs=[x[0], x[1].transpose(1, 2)]),                     # not contiguous / shape
+        dict(op=F, xs=[x[0].unsqueeze(0), x[1]]),                        # a batch, not one vector
+        dict(op=A, xs=r, outs=[None, None]),
+        dict(op=7, xs=x),
+    ]
+    for kw in bad:
+        with pytest.raises((ValueError, TypeError)):
+            grp.apply(**kw)
+    # entries of the diagonals may be None (identity for that member)
+    ys = grp.apply(F, x, winv=[None, wi[1]], wd=[wd[0], None])
+    ref0 = ops[0].matvec(x[0], wd=wd[0])
+    ref1 = ops[1].matvec(x[1], winv=wi[1])
+    assert rel(host(ys[0]), host(ref0)) <= 1e-12 and rel(host(ys[1]), host(ref1)) <= 1e-12
+    grp.close()
+    for op in ops:
+        op.close()

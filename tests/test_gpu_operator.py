@@ -46,6 +46,10 @@ TINY = synth.Grid(1, 1, 1, 1, 1, 50.0, 50.0, 50.0)
 ODD = synth.Grid(3, 5, 2, 7, 2, 30.0, 20.0, 10.0, h=2.0, top=5.0, incl=40.0, decl=-30.0)
 # a padded model domain: 6x5 stations over the interior of 10x9x3 prisms, offset (2, 3)
 PADDED = synth.Grid(6, 5, 10, 9, 3, 40.0, 30.0, 25.0, ox=2, oy=3)
+# transforms with radix-5 (and 3) passes: 39 -> 40 = 8 5, 119 -> 120 = 8 3 5, 199 -> 200 = 8 5 5
+R5 = synth.Grid(20, 20, 20, 20, 4, 40.0, 40.0, 25.0)
+R35 = synth.Grid(60, 60, 60, 60, 5, 40.0, 40.0, 25.0, decl=10.0)
+R55 = synth.Grid(100, 100, 100, 100, 8, 40.0, 40.0, 25.0)
 
 
 # ------------------------------------------------------------------------------------
@@ -92,7 +96,7 @@ def test_prism_kernels_match_oracle(pk, g):
 # ------------------------------------------------------------------------------------
 # products vs the dense oracle (small grids, GPU-generated kernels end to end)
 # ------------------------------------------------------------------------------------
-@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, TINY, PADDED])
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, TINY, PADDED, R5])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_products_match_dense_oracle(pk, g, dtype):
     og = ogeom(g)
@@ -174,6 +178,19 @@ def _fft_case(pk, g, models, dtype, tol):
 def test_mid_grid_matches_fft_oracle(pk, dtype):
     g = synth.MID
     _fft_case(pk, g, synth.random_boxes(g), dtype, F64_TOL if dtype == torch.float64 else F32_TOL)
+
+
+@pytest.mark.parametrize("g", [R5, R35, R55], ids=["P40", "P120", "P200"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_radix5_transforms_match_fft_oracle(pk, g, dtype):
+    # 5-smooth transform sizes with radix-5 passes in every product kernel (rows and columns)
+    P = {R5: 40, R35: 120, R55: 200}[g]
+    T = obttb.kernel_array(pk.GRAVITY, ogeom(g))
+    op = pk.Operator(dev(T), (g.sx, g.sy), dtype=dtype)
+    assert op.info()["Px"] == P and op.info()["Py"] == P
+    op.close()
+    _fft_case(pk, g, synth.random_boxes(g, seed_workload=2, index=P), dtype,
+              F64_TOL if dtype == torch.float64 else F32_TOL)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

@@ -1,5 +1,6 @@
 """GPU joint RRCG through the C ABI vs the FP64 oracle (run on an MI355X)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -70,10 +71,13 @@ def gpu_solver(pk, g, T, data, prm, dtype, state=None, use_graph=True):
     m0 = state.m if state is not None else None
     s = pk.JointRRCG(ops, data.dobs, data.wd, data.wdepth, lo=prm.lo, hi=prm.hi, alpha0=prm.alpha0, q=prm.q,
                      alpha_min=prm.alpha_min, lam=prm.lam, eps2=prm.eps2, coupled=prm.coupled,
-                     restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian, m0=m0, use_graph=use_graph)
+                     restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian, anchor=prm.anchor, m0=m0,
+                     use_graph=use_graph)
     if state is not None:
         for i in range(2):
             s.p[i].copy_(torch.as_tensor(state.p[i], dtype=dtype, device="cuda"))
+            if prm.anchor == "prev":
+                s.mprev[i].copy_(torch.as_tensor(state.m_prev[i], dtype=dtype, device="cuda"))
         s.set_scalars(alpha=state.alpha, L_prev=state.L_prev, frozen=state.frozen, k=state.k)
         s.refresh()
     return s, ops
@@ -86,6 +90,8 @@ VARIANTS = [
     dict(n_inner=4, restart=True, coupled=False, lam=(0.0, 0.0)),   # stand-alone
     dict(n_inner=4, restart=True, p_norm=2, alpha_min=(500.0, 500.0)),  # joint minimum length
     dict(n_inner=3, restart=False, gramian="weighted", lam=(1e-3, 1e-1)),
+    dict(n_inner=1, restart=False, anchor="prev"),        # RRCG:4 as printed, single loop
+    dict(n_inner=4, restart=True, anchor="prev", gramian="weighted", lam=(1e-3, 1e-1)),
 ]
 
 
@@ -110,6 +116,8 @@ def test_single_outer_step_parity_fp64(pk, var, g):
         assert rel(host(s.m[i]), ref.m[i]) <= 1e-12
         # p is the CG direction (an intermediate, O(100) in size), not a result
         assert rel(host(s.p[i]), ref.p[i]) <= 1e-11
+        if prm.anchor == "prev":
+            assert rel(host(s.mprev[i]), ref.m_prev[i]) <= 1e-12
         assert sc["alpha"][i] == pytest.approx(ref.alpha[i], rel=1e-15)
         assert sc["phi"][i] == pytest.approx(rec["phi"][i], rel=1e-12)
         assert sc["L_prev"][i] == pytest.approx(ref.L_prev[i], rel=1e-12)
@@ -137,7 +145,7 @@ def test_full_solve_divergence_curve_fp64(pk):
     s.close()
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-11), (torch.float32, 1e-5)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_mid_grid_single_step(pk, dtype, tol):
     g = synth.MID
     ops, T, data, _ = problem(g, dense=False)
@@ -249,5 +257,89 @@ def test_autotune_mid_solve_keeps_the_trajectory(pk, dtype, tol):
     for i in range(2):
         assert rel(host(b.m[i]), host(a.m[i])) <= tol
     assert b.scalars()["k"] == a.scalars()["k"] == 3
+    a.close()
+    b.close()
+
+
+# ------------------------------------------------------------------------------------
+# the benchmarked solve: 256x256 stations over 256x256x32 prisms (512-point transforms, the
+# fused N = 512 forms of the group path), the bench's model, noise and parameters
+# ------------------------------------------------------------------------------------
+_LARGE = {}
+LARGE_INNER = 3
+
+
+def large_reference():
+    """Oracle state after one outer step from the start, and the oracle's next outer step
+    from it (FFT2 products on the host cores)."""
+    if _LARGE:
+        return _LARGE["v"]
+    g = synth.LARGE
+    og = ogeom(g)
+    workers = min(16, os.cpu_count() or 1)
+    T = [obttb.kernel_array(k, og) for k in (oprism.GRAVITY, oprism.MAGNETIC)]
+    ops = [obttb.FFTOperator(T[i], g.sx, g.sy, workers=workers) for i in range(2)]
+    rho, kap = synth.dyke_and_block(g)
+    d = [ops[0].matvec(rho), ops[1].matvec(kap)]
+    sig = [synth.noise_sigma(d[0], 0.02, 0.02), synth.noise_sigma(d[1], 0.02, 1.0)]
+    dobs = [d[i] + sig[i] * synth.normal_like(d[i].shape, 3, 100 + i) for i in range(2)]
+    data = orrcg.Data(dobs=dobs, wd=[1.0 / x for x in sig],
+                      wdepth=[synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)])
+    prm = orrcg.Params(alpha0=(20000.0, 20000.0), q=(0.95, 0.95), lam=(2.0, 100.0), eps2=1e-9, lo=(0.0, 0.0),
+                       hi=(1.0, 0.1), coupled=True, restart=True, p_norm=1)
+    st, _ = orrcg.outer_step(ops, data, prm, orrcg.initial_state(data, prm, g.model_shape), LARGE_INNER)
+    ref, rec = orrcg.outer_step(ops, data, prm, st, LARGE_INNER)
+    _LARGE["v"] = (T, data, prm, st, ref, rec)
+    return _LARGE["v"]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("shape", [None, (512, 64, 128, 2)], ids=["default-shape", "bench-shape"])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_large_grid_outer_step_parity(pk, dtype, tol, shape):
+    g = synth.LARGE
+    T, data, prm, st, ref, rec = large_reference()
+    s, ops = gpu_solver(pk, g, T, data, prm, dtype, state=st)
+    if shape is not None:   # the launch shape the bench's tuner picks (set before the first capture)
+        s.products().set_launch(*shape)
+    print(f"256x256x32 {dtype} shape {shape}: launch {s.products().info()}", flush=True)
+    s.step(LARGE_INNER)
+    sc = s.scalars()
+    errs = [rel(host(s.m[i]), ref.m[i]) for i in range(2)]
+    print(f"  model rel err {errs}; phi {sc['phi']} vs {rec['phi']}; S_G {sc['gramian']} vs {rec['gramian']}",
+          flush=True)
+    assert max(errs) <= tol
+    for i in range(2):
+        assert sc["phi"][i] == pytest.approx(rec["phi"][i], rel=tol)
+        assert sc["alpha"][i] == pytest.approx(ref.alpha[i], rel=1e-15)
+    assert sc["gramian"] == pytest.approx(rec["gramian"], rel=100 * tol)
+    assert sc["similarity"] == pytest.approx(orrcg.similarity(ref.m[0], ref.m[1]), rel=tol)
+    s.close()
+    for op in ops:
+        op.close()
+
+
+def test_timed_solver_steps_like_an_untimed_one(pk):
+    # per-kernel event timing repeats each product launch; the repeats of the fused direction
+    # update write to scratch, so the solver's trajectory is bitwise that of an untimed solver
+    g = synth.SMALL
+    _, T, data, _ = problem(g, dense=True)
+    prm = orrcg.Params(**BASE)
+    a, _ = gpu_solver(pk, g, T, data, prm, torch.float64, use_graph=False)
+    b, _ = gpu_solver(pk, g, T, data, prm, torch.float64, use_graph=False)
+    prod = b.products()
+    prod.timing_enable(200, 10)
+    for _ in range(2):
+        a.step(4)
+        b.step(4)
+    tm = prod.timing_read()
+    prod.timing_enable(0)
+    # 8 CG steps (fused forms) and 2 residual products (plain) of the forward row transform
+    assert tm["fwd_row_r2c"][1] == 10 * (8 + 2) and tm["adj_row_c2r"][1] == 10 * 8
+    for i in range(2):
+        assert np.array_equal(host(a.m[i]), host(b.m[i]))
+        assert np.array_equal(host(a.p[i]), host(b.p[i]))
+    sa, sb = a.scalars(), b.scalars()
+    assert sa["phi"] == sb["phi"] and sa["beta"] == sb["beta"] and sa["step"] == sb["step"]
     a.close()
     b.close()

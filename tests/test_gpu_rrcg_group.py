@@ -20,14 +20,15 @@ def pk():
 
 # uneven inversions (transforms 32 after power-of-two padding, ragged 7 x 9 over 11 x 5 x 3)
 GRIDS = [synth.SMALL, synth.SUB, synth.Grid(7, 9, 11, 5, 3, 40.0, 30.0, 25.0, decl=20.0),
-         synth.Grid(10, 14, 10, 14, 4, 50.0, 40.0, 30.0)]
+         synth.Grid(10, 14, 10, 14, 4, 50.0, 40.0, 30.0), synth.Grid(16, 12, 16, 12, 3, 50.0, 50.0, 40.0)]
 # one solver variant per inversion: nested with restart, stand-alone, joint minimum length,
-# weighted Gramian without restart
+# weighted Gramian without restart, the printed previous-iterate anchor of RRCG:4
 VARIANTS = [
     dict(restart=True),
     dict(restart=True, coupled=False, lam=(0.0, 0.0)),
     dict(restart=True, p_norm=2, alpha_min=(500.0, 500.0)),
     dict(restart=False, gramian="weighted", lam=(1e-3, 1e-1)),
+    dict(restart=False, anchor="prev"),
 ]
 N_INNER = 3
 
@@ -40,7 +41,8 @@ def params(v):
 
 def solver_kwargs(prm):
     return dict(lo=prm.lo, hi=prm.hi, alpha0=prm.alpha0, q=prm.q, alpha_min=prm.alpha_min, lam=prm.lam,
-                eps2=prm.eps2, coupled=prm.coupled, restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian)
+                eps2=prm.eps2, coupled=prm.coupled, restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian,
+                anchor=prm.anchor)
 
 
 def ops_for(pk, g, T, dtype):
@@ -63,6 +65,8 @@ def set_state(grp, i, st, dtype):
     for k in range(2):
         grp.inv[i].m[k].copy_(torch.as_tensor(st.m[k], dtype=dtype, device="cuda"))
         grp.inv[i].p[k].copy_(torch.as_tensor(st.p[k], dtype=dtype, device="cuda"))
+        if grp.inv[i].mprev is not None:
+            grp.inv[i].mprev[k].copy_(torch.as_tensor(st.m_prev[k], dtype=dtype, device="cuda"))
     grp.set_scalars(i, alpha=st.alpha, L_prev=st.L_prev, frozen=st.frozen, k=st.k)
 
 

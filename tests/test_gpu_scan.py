@@ -25,7 +25,7 @@ def solver_kwargs(prm):
                 coupled=prm.coupled, restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian)
 
 
-@pytest.mark.parametrize("dtype,tol_m,tol_s", [(torch.float64, 1e-9, 1e-10), (torch.float32, None, 1e-4)])
+@pytest.mark.parametrize("dtype,tol_m,tol_s", [(torch.float64, 1e-9, 1e-10), (torch.float32, 1e-5, 1e-5)])
 def test_scan_matches_oracle(pk, dtype, tol_m, tol_s):
     g = synth.SMALL
     ops, T, data, _ = problem(g, dense=True)
@@ -38,15 +38,15 @@ def test_scan_matches_oracle(pk, dtype, tol_m, tol_s):
     for a, b in zip(got["records"], ref["records"]):
         assert a["lam"] == b["lam"]
         assert a["converged"] == b["converged"] and a["k"] == b["k"]
+        errs = [rel(host(a["m"][i]), b["m"][i]) for i in range(2)]
+        print(f"{dtype} lambda {a['lam']}: model rel err {errs}, similarity {a['similarity']} vs "
+              f"{b['similarity']}", flush=True)
         assert a["similarity"] == pytest.approx(b["similarity"], rel=tol_s)
-        if tol_m is not None:
-            for i in range(2):
-                assert rel(host(a["m"][i]), b["m"][i]) <= tol_m
+        assert max(errs) <= tol_m
     # the choice is the rule applied to the records (the same rule, written separately)
     assert got["selected"] == pk.scan.choose(got["records"], sim_min)
     assert got["selected"] == orrcg.select_lambda(got["records"], sim_min)
-    if tol_m is not None:
-        assert got["selected"] == ref["selected"]
+    assert got["selected"] == ref["selected"]
 
 
 def test_scan_more_pairs_than_a_group(pk, monkeypatch):
