@@ -145,6 +145,19 @@ BTTB_API int bttb_rmatvec(bttb_plan plan, const void* r, void* z, void* stream);
 BTTB_API int bttb_apply(bttb_plan plan, int op, int batch, const void* in, long long in_stride,
                void* out, long long out_stride, const void* winv, const void* wd, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): bttb_apply with batch 1 (same arguments, same
+ * kernels, same results), with the products' intermediates (the row spectra and the data-side
+ * spectra) in a fixed array of BTTB_NOALLOC_MAX_SCRATCH bytes that the library holds on every GPU
+ * it runs on until the process ends, instead of the plan's scratch.  Allocates nothing.  Call it
+ * with the plan's device current.  A plan whose intermediates need more than the array returns
+ * BTTB_ESIZE (at 32 MiB: 256x256x32 in FP32 fits, in FP64 it does not).  Every call on one GPU
+ * shares that GPU's array: calls that overlap on one GPU (two streams, or two host threads) race.
+ * The first call on a device looks up the array's address there (no allocation). */
+#define BTTB_NOALLOC_MAX_SCRATCH (32u << 20)
+BTTB_API int bttb_apply_noalloc(bttb_plan plan, int op, const void* in, void* out, const void* winv,
+                                const void* wd, void* stream);
+
 /* Launch shape: FFTs per block for the column and row passes and the number of layer
  * chunks of the forward column pass.  Values <= 0 keep the current choice.  Changes
  * only the work split, never the arithmetic of an output element.  BTTB_EINVAL if a

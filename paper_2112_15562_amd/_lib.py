@@ -19,6 +19,7 @@ BTTB_ANCHOR_APR, BTTB_ANCHOR_PREV = 0, 1
 BTTB_PAD_POW2 = 0x10
 BTTB_EIG_FULL = 0x20
 MAX_TRANSFORM = 2048
+NOALLOC_MAX_SCRATCH = 32 << 20
 
 EXPORTED = [
     "bttb_prism_kernels", "bttb_setup", "bttb_matvec", "bttb_rmatvec", "bttb_apply", "bttb_set_launch",
@@ -30,7 +31,7 @@ EXPORTED = [
     "rrcg_group_refresh", "rrcg_group_set_launch", "rrcg_group_products", "rrcg_group_destroy",
     "bttb_autotune", "bttb_group_autotune", "rrcg_group_autotune", "bttb_group_timing_enable",
     "bttb_group_timing_read", "rrcg_products", "rrcg_autotune", "rrcg_prepare", "rrcg_group_prepare",
-    "bttb_group_timing_list",
+    "bttb_group_timing_list", "bttb_apply_noalloc",
 ]
 NKERNELS = 6
 KERNEL_NAMES = ["fwd_row_r2c", "fwd_col_eig_sum", "fwd_row_c2r", "adj_row_r2c", "adj_col_conj_eig", "adj_row_c2r"]
@@ -137,6 +138,7 @@ def lib() -> C.CDLL:
         "rrcg_prepare": [vp, i],
         "rrcg_group_prepare": [vp, i],
         "bttb_group_timing_list": [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_int)],
+        "bttb_apply_noalloc": [vp, i, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)

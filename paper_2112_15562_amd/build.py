@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libbttb.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["operator.hip", "operator_fast.hip", "group.hip", "autotune.hip", "prism.hip", "rrcg.hip",
-           "rrcg_group.hip", "status.cpp"]
+           "rrcg_group.hip", "noalloc.hip", "status.cpp"]
 HEADERS = ["common.h", "fft_engine.h", "fft_reg.h", "fast_kernels.h", "rrcg_fuse.h", "rrcg_kernels.h", "group.h"]
 
 ARCH = "gfx950"

@@ -119,8 +119,12 @@ int fast_col(bool fwd, const cx<T>* in, long long in_bs, const cx<T>* eig, int e
              long long out_cs, int L, int nin, int nout, int ldin, int ldout, int K2, int N, int G, int nchunk,
              const cx<T>* tw, int batch, hipStream_t s);
 
+// The products of one plan (bttb_apply).  scratch_U, scratch_V: where the row spectra and the
+// data-side spectra go, or NULL for the plan's own scratch (apply_scratch_bytes: the bytes a
+// call with `batch` members needs, U first and V right after it, at batch-stride offsets).
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,
-               const T* winv, const T* wd, hipStream_t s);
+               const T* winv, const T* wd, hipStream_t s, void* scratch_U = nullptr, void* scratch_V = nullptr);
+size_t apply_scratch_bytes(const Plan* P, int batch);
 
 }  // namespace bttb

@@ -549,12 +549,12 @@ static int small_row_groups(const Plan* P, int nrows, int batch) {
 
 template <typename T>
 int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* out, long long out_stride,
-               const T* winv, const T* wd, hipStream_t s) {
+               const T* winv, const T* wd, hipStream_t s, void* scratch_U, void* scratch_V) {
   const cx<T>* eig = static_cast<const cx<T>*>(P->eig);
   const cx<T>* twx = static_cast<const cx<T>*>(P->twx);
   const cx<T>* twy = static_cast<const cx<T>*>(P->twy);
-  cx<T>* U = static_cast<cx<T>*>(P->U);
-  cx<T>* V = static_cast<cx<T>*>(P->V);
+  cx<T>* U = static_cast<cx<T>*>(scratch_U ? scratch_U : P->U);
+  cx<T>* V = static_cast<cx<T>*>(scratch_V ? scratch_V : P->V);
   const long long U_bs = (long long)P->nz * P->K2 * P->ldx;
   const long long V_cs = (long long)P->K2 * P->lds;
   const long long V_fcs = (long long)P->lds * P->ldk;  // power-of-two path: one row-major partial
@@ -660,9 +660,17 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
 }
 
 template int apply_impl<float>(Plan*, int, int, const float*, long long, float*, long long, const float*,
-                               const float*, hipStream_t);
+                               const float*, hipStream_t, void*, void*);
 template int apply_impl<double>(Plan*, int, int, const double*, long long, double*, long long, const double*,
-                                const double*, hipStream_t);
+                                const double*, hipStream_t, void*, void*);
+
+size_t apply_scratch_bytes(const Plan* P, int batch) {
+  const size_t elem = P->precision == BTTB_F64 ? 16 : 8;
+  const size_t U_bs = (size_t)P->nz * P->K2 * P->ldx;
+  const size_t V_one = std::max((size_t)P->K2 * P->lds, (size_t)P->lds * P->ldk);
+  // batch members beyond the first start one full (nchunk_max) slot apart; the last holds nchunk
+  return elem * ((size_t)(batch - 1) * (U_bs + (size_t)P->nchunk_max * V_one) + U_bs + (size_t)P->nchunk * V_one);
+}
 
 // ------------------------------------------------------------------------------------
 // Launch shapes
