@@ -71,11 +71,6 @@ def is_built() -> bool:
     return os.path.exists(LIB)
 
 
-def load_builder():
-    """This module, imported by file path (without importing the package)."""
-    return sys.modules[__name__]
-
-
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)
