@@ -130,46 +130,70 @@ BATCH_OUTER, BATCH_INNER = 5, 10
 
 def batched_workload(pk, torch):
     """16 independent joint inversions, n = nx = ny ~ U{64..320}, nz ~ U{16..40}, stepped
-    together by the group solver (one launch per phase for all of them, HIP graphs,
-    autotuned launch shapes), FP32 with FP64 reductions; 5 outer x 10 inner steps.
-    Against it: the same inversions solved one after another by one-inversion solvers."""
+    together by the group solver (one launch per phase and transform size for all of them, HIP
+    graphs, autotuned launch shapes), FP32 with FP64 reductions; 5 outer x 10 inner steps, on the
+    5-smooth transform sizes (no power-of-two padding).  Beside it: the same group on
+    power-of-two transforms, and the inversions solved one after another by one-inversion
+    solvers (5-smooth transforms, each tuned)."""
     import synth
     grids = synth.uneven_sizes(16)
-    problems, keep = [], []
+    prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.95, 0.95), lam=(2.0, 100.0),
+               eps2=1e-9, coupled=True, restart=True, p_norm=1)
+    data, kern = [], []
     for idx, g in enumerate(grids):
         rho, kap = synth.random_boxes(g, seed_workload=5, index=1 + idx)
         T = [pk.prism_kernels(k, g) for k in (pk.GRAVITY, pk.MAGNETIC)]
         d = []
         for i, m in enumerate((rho, kap)):
-            op = pk.Operator(T[i], (g.sx, g.sy), dtype=torch.float64, pad_pow2=True)
+            op = pk.Operator(T[i], (g.sx, g.sy), dtype=torch.float64)
             d.append(op.matvec(torch.as_tensor(m, device="cuda")).cpu().numpy())
             op.close()
         floors = (0.02, 1.0)
         sig = [synth.noise_sigma(d[i], 0.02, floors[i]) for i in range(2)]
         dobs = [d[i] + sig[i] * synth.normal_like(d[i].shape, 5, 100 + 2 * idx + i) for i in range(2)]
-        ops = [pk.Operator(T[i], (g.sx, g.sy), dtype=torch.float32, pad_pow2=True) for i in range(2)]
-        keep.append(ops)
-        problems.append(dict(ops=ops, dobs=dobs, wd=[1.0 / s_ for s_ in sig],
-                             wdepth=[synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)]))
-    prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.95, 0.95), lam=(2.0, 100.0),
-               eps2=1e-9, coupled=True, restart=True, p_norm=1)
-    grp = pk.JointRRCGGroup(problems, **prm)
-    tune = grp.autotune(reps=5)
-    grp.step(BATCH_INNER)  # warm-up outer step (also captures its graph)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(BATCH_OUTER):
-        grp.step(BATCH_INNER)
-    torch.cuda.synchronize()
-    t_group = time.perf_counter() - t0
-    chi = [grp.scalars(i)["phi"] for i in range(len(grids))]
-    grp.close()
-    # the same inversions one at a time (each plan tuned on its own first)
+        data.append(dict(dobs=dobs, wd=[1.0 / s_ for s_ in sig],
+                         wdepth=[synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)]))
+        kern.append(T)
+    pairs = len(grids) * 2 * BATCH_INNER * BATCH_OUTER
+
+    def make_ops(pad_pow2):
+        return [[pk.Operator(kern[j][i], (g.sx, g.sy), dtype=torch.float32, pad_pow2=pad_pow2) for i in range(2)]
+                for j, g in enumerate(grids)]
+
+    def close(opss):
+        for ops in opss:
+            for op in ops:
+                op.close()
+
+    def group_run(pad_pow2):
+        opss = make_ops(pad_pow2)
+        grp = pk.JointRRCGGroup([dict(ops=opss[j], **data[j]) for j in range(len(grids))], **prm)
+        tune = grp.autotune(reps=5)
+        grp.step(BATCH_INNER)  # warm-up outer step (also captures its graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(BATCH_OUTER):
+            grp.step(BATCH_INNER)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        chi = [grp.scalars(i)["phi"] for i in range(len(grids))]
+        transforms = sorted({op.info()["Px"] for ops in opss for op in ops})
+        grp.close()
+        close(opss)
+        return {"op_pairs_per_s": pairs / dt, "solve_s": dt, "per_inversion_latency_s": dt,
+                "transforms": transforms,
+                "launch_shape": {k: tune[k] for k in ("model_row_threads", "data_row_threads", "col_threads",
+                                                      "layer_chunks")},
+                "autotune_candidates": tune["tried"]}, chi
+
+    group5, chi = group_run(False)
+    group2, _ = group_run(True)
+    # the same inversions one at a time (5-smooth transforms; each solver tuned on its own first)
+    opss = make_ops(False)
     t_seq, lat = 0.0, []
-    for pr in problems:
-        for op in pr["ops"]:
-            op.autotune(reps=2)
-        s1 = pk.JointRRCG(**{k: v for k, v in pr.items() if k != "ops"}, ops=pr["ops"], **prm)
+    for j in range(len(grids)):
+        s1 = pk.JointRRCG(opss[j], **data[j], **prm)
+        s1.autotune(reps=3)
         s1.step(BATCH_INNER)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -180,22 +204,18 @@ def batched_workload(pk, torch):
         lat.append(dt)
         t_seq += dt
         s1.close()
-    for ops in keep:
-        for op in ops:
-            op.close()
-    pairs = len(grids) * 2 * BATCH_INNER * BATCH_OUTER
+    close(opss)
     return {
         "workload": f"16 joint inversions, n = {min(g.nx for g in grids)}..{max(g.nx for g in grids)}, "
-                    f"nz = {min(g.nz for g in grids)}..{max(g.nz for g in grids)}, power-of-two transforms, "
-                    f"{BATCH_OUTER} outer x {BATCH_INNER} inner, FP32 with FP64 reductions",
+                    f"nz = {min(g.nz for g in grids)}..{max(g.nz for g in grids)}, {BATCH_OUTER} outer x "
+                    f"{BATCH_INNER} inner, FP32 with FP64 reductions",
         "sizes": [[g.nx, g.nz] for g in grids],
-        "group": {"op_pairs_per_s": pairs / t_group, "solve_s": t_group, "per_inversion_latency_s": t_group,
-                  "launch_shape": {k: tune[k] for k in ("model_row_threads", "data_row_threads", "col_threads",
-                                                        "layer_chunks")},
-                  "autotune_candidates": tune["tried"]},
+        "group": group5,
+        "group_pow2_padding": group2,
         "sequential": {"op_pairs_per_s": pairs / t_seq, "solve_s": t_seq,
                        "per_inversion_latency_s": {"min": min(lat), "max": max(lat),
                                                    "mean": sum(lat) / len(lat)}},
+        "group_vs_sequential": t_seq / group5["solve_s"],
         "phi_after": [[round(a, 1) for a in c] for c in chi],
     }
 

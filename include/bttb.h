@@ -72,8 +72,8 @@ typedef enum {
 
 typedef enum { BTTB_F64 = 0, BTTB_F32 = 1 } bttb_precision;
 /* Flag or-ed into bttb_setup's precision: pad to powers of two (>= 32) instead of the
- * smallest 5-smooth multiples of 8, so that the plan takes the register-FFT kernels and
- * can join a group. */
+ * smallest 5-smooth multiples of 8, so that the plan takes the register-FFT kernels of the
+ * one-plan products.  (Groups and solvers also take 5-smooth plans: see bttb_group_create.) */
 #define BTTB_PAD_POW2 0x10
 /* Flag or-ed into bttb_setup's precision: keep the full complex eigenvalues even when the
  * operator is symmetric.  Without it, a power-of-two plan whose eigenvalues are real and
@@ -197,9 +197,13 @@ BTTB_API int bttb_timing_read(bttb_plan plan, double* total_ms, int* count);
 /* A group runs the products (Sec. 2.7.1, eq. matrixvector) of up to 64 plans -- e.g. the
  * gravity and magnetic operators of many inversions of uneven sizes -- as one kernel
  * launch per stage (row transform, column pass, inverse row transform), each member
- * with its own plan's eigenvalues and scratch.  Members must be power-of-two plans
- * (bttb_setup with BTTB_PAD_POW2, transforms 32..2048) of one precision, each plan at
- * most once (a member's intermediates live in its plan; a repeated plan is BTTB_EINVAL).
+ * with its own plan's eigenvalues and scratch.  Members are plans of one precision whose
+ * transform sizes are powers of two from 32 to 2048 (bttb_setup with BTTB_PAD_POW2), or
+ * 5-smooth sizes up to 640 that are not powers of two (radix-3 and -5 passes, the default
+ * padding of bttb_setup) where the rows and columns, model and data side, fill at most half of
+ * the transform (stations over the prism centres always do); otherwise BTTB_ESTATE.  Each
+ * plan at most once (a member's intermediates live in its plan; a repeated plan is
+ * BTTB_EINVAL).
  * The group refers to the plans, which must outlive it and must not be used on another
  * stream while a group product runs.  Creation allocates a small device table and
  * synchronises `stream`. */
@@ -346,9 +350,9 @@ typedef struct {
 
 /* Create a solver for one inversion: the scalars start at alpha = alpha0, no previous
  * gradient, k = 0, and resid / Phi / S_G are computed from the given m.  Allocates the
- * solver's own work vectors.  When both plans have power-of-two transforms the solver runs
- * as a one-inversion group solver (rrcg_group_create): both operators' products share each
- * launch and the CG pieces ride on their row transforms.  Synchronises `stream`. */
+ * solver's own work vectors.  When both plans can join a product group (bttb_group_create) the
+ * solver runs as a one-inversion group solver (rrcg_group_create): both operators' products
+ * share each launch and the CG pieces ride on their row transforms.  Synchronises `stream`. */
 BTTB_API int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out);
 
 /* One outer step: n_inner >= 1 CG steps at the outer step's W and alpha (RRCG:1-7, the
@@ -359,7 +363,7 @@ BTTB_API int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out);
 BTTB_API int rrcg_step(rrcg_handle h, int n_inner, void* stream);
 
 /* Capture the graph of an outer step with n_inner CG steps ahead of its first use (a
- * solver on power-of-two plans with use_graph replays each outer step as one graph,
+ * solver on group plans (bttb_group_create) with use_graph replays each outer step as one graph,
  * captured on first use per step length; otherwise this does nothing). */
 BTTB_API int rrcg_prepare(rrcg_handle h, int n_inner);
 
@@ -371,10 +375,10 @@ BTTB_API int rrcg_write_scalars(rrcg_handle h, const rrcg_scalars* in, void* str
  * from a checkpoint (with rrcg_write_scalars for the scalar state). */
 BTTB_API int rrcg_refresh(rrcg_handle h, void* stream);
 
-/* rrcg_group_autotune for a solver on power-of-two plans (BTTB_ESTATE otherwise). */
+/* rrcg_group_autotune for a solver on group plans (BTTB_ESTATE otherwise). */
 BTTB_API int rrcg_autotune(rrcg_handle h, int reps, void* stream, bttb_tune_result* out);
 
-/* The product group of a solver on power-of-two plans (owned by the solver), for
+/* The product group of a solver on group plans (owned by the solver), for
  * inspection and timing; BTTB_ESTATE for other plans. */
 BTTB_API int rrcg_products(rrcg_handle h, bttb_group* out);
 
@@ -385,8 +389,8 @@ BTTB_API int rrcg_destroy(rrcg_handle h);
  * parameters, with the same arithmetic as a one-inversion solver; every phase of a step
  * is one launch over all of them (the products of all their operators through one
  * product group, the CG pieces fused into the row transforms, and the elementwise
- * updates over the concatenated vectors).  All plans must be power-of-two plans
- * (BTTB_PAD_POW2) of one precision, each used by one inversion once (as in
+ * updates over the concatenated vectors).  All plans must be able to join a product group
+ * (bttb_group_create) and share one precision, each used by one inversion once (as in
  * bttb_group_create); descs[0].use_graph decides graph capture for the whole group.
  * Creation allocates the work vectors and synchronises `stream`. */
 BTTB_API int rrcg_group_create(const rrcg_desc* descs, int count, void* stream, rrcg_group* out);

@@ -18,9 +18,10 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbttb.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["operator.hip", "operator_fast.hip", "group.hip", "autotune.hip", "prism.hip", "rrcg.hip",
-           "rrcg_group.hip", "noalloc.hip", "status.cpp"]
-HEADERS = ["common.h", "fft_engine.h", "fft_reg.h", "fast_kernels.h", "rrcg_fuse.h", "rrcg_kernels.h", "group.h"]
+SOURCES = ["operator.hip", "operator_fast.hip", "group.hip", "group_mixed_f32.hip", "group_mixed_f64.hip",
+           "autotune.hip", "prism.hip", "rrcg.hip", "rrcg_group.hip", "noalloc.hip", "status.cpp"]
+HEADERS = ["common.h", "fft_engine.h", "fft_reg.h", "fast_kernels.h", "rrcg_fuse.h", "rrcg_kernels.h", "group.h",
+           "group_kernels.h", "group_mixed.h"]
 
 ARCH = "gfx950"
 CFLAGS = [

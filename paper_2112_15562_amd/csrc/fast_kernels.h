@@ -20,17 +20,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int TPF>
-struct GroupSync {
+template <int LANES>
+struct GroupSync {  // a group of LANES (a power of two) lanes: inside one wave up to 64
   __device__ __forceinline__ void operator()() const {
-    if constexpr (TPF <= 64) wave_sync();
+    if constexpr (LANES <= 64) wave_sync();
     else __syncthreads();
   }
 };
 
 template <int N>
 constexpr int row_buf() {  // per-group LDS elements of the row kernels (exchange and [2][K2] staging)
-  return Pow2<N>::BUF > N + 2 ? Pow2<N>::BUF : N + 2;
+  return Len<N>::BUF > N + 2 ? Len<N>::BUF : N + 2;
 }
 
 #ifndef BTTB_ROW_WAVES32
@@ -46,7 +46,10 @@ constexpr int row_buf() {  // per-group LDS elements of the row kernels (exchang
 // keep the default.
 template <typename T, int N, int MODE, bool HALF>
 constexpr int row_waves() {
-  return sizeof(T) != 4 || N > 512 ? 2 : MODE == FUSE_DIR && !HALF ? BTTB_GRAD_WAVES32 : BTTB_ROW_WAVES32;
+  // (a 5-smooth size's direction form holds a composite radix's values as well: six waves)
+  return sizeof(T) != 4 || N > 512                                         ? 2
+         : MODE == FUSE_DIR && (!HALF || (N & (N - 1)) != 0) ? BTTB_GRAD_WAVES32
+                                                             : BTTB_ROW_WAVES32;
 }
 // The inverse row transforms: the model-row ones as above, except the gradient form in the
 // full form, which needs more than 64 registers (six waves, three blocks per CU); the data-row
@@ -85,21 +88,24 @@ template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
 __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T>& fz, int bx, int by, int pid,
                                               int pcount, unsigned char* smem_raw) {
   static_assert(MODE == FUSE_NONE || (MODE == FUSE_DIR && !ROWOUT) || (MODE == FUSE_RUPD && ROWOUT), "fused form");
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
+  using P = Len<N>;
+  constexpr int TPF = P::TPF, LANES = P::LANES, BS = row_buf<N>(), K2 = N / 2 + 1;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
+  const int f = threadIdx.x / LANES, tl = threadIdx.x - f * LANES;
+  // a 5-smooth size's lanes past TPF hold no values: they index as lane 0 and store nothing
+  const bool live = P::POW2 || tl < TPF;
+  const int t = P::POW2 ? tl : (live ? tl : 0);
   const int l = bx / a.tiles, tile = bx - l * a.tiles;
   const int b = by;
   const int RT = 2 * a.fpb;
   const int r0 = tile * RT + 2 * f;
   cx<T>* buf = smem + f * BS;
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
+  GroupSync<LANES> gsync;
+  FFTOf<T, N> F;
   const long long lofs = (long long)l * a.nrows * a.ncols;
   const T* src = a.in + b * a.in_bs + lofs;
   const T* sc = a.scale ? a.scale + lofs : nullptr;
-  const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
+  const bool ra = live && r0 < a.nrows, rb = live && r0 + 1 < a.nrows;
   cx<T> v[8];
   double acc[2] = {0.0, 0.0};
   if constexpr (MODE == FUSE_DIR) {
@@ -240,10 +246,13 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     for (int i = 0; i < 8; ++i) v[i] = cx<T>{XA[i] * SA[i], XB[i] * SB[i]};
   }
   F.init(a.tw, t);  // twiddles loaded here: not live during the prologue
+  if constexpr (!P::POW2) F.live = live;
   F.template run<false>(v, buf, t, gsync);
   // X_a[k] = (Z[k] + conj Z[N-k]) / 2,  X_b[k] = (Z[k] - conj Z[N-k]) / (2i),  k <= N/2
+  if (live) {
 #pragma unroll
-  for (int i = 0; i < 8; ++i) buf[lds_pad(t + i * TPF)] = v[i];
+    for (int i = 0; i < 8; ++i) buf[lds_pad(t + i * TPF)] = v[i];
+  }
   gsync();
   const T h = T(0.5);
   cx<T> xa[5], xb[5];
@@ -252,7 +261,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
     const int k = t + i * TPF;
     if (k <= N / 2) {
       const cx<T> A = v[i];
-      const cx<T> C = buf[lds_pad((N - k) & (N - 1))];
+      const cx<T> C = buf[lds_pad(P::POW2 ? ((N - k) & (N - 1)) : (k == 0 ? 0 : N - k))];
       xa[i] = cx<T>{h * (A.re + C.re), h * (A.im - C.im)};
       xb[i] = cx<T>{h * (A.im + C.im), h * (C.re - A.re)};
     }
@@ -273,7 +282,7 @@ __device__ __forceinline__ void frow_r2c_body(const FRowArgs<T>& a, const Fuse<T
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
     const int k = t + i * TPF;
-    if (k <= N / 2) {
+    if (live && k <= N / 2) {
       buf[k] = xa[i];
       buf[K2 + k] = xb[i];
     }
@@ -334,18 +343,22 @@ template <typename T, int N, bool ROWIN, int MODE, bool HALF>
 __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T>& fz, int bx, int by, int pid,
                                               int pcount, unsigned char* smem_raw) {
   static_assert(MODE == FUSE_NONE || (MODE == FUSE_QQ && ROWIN) || (MODE == FUSE_GRAD && !ROWIN), "fused form");
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF, BS = row_buf<N>(), K2 = N / 2 + 1;
+  using P = Len<N>;
+  constexpr int TPF = P::TPF, LANES = P::LANES, BS = row_buf<N>(), K2 = N / 2 + 1;
+  // the row-split staging below needs groups of exactly TPF lanes
+  constexpr bool SPLIT = TPF >= 2 && P::POW2;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
+  const int f = threadIdx.x / LANES, tl = threadIdx.x - f * LANES;
+  const bool live = P::POW2 || tl < TPF;  // as in the forward row transform
+  const int t = P::POW2 ? tl : (live ? tl : 0);
   const int l = bx / a.tiles, tile = bx - l * a.tiles;
   const int b = by;
   const int RT = 2 * a.fpb;
   cx<T>* buf = smem + f * BS;
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
+  GroupSync<LANES> gsync;
+  FFTOf<T, N> F;
   const int r0 = tile * RT + 2 * f;
-  const bool ra = r0 < a.nrows, rb = r0 + 1 < a.nrows;
+  const bool ra = live && r0 < a.nrows, rb = live && r0 + 1 < a.nrows;
   const long long lofs = (long long)l * a.nrows * a.ncols;
   const T* sc = a.scale ? a.scale + lofs : nullptr;
   cx<T> v[8];
@@ -400,7 +413,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
     const int rows = min(RT, a.nrows - tile * RT);
     const int rr0 = threadIdx.x % RT, k0 = threadIdx.x / RT;
     auto pos = [&](int it, int& k2, int& rr) {
-      if constexpr (TPF >= 2) {
+      if constexpr (SPLIT) {
         k2 = k0 + it * (TPF / 2);
         rr = rr0;
       } else {
@@ -410,7 +423,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       }
     };
     cx<T> hv[ITER];
-    if constexpr (TPF >= 2) {
+    if constexpr (SPLIT) {
       // k0 < TPF / 2, so only the last pass can reach past K2 (its k0 = 0 lane holds the
       // Nyquist column); a row past `rows` reads row 0 (in range) and is zeroed when staged.
       const bool okr = rr0 < rows;
@@ -439,7 +452,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
       pos(it, k2, rr);
       if (k2 < K2) {
         cx<T> h = hv[it];
-        if constexpr (TPF >= 2) {
+        if constexpr (SPLIT) {
           if (rr0 >= rows) h = cx<T>{T(0), T(0)};
         }
         if (k2 == 0 || k2 == K2 - 1) h.im = T(0);  // DC and Nyquist of a real row are real
@@ -461,6 +474,7 @@ __device__ __forceinline__ void frow_c2r_body(const FRowArgs<T>& a, const Fuse<T
   }
   gsync();
   F.init(a.tw, t);  // twiddles loaded here: not live while the input is staged
+  if constexpr (!P::POW2) F.live = live;
   F.template run<true>(v, buf, t, gsync);
   T* dst = reinterpret_cast<T*>(a.out) + b * a.out_bs + lofs;
   if constexpr (MODE == FUSE_GRAD) {
@@ -648,14 +662,14 @@ struct ColBuf {
 // layer in flight was measured slower: the extra registers cost more than the latency they
 // hide.)
 template <typename T, int N, bool EVEN, bool HALF>
-__device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
+__device__ __forceinline__ void fwd_layers(const FColArgs<T>& a, const FFTOf<T, N>& F, cx<T>* buf, int t, int f,
                                            int G, int k2, int l0, int l1, int b,
                                            typename LayerAcc<T>::type (&ar)[8],
                                            typename LayerAcc<T>::type (&ai)[8]) {
   using Acc = typename LayerAcc<T>::type;
   constexpr int TPF = N / 8;
   constexpr bool PF_IN = sizeof(T) == 4;
-  GroupSync<TPF> gsync;
+  GroupSync<Len<N>::LANES> gsync;
   const cx<T>* src = a.in + b * a.in_bs + (long long)k2 * a.ldin;
   const long long lstride_in = (long long)a.K2 * a.ldin;
   const int nit = (l1 - l0 + G - 1) / G;
@@ -720,16 +734,20 @@ constexpr int col_threads(int esz) { return esz == 4 ? 512 : 256; }
 // outputs are not stored, both known at compile time.
 template <typename T, int N, bool HALF>
 __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int k2, int c, int b, unsigned char* smem_raw) {
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF;
+  using P = Len<N>;
+  constexpr int TPF = P::TPF, LANES = P::LANES;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
+  const int f = threadIdx.x / LANES, tl = threadIdx.x - f * LANES;
+  // a 5-smooth size's lanes past TPF hold no values: they index as lane 0 and store nothing
+  const bool live = P::POW2 || tl < TPF;
+  const int t = P::POW2 ? tl : (live ? tl : 0);
   const int G = a.fpb;
   const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
   cx<T>* buf = smem + f * P::BUF;
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
+  GroupSync<LANES> gsync;
+  FFTOf<T, N> F;
   F.init(a.tw, t);
+  if constexpr (!P::POW2) F.live = live;
   using Acc = typename LayerAcc<T>::type;
   Acc ar[8], ai[8];
 #pragma unroll
@@ -740,7 +758,7 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int k2, int 
   AccPair<Acc>* red = reinterpret_cast<AccPair<Acc>*>(smem_raw);
   for (int half = G >> 1; half >= 1; half >>= 1) {
     __syncthreads();
-    if (f >= half && f < 2 * half) {
+    if (live && f >= half && f < 2 * half) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) red[(f - half) * N + t + i * TPF] = AccPair<Acc>{ar[i], ai[i]};
     }
@@ -755,12 +773,12 @@ __device__ __forceinline__ void fcol_fwd_body(const FColArgs<T>& a, int k2, int 
     }
   }
   __syncthreads();
-  if (TPF > 64 || f == 0) {  // groups wider than a wave run the transform together
+  if (LANES > 64 || f == 0) {  // groups wider than a wave run the transform together
     cx<T> v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = cx<T>{(T)ar[i], (T)ai[i]};
     F.template run<true>(v, buf, t, gsync);
-    if (f == 0) {
+    if (live && f == 0) {
       cx<T>* dst = a.out + b * a.out_bs + c * a.out_cs;
 #pragma unroll
       for (int i = 0; i < (HALF ? 4 : 8); ++i) {
@@ -781,10 +799,11 @@ __global__ void __launch_bounds__(col_threads(sizeof(T))) k_fcol_fwd(FColArgs<T>
 // FFT_x, rows a < nout stored.  The next layer's eigenvalues are loaded while the current one
 // is transformed.
 template <typename T, int N, bool EVEN, bool HALF>
-__device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T, N>& F, cx<T>* buf, int t, int f,
-                                           int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8]) {
+__device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const FFTOf<T, N>& F, cx<T>* buf, int t, int f,
+                                           int G, int k2, int l0, int l1, int b, const cx<T> (&R)[8],
+                                           bool live) {
   constexpr int TPF = N / 8;
-  GroupSync<TPF> gsync;
+  GroupSync<Len<N>::LANES> gsync;
   cx<T>* dst = a.out + b * a.out_bs + (long long)k2 * a.ldout;
   const long long lstride_out = (long long)a.K2 * a.ldout;
   const int nit = (l1 - l0 + G - 1) / G;
@@ -795,9 +814,10 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
 #pragma unroll
     for (int i = 0; i < 8; ++i) B.en[i] = eig_at<T, N, EVEN>(ecol, t + i * TPF);
   };
+  // (live: false for a 5-smooth size's lanes past TPF, which store nothing)
   auto layer = [&](int it, Buf& B) {
     const int l = l0 + it * G + f;
-    const bool act = l < l1;
+    const bool act = live && l < l1;
     cx<T> v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = cmulc(R[i], B.en[i]);
@@ -821,19 +841,22 @@ __device__ __forceinline__ void adj_layers(const FColArgs<T>& a, const RegFFT<T,
 // to out[l][k2][a] (ldout = padded rows).  Rrow is row-major Rrow[p][k2] (ldin = padded K2).
 template <typename T, int N, bool HALF>
 __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int k2, int c, int b, unsigned char* smem_raw) {
-  using P = Pow2<N>;
-  constexpr int TPF = P::TPF;
+  using P = Len<N>;
+  constexpr int TPF = P::TPF, LANES = P::LANES;
   cx<T>* smem = reinterpret_cast<cx<T>*>(smem_raw);
-  const int f = threadIdx.x / TPF, t = threadIdx.x - f * TPF;
+  const int f = threadIdx.x / LANES, tl = threadIdx.x - f * LANES;
+  const bool live = P::POW2 || tl < TPF;  // as in the forward pass
+  const int t = P::POW2 ? tl : (live ? tl : 0);
   const int G = a.fpb;
   const int l0 = (c * a.L) / a.nchunk, l1 = ((c + 1) * a.L) / a.nchunk;
   cx<T>* buf = smem + f * P::BUF;
   cx<T>* Rs = smem + G * P::BUF;  // the shared column spectrum, N values
-  GroupSync<TPF> gsync;
-  RegFFT<T, N> F;
+  GroupSync<LANES> gsync;
+  FFTOf<T, N> F;
   F.init(a.tw, t);
+  if constexpr (!P::POW2) F.live = live;
   const cx<T>* col = a.in + b * a.in_bs;
-  if (TPF > 64 || f == 0) {
+  if (LANES > 64 || f == 0) {
     cx<T> R[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -841,7 +864,7 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int k2, int 
       R[i] = (HALF && i >= 4) || n >= a.nin ? cx<T>{T(0), T(0)} : gload(col + (long long)n * a.ldin + k2);
     }
     F.template run<false>(R, buf, t, gsync);
-    if (f == 0) {
+    if (live && f == 0) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) Rs[t + i * TPF] = R[i];
     }
@@ -850,8 +873,8 @@ __device__ __forceinline__ void fcol_adj_body(const FColArgs<T>& a, int k2, int 
   cx<T> R[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) R[i] = Rs[t + i * TPF];
-  if (a.eig_even) adj_layers<T, N, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R);
-  else adj_layers<T, N, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R);
+  if (a.eig_even) adj_layers<T, N, true, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, live);
+  else adj_layers<T, N, false, HALF>(a, F, buf, t, f, G, k2, l0, l1, b, R, live);
 }
 
 template <typename T, int N, bool HALF>

@@ -75,6 +75,19 @@ __device__ __forceinline__ int group_member(const int* start, int count, int blk
   return i;
 }
 
+// A stage kernel of the group products.
+template <typename T>
+using StageKernel = void (*)(GLaunch<T>);
+// The stage kernel of a 5-smooth size that is not a power of two (half forms only; group_mixed.h),
+// or NULL when there is none for (N, half).
+template <typename T>
+StageKernel<T> stage_kernel_mixed(int N, int st, bool fused, bool half);
+// N is one of those sizes.
+bool mixed_size(int N);
+// The plan's transform sizes have group kernels: powers of two from 32 to 2048, or 5-smooth sizes
+// with group kernels whose rows and columns fill at most half of them.
+bool group_member_ok(const Plan* P);
+
 int group_create(const bttb_plan* plans, int count, void* stream, Group** out);
 void group_destroy(Group* g);
 int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s);

@@ -8,7 +8,7 @@
 // eigenvalues and scratch.  A stage is one launch per transform size present (so each
 // kernel is compiled for one size and keeps that size's register budget).  All blocks of a
 // stage have the same thread count, so a member of transform size N runs
-// (threads / (N / 8)) FFTs per block.  The per-call vectors come from device arrays of pointers, so a group product
+// (threads / L) FFTs per block, L = N / 8 rounded up to a power of two.  The per-call vectors come from device arrays of pointers, so a group product
 // can be captured in a HIP graph and replayed with new data in the same buffers.
 #include <hip/hip_runtime.h>
 
@@ -16,93 +16,21 @@
 #include <new>
 
 #include "common.h"
-#include "fast_kernels.h"
-#include "group.h"
+#include "group_kernels.h"
 
 namespace bttb {
 
-
-template <typename T, int MODE>
-__device__ __forceinline__ Fuse<T> member_fuse(const GLaunch<T>& g, int i) {
-  if constexpr (MODE != FUSE_NONE) return launch_const(g.fz + i);
-  return Fuse<T>{};
-}
-
-// Row transform R2C of transform size N.  ROWOUT = false: model rows into U (forward, first
-// stage); ROWOUT = true: data rows into V (transpose, first stage).
-template <typename T, int N, bool ROWOUT, int MODE, bool HALF>
-__global__ void __launch_bounds__(512, (row_waves<T, N, MODE, HALF>())) k_grow_r2c(GLaunch<T> g) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int k = uniform(group_member(g.start, g.count, blockIdx.x));
-  const int i = uniform(g.idx[k]);
-  const GMember<T> M = launch_const(g.mem + i);
-  const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
-  constexpr int G1 = N / 8;
-  const int G = g.bt / G1;
-  const T* in = launch_const(g.in + i);
-  FRowArgs<T> a;
-  if constexpr (!ROWOUT) {
-    a = FRowArgs<T>{in, 0, g.winv ? launch_const(g.winv + i) : nullptr, M.U, 0, 0, 1, M.nz, M.nx, M.ny, M.ldx, M.K2, G,
-                    (M.nx + 2 * G - 1) / (2 * G), M.twy};
-  } else {
-    a = FRowArgs<T>{in, 0, g.wd ? launch_const(g.wd + i) : nullptr, M.V, 0, 0, 1, 1, M.sx, M.sy, M.ldk, M.K2, G,
-                    (M.sx + 2 * G - 1) / (2 * G), M.twy};
-  }
-  const Fuse<T> fz = member_fuse<T, MODE>(g, i);
-  frow_r2c_body<T, N, ROWOUT, MODE, HALF>(a, fz, local, 0, local, nb, smem_raw);
-}
-
-// Inverse row transform C2R of size N.  ROWIN = true: data rows from V (forward, last
-// stage, sums the layer-chunk partials); ROWIN = false: model rows from U (transpose, last).
-template <typename T, int N, bool ROWIN, int MODE, bool HALF>
-__global__ void __launch_bounds__(512, (c2r_waves<T, N, ROWIN, MODE, HALF>())) k_grow_c2r(GLaunch<T> g) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int k = uniform(group_member(g.start, g.count, blockIdx.x));
-  const int i = uniform(g.idx[k]);
-  const GMember<T> M = launch_const(g.mem + i);
-  const int local = blockIdx.x - g.start[k], nb = g.start[k + 1] - g.start[k];
-  const int G = g.bt / (N / 8);
-  T* out = launch_const(g.out + i);
-  FRowArgs<T> a;
-  if constexpr (ROWIN) {
-    a = FRowArgs<T>{reinterpret_cast<const T*>(M.V), 0, g.wd ? launch_const(g.wd + i) : nullptr, reinterpret_cast<cx<T>*>(out), 0,
-                    M.V_fcs, M.nchunk, 1, M.sx, M.sy, M.ldk, M.K2, G, (M.sx + 2 * G - 1) / (2 * G), M.twy};
-  } else {
-    a = FRowArgs<T>{reinterpret_cast<const T*>(M.U), 0, g.winv ? launch_const(g.winv + i) : nullptr,
-                    reinterpret_cast<cx<T>*>(out), 0, 0, 1, M.nz, M.nx, M.ny, M.ldx, M.K2, G,
-                    (M.nx + 2 * G - 1) / (2 * G), M.twy};
-  }
-  const Fuse<T> fz = member_fuse<T, MODE>(g, i);
-  frow_c2r_body<T, N, ROWIN, MODE, HALF>(a, fz, local, 0, local, nb, smem_raw);
-}
-
-// Column pass of size N: forward (eigenvalue multiply and layer sum into V partials) or
-// transpose (conjugate eigenvalue multiply per layer into U).
-template <typename T, int N, bool FWD, bool HALF>
-__global__ void __launch_bounds__(col_threads(sizeof(T))) k_gcol(GLaunch<T> g) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int k = uniform(group_member(g.start, g.count, blockIdx.x));
-  const int i = uniform(g.idx[k]);
-  const GMember<T> M = launch_const(g.mem + i);
-  const int local = blockIdx.x - g.start[k];
-  const int jobs = M.K2;
-  const int c = local / jobs, job = local - c * jobs;
-  const int G = g.bt / (N / 8);
-  if constexpr (FWD) {
-    const FColArgs<T> a{M.U, 0, M.eig, M.V, 0, M.V_fcs, M.nz, M.nx, M.sx, M.ldx, M.ldk, M.K2, G, M.nchunk, M.twx,
-                        M.eig_even};
-    fcol_fwd_body<T, N, HALF>(a, job, c, 0, smem_raw);
-  } else {
-    const FColArgs<T> a{M.V, 0, M.eig, M.U, 0, 0, M.nz, M.sx, M.nx, M.ldk, M.ldx, M.K2, G, M.nchunk, M.twx,
-                        M.eig_even};
-    fcol_adj_body<T, N, HALF>(a, job, c, 0, smem_raw);
-  }
-}
 
 // ------------------------------------------------------------------------------------
 // Host side
 // ------------------------------------------------------------------------------------
 static bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+// Lanes of one transform of size N in the group kernels: N / 8 rounded up to a power of two.
+static int lanes(int N) {
+  int l = 1;
+  while (l < N / 8) l *= 2;
+  return l;
+}
 
 static int stage_threads(const Group* g, int st) {
   switch (st) {
@@ -122,7 +50,7 @@ static int layout(Group* g) {
   }
   for (int i = 0; i < g->count; ++i) {
     const Plan* P = g->P[i];
-    const int tr = P->Py / 8, tc = P->Px / 8;
+    const int tr = lanes(P->Py), tc = lanes(P->Px);
     const int Grm = g->bt_rm / tr, Grd = g->bt_rd / tr, Gc = g->bt_c / tc;
     if (Grm < 1 || Grd < 1 || Gc < 1) return fail(BTTB_EINVAL, "group: threads per block below one transform");
     const int nch = std::min(g->nchunk, std::min(P->nz, P->nchunk_max));
@@ -162,7 +90,9 @@ static int layout(Group* g) {
       C.start[C.count + 1] = (int)nb;
       C.count += 1;
       C.lds = std::max(C.lds, l[st]);
-      if (C.lds > 160 * 1024) return fail(BTTB_EINVAL, "group: launch shape needs more LDS than a CU has");
+      // (a 5-smooth size's kernels also hold its twiddle table in static LDS)
+      const size_t stat = (pow2(C.N) ? 0 : (size_t)C.N * 2 * esz) + 2048;
+      if (C.lds + stat > 160 * 1024) return fail(BTTB_EINVAL, "group: launch shape needs more LDS than a CU has");
       g->blocks[st] += (int)b[st];
     }
   }
@@ -184,14 +114,14 @@ static int upload_members(Group* g, hipStream_t s) {
   return BTTB_OK;
 }
 
-static int check_threads(const Group* g, int rm, int rd, int c) {
+static int check_threads(const Group* g, int rm, int rd, int c) {  // (powers of two >= N/8 of every member)
   const int cmax = g->precision == BTTB_F64 ? 256 : 512;
   if (!pow2(rm) || !pow2(rd) || !pow2(c) || rm > 512 || rd > 512 || c > cmax)
     return fail(BTTB_EINVAL, "group: threads per block must be powers of two <= 512 (columns: <= 256 in FP64)");
   for (int i = 0; i < g->count; ++i) {
     const Plan* P = g->P[i];
-    if (rm < P->Py / 8 || rd < P->Py / 8 || c < P->Px / 8)
-      return fail(BTTB_EINVAL, "group: threads per block below a member's transform (N / 8)");
+    if (rm < lanes(P->Py) || rd < lanes(P->Py) || c < lanes(P->Px))
+      return fail(BTTB_EINVAL, "group: threads per block below a member's transform (N / 8 rounded up to a power of two)");
   }
   return BTTB_OK;
 }
@@ -225,23 +155,6 @@ static GLaunch<T> launch_of(const Group* g, int st, const GClass& C, const Fuse<
     default: return fail(BTTB_ESIZE, "group: transform size out of range"); \
   }
 
-// The kernel of stage st at transform size N (in the CG step's fused form when fused).
-template <typename T, int N, bool H>
-static auto stage_kernel_h(int st, bool fused) -> void (*)(GLaunch<T>) {
-  switch (st) {
-    case GS_F1: return fused ? k_grow_r2c<T, N, false, FUSE_DIR, H> : k_grow_r2c<T, N, false, FUSE_NONE, H>;
-    case GS_F2: return k_gcol<T, N, true, H>;
-    case GS_F3: return fused ? k_grow_c2r<T, N, true, FUSE_QQ, H> : k_grow_c2r<T, N, true, FUSE_NONE, H>;
-    case GS_T1: return k_grow_r2c<T, N, true, FUSE_NONE, H>;
-    case GS_T2: return k_gcol<T, N, false, H>;
-    default: return fused ? k_grow_c2r<T, N, false, FUSE_GRAD, H> : k_grow_c2r<T, N, false, FUSE_NONE, H>;
-  }
-}
-template <typename T, int N>
-static auto stage_kernel(int st, bool fused, bool half) -> void (*)(GLaunch<T>) {
-  return half ? stage_kernel_h<T, N, true>(st, fused) : stage_kernel_h<T, N, false>(st, fused);
-}
-
 template <typename T>
 int group_apply_impl(const Group* g_, int op, const void* const* in, void* const* out, const void* const* winv,
                      const void* const* wd, const Fuse<T>* fz, hipStream_t s, int skip_first,
@@ -266,9 +179,14 @@ int group_apply_impl(const Group* g_, int op, const void* const* in, void* const
         const GClass& C = g->cls[st][c];
         const GLaunch<T> L = launch_of<T>(g, st, C, fzr, in, out, winv, wd);
         void (*kern)(GLaunch<T>) = nullptr;
+        if (pow2(C.N)) {
 #define BTTB_K(NN) kern = stage_kernel<T, NN>(st, fz != nullptr, C.half != 0)
-        BTTB_GROUP_SIZES(C.N, BTTB_K)
+          BTTB_GROUP_SIZES(C.N, BTTB_K)
 #undef BTTB_K
+        } else {
+          kern = stage_kernel_mixed<T>(C.N, st, fz != nullptr, C.half != 0);
+        }
+        if (!kern) return fail(BTTB_ESIZE, "group: no kernel for this transform size and form");
         hipLaunchKernelGGL(kern, dim3(C.start[C.count]), dim3(L.bt), C.lds, s, L);
         BTTB_LAUNCHED("group stage");
       }
@@ -298,7 +216,7 @@ int group_stage_launch(const Group* g, int st, int bt, const Fuse<T>* fz, const 
                        int* half, size_t* lds) {
   if (g->ncls[st] != 1) return BTTB_ESTATE;  // several transform sizes or half forms
   const GClass& C0 = g->cls[st][0];
-  const int tr = C0.N / 8;
+  const int tr = lanes(C0.N);
   if (bt < tr || bt % tr) return BTTB_ESTATE;
   const int G = bt / tr;
   const size_t esz = g->precision == BTTB_F64 ? 8 : 4;
@@ -356,12 +274,21 @@ int group_set_launch(Group* g, int rm, int rd, int c, int nchunk, hipStream_t s)
   return rc;
 }
 
+// A plan can join a group when each transform size is a power of two from 32 to 2048 (the
+// register FFT), or a 5-smooth size with group kernels (mixed_size) whose rows and columns (model
+// and data side) fill at most half of it.
+bool group_member_ok(const Plan* P) {
+  auto size_ok = [](int N, bool half) { return pow2(N) ? (N >= 32 && N <= 2048) : (mixed_size(N) && half); };
+  return size_ok(P->Px, 2 * P->nx <= P->Px && 2 * P->sx <= P->Px) &&
+         size_ok(P->Py, 2 * P->ny <= P->Py && 2 * P->sy <= P->Py);
+}
+
 // Largest transforms of the members decide the default shape: one FFT per 64 lanes or more.
 static void default_shape(Group* g) {
   int tr = 1, tc = 1;
   for (int i = 0; i < g->count; ++i) {
-    tr = std::max(tr, g->P[i]->Py / 8);
-    tc = std::max(tc, g->P[i]->Px / 8);
+    tr = std::max(tr, lanes(g->P[i]->Py));
+    tc = std::max(tc, lanes(g->P[i]->Px));
   }
   g->bt_rm = std::max(512, tr);  // 16-row tiles: whole 128-byte segments in the transposed stores
   g->bt_rd = std::max(64, tr);
@@ -381,10 +308,11 @@ int group_create(const bttb_plan* plans, int count, void* stream, Group** out) {
       delete g;
       return fail(BTTB_EINVAL, "bttb_group_create: NULL plan");
     }
-    if (!P->fast || P->Px < 32 || P->Py < 32) {
+    if (!group_member_ok(P)) {
       delete g;
-      return fail(BTTB_ESTATE, "bttb_group_create: members need power-of-two transforms of at least 32 "
-                               "(bttb_setup with BTTB_PAD_POW2)");
+      return fail(BTTB_ESTATE, "bttb_group_create: a member's transform sizes must be powers of two from 32 "
+                               "(bttb_setup with BTTB_PAD_POW2), or 5-smooth sizes up to 640 whose rows and "
+                               "columns fill at most half of them");
     }
     if (i > 0 && P->precision != g->P[0]->precision) {
       delete g;

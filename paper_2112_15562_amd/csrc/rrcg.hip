@@ -17,8 +17,10 @@
 //   m <- clip(m, lo, hi)                                                  k_clip
 //   r~ = W_d (A m - d), Phi = ||r~||^2, chi^2 test, alpha <- max(q alpha, alpha_min)
 //   unless frozen                                                         k_resid
-// On power-of-two plans the gradient, direction and ||q||^2 are computed inside the
-// products' row transforms; otherwise by the bracketed elementwise kernels.  Dot
+// On plans that can join a product group (power-of-two transforms, or 5-smooth ones whose rows
+// and columns fill at most half of them) the step runs as a one-inversion group solver, with the
+// gradient, direction and ||q||^2 computed inside the products' row transforms; otherwise by the
+// bracketed elementwise kernels.  Dot
 // products are accumulated in FP64 per block and summed in a fixed order by the last
 // block to finish, so results are bitwise repeatable; no scalar leaves the device
 // during a step.
@@ -30,6 +32,7 @@
 #include <new>
 
 #include "common.h"
+#include "group.h"
 #include "rrcg_fuse.h"
 #include "rrcg_kernels.h"
 
@@ -311,7 +314,7 @@ extern "C" int rrcg_create(const rrcg_desc* d, void* stream, rrcg_handle* out) {
   }
   Rrcg* h = new (std::nothrow) Rrcg{};
   if (!h) return fail(BTTB_ENOMEM, "rrcg_create: host allocation failed");
-  if (P0->fast && P1->fast && P0->Px >= 32 && P0->Py >= 32) {
+  if (group_member_ok(P0) && group_member_ok(P1)) {
     // both operators' products in one launch per stage, the CG pieces fused into them
     const int rc = rrcg_group_create(d, 1, stream, &h->grp);
     if (rc != BTTB_OK) {
@@ -463,7 +466,7 @@ extern "C" int rrcg_prepare(rrcg_handle hh, int n_inner) {
 extern "C" int rrcg_autotune(rrcg_handle hh, int reps, void* stream, bttb_tune_result* out) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h) return fail(BTTB_EINVAL, "rrcg_autotune: NULL handle");
-  if (!h->grp) return fail(BTTB_ESTATE, "rrcg_autotune: the plans are not power-of-two plans (tune them with "
+  if (!h->grp) return fail(BTTB_ESTATE, "rrcg_autotune: the plans cannot join a product group (tune them with "
                                         "bttb_autotune before creating the solver)");
   return rrcg_group_autotune(h->grp, reps, stream, out);
 }
@@ -472,7 +475,7 @@ extern "C" int rrcg_products(rrcg_handle hh, bttb_group* out) {
   Rrcg* h = reinterpret_cast<Rrcg*>(hh);
   if (!h || !out) return fail(BTTB_EINVAL, "rrcg_products: NULL argument");
   *out = nullptr;
-  if (!h->grp) return fail(BTTB_ESTATE, "rrcg_products: the plans are not power-of-two plans");
+  if (!h->grp) return fail(BTTB_ESTATE, "rrcg_products: the plans cannot join a product group");
   return rrcg_group_products(h->grp, out);
 }
 

@@ -455,9 +455,10 @@ static int g_tables(RrcgGroup* h, const rrcg_desc* descs, hipStream_t s) {
     GLaunch<T> L{};
     int nt1 = 0, N = 0, half = 0;
     size_t lds = 0;
+    // (power-of-two data rows only: the fused kernel is not compiled for the 5-smooth sizes)
     h->fuse_t1 = sizeof(T) == 4 && group_stage_launch<T>(h->grp, GS_T1, eb_threads(sizeof(T)), nullptr, nullptr,
                                                          nullptr, nullptr, nullptr, &L, &nt1, &N, &half,
-                                                         &lds) == BTTB_OK;
+                                                         &lds) == BTTB_OK && (N & (N - 1)) == 0;
   }
   BTTB_HIP(hipMemcpyAsync(h->inv, inv, sizeof(GInv<T>) * h->count, hipMemcpyHostToDevice, s));
   for (int r = 0; r < 4; ++r)

@@ -218,8 +218,10 @@ def pointer_array(tensors, device) -> torch.Tensor:
 
 class Group:
     """The products of many operators (e.g. gravity and magnetic of many inversions of
-    uneven sizes) in one kernel launch per stage.  Members must be power-of-two plans
-    (Operator(..., pad_pow2=True)) of one dtype; the operators must stay open."""
+    uneven sizes) in one kernel launch per stage per transform size.  Members share one dtype,
+    and each transform size is a power of two from 32 (Operator(..., pad_pow2=True)) or a
+    5-smooth size up to 640 whose rows and columns fill at most half of it (the default padding
+    of stations over prism centres); the operators must stay open."""
 
     def __init__(self, ops: Sequence[Operator]):
         ops = list(ops)

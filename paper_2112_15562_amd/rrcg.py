@@ -135,15 +135,15 @@ class JointRRCG:
         L.check(L.lib().rrcg_prepare(self._h, int(n_inner)), "rrcg_prepare")
 
     def autotune(self, reps: int = 3) -> dict:
-        """Choose the launch shape of the solver's products by timing CG steps (power-of-two
-        plans); the solver state is restored afterwards."""
+        """Choose the launch shape of the solver's products by timing CG steps (plans that can
+        join a product group); the solver state is restored afterwards."""
         from .operator import _tune_dict
         r = L.TuneResult()
         L.check(L.lib().rrcg_autotune(self._h, int(reps), C.c_void_p(self._stream()), C.byref(r)), "rrcg_autotune")
         return _tune_dict(r)
 
     def products(self) -> Optional[Group]:
-        """The product group the solver runs on (power-of-two plans), as a non-owning view
+        """The product group the solver runs on (plans that can join one), as a non-owning view
         valid while the solver is open; None for other plans."""
         g = C.c_void_p()
         if L.lib().rrcg_products(self._h, C.byref(g)) != L.BTTB_OK:
@@ -222,7 +222,7 @@ class JointRRCGGroup:
     outer step is one launch over all of them.  problems: sequence of dicts with the
     arguments of JointRRCG (ops, dobs, wd, wdepth and optionally whard, mapr and any solver
     parameter); `defaults` fills parameters a problem does not give.  The operators must be
-    power-of-two plans (Operator(..., pad_pow2=True)) of one dtype."""
+    plans that can join a product group (see Group) of one dtype."""
 
     def __init__(self, problems, use_graph: bool = True, **defaults):
         self.inv = []

@@ -55,7 +55,7 @@ def lambda_scan(kernels, data_shape, dobs, wd, wdepth, lams, *, n_outer: int, n_
     records = []
     for c0 in range(0, len(lams), MAX_GROUP):
         part = lams[c0:c0 + MAX_GROUP]
-        ops_all = [[Operator(ktens[i], tuple(data_shape), dtype=dtype, pad_pow2=True) for i in range(2)]
+        ops_all = [[Operator(ktens[i], tuple(data_shape), dtype=dtype) for i in range(2)]
                    for _ in part]
         probs = [dict(ops=ops, dobs=dobs, wd=wd, wdepth=wdepth, whard=whard, mapr=mapr, lam=lam)
                  for ops, lam in zip(ops_all, part)]

@@ -147,7 +147,8 @@ def test_group_rejects_bad_members_and_shapes(pk):
     from paper_2112_15562_amd import _lib as L
     T = torch.as_tensor(oracle_case(0)[0], device="cuda")
     g = MEMBERS[0][1]
-    radix3 = pk.Operator(torch.zeros((2, 23, 23), dtype=torch.float64, device="cuda"), (12, 12))  # 24 x 24
+    # 16 stations over 8 prism columns on a 24-point circle: 2 sx > 24, so no half form
+    radix3 = pk.Operator(torch.zeros((2, 23, 23), dtype=torch.float64, device="cuda"), (16, 16))
     a = pk.Operator(T, (g.sx, g.sy), dtype=torch.float64, pad_pow2=True)
     b = pk.Operator(T, (g.sx, g.sy), dtype=torch.float32, pad_pow2=True)
     assert a.info()["Px"] == 32 and radix3.info()["Px"] == 24
@@ -200,6 +201,68 @@ def test_group_apply_checks_every_vector(pk):
     ref0 = ops[0].matvec(x[0], wd=wd[0])
     ref1 = ops[1].matvec(x[1], winv=wi[1])
     assert rel(host(ys[0]), host(ref0)) <= 1e-12 and rel(host(ys[1]), host(ref1)) <= 1e-12
+    grp.close()
+    for op in ops:
+        op.close()
+
+
+# ------------------------------------------------------------------------------------
+# 5-smooth transform sizes (no power-of-two padding): radix-3 and radix-5 passes
+# ------------------------------------------------------------------------------------
+MIXED = [
+    (oprism.GRAVITY, synth.Grid(12, 12, 12, 12, 6, 50.0, 50.0, 50.0)),                # 24 = 8 3
+    (oprism.MAGNETIC, synth.Grid(20, 20, 20, 20, 4, 40.0, 40.0, 25.0)),               # 40 = 8 5
+    (oprism.MAGNETIC, synth.Grid(36, 30, 36, 30, 5, 40.0, 45.0, 25.0, decl=15.0)),    # 72 x 64
+    (oprism.GRAVITY, synth.Grid(16, 16, 16, 16, 8, 50.0, 50.0, 50.0)),                # 32: a power of two
+    (oprism.GRAVITY, synth.Grid(60, 60, 60, 60, 5, 40.0, 40.0, 25.0)),                # 120 = 8 3 5
+    (oprism.MAGNETIC, synth.Grid(100, 100, 100, 100, 6, 40.0, 40.0, 25.0)),           # 200 = 8 5 5
+    (oprism.MAGNETIC, synth.Grid(108, 108, 108, 108, 4, 40.0, 40.0, 25.0)),           # 216 = 8 27
+]
+_MCACHE = {}
+
+
+def mixed_case(idx):
+    if idx in _MCACHE:
+        return _MCACHE[idx]
+    kind, g = MIXED[idx]
+    og = oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+    T = obttb.kernel_array(kind, og)
+    x = synth.rng(7, idx).uniform(0.0, 1.0, g.model_shape)
+    r = synth.rng(7, 100 + idx).standard_normal(g.data_shape)
+    winv = synth.rng(7, 200 + idx).uniform(0.5, 2.0, g.model_shape)
+    wd = synth.rng(7, 300 + idx).uniform(0.5, 2.0, g.data_shape)
+    _MCACHE[idx] = (T, x, r, winv, wd, obttb.fft_matvec(T, x, g.sx, g.sy), obttb.fft_rmatvec(T, r, g.sx, g.sy),
+                    obttb.weighted_matvec(T, x, winv, wd, g.sx, g.sy),
+                    obttb.weighted_rmatvec(T, r, winv, wd, g.sx, g.sy))
+    return _MCACHE[idx]
+
+
+@pytest.mark.parametrize("shape", [None, (512, 256, 512, 2), (128, 64, 128, 1)], ids=["default", "wide", "narrow"])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_group_products_at_5smooth_sizes(pk, dtype, tol, shape):
+    ops = []
+    for i, (kind, g) in enumerate(MIXED):
+        ops.append(pk.Operator(torch.as_tensor(mixed_case(i)[0], device="cuda"), (g.sx, g.sy), dtype=dtype))
+    sizes = [(op.info()["Px"], op.info()["Py"]) for op in ops]
+    assert sizes == [(24, 24), (40, 40), (72, 64), (32, 32), (120, 120), (200, 200), (216, 216)]
+    grp = pk.Group(ops)
+    if shape is not None:
+        if dtype == torch.float64:
+            shape = (shape[0], shape[1], min(shape[2], 256), shape[3])
+        grp.set_launch(*shape)
+    print(f"{dtype} launch {grp.info()}", flush=True)
+    dev = lambda a: torch.as_tensor(a, dtype=dtype, device="cuda")
+    xs = [dev(mixed_case(i)[1]) for i in range(len(ops))]
+    rs = [dev(mixed_case(i)[2]) for i in range(len(ops))]
+    wi = [dev(mixed_case(i)[3]) for i in range(len(ops))]
+    wd = [dev(mixed_case(i)[4]) for i in range(len(ops))]
+    ys, zs = grp.matvec(xs), grp.rmatvec(rs)
+    yw, zw = grp.matvec(xs, winv=wi, wd=wd), grp.rmatvec(rs, winv=wi, wd=wd)
+    for i in range(len(ops)):
+        c = mixed_case(i)
+        errs = [rel(host(ys[i]), c[5]), rel(host(zs[i]), c[6]), rel(host(yw[i]), c[7]), rel(host(zw[i]), c[8])]
+        print(f"  member {i} {sizes[i]}: rel errs {['%.1e' % e for e in errs]}", flush=True)
+        assert max(errs) <= tol, (i, errs)
     grp.close()
     for op in ops:
         op.close()

@@ -95,9 +95,13 @@ VARIANTS = [
 ]
 
 
-# SMALL (transform 32): the CG pieces ride on the products' row transforms;
-# SUB (transform 24, radix 3): separate elementwise kernels
-@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB], ids=["pow2-fused", "radix3"])
+# SMALL (transform 32) and SUB (transform 24 = 8 3, a radix-3 pass): the CG pieces ride on the
+# products' row transforms (group path); RAGGED (24 x 16 with 9 stations per 16-point row, which
+# has no half form): the general kernels and separate elementwise kernels
+RAGGED = synth.Grid(7, 9, 11, 5, 3, 40.0, 30.0, 25.0, decl=20.0)
+
+
+@pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED], ids=["pow2-fused", "radix3-fused", "general"])
 @pytest.mark.parametrize("var", range(len(VARIANTS)))
 def test_single_outer_step_parity_fp64(pk, var, g):
     ops, T, data, _ = problem(g, dense=True)

@@ -146,3 +146,39 @@ def test_group_launch_shape_recaptures(pk, how):
             assert rel(host(grp.inv[i].m[k]), host(ref.inv[i].m[k])) <= 1e-12
     grp.close()
     ref.close()
+
+
+# five inversions whose plans keep their 5-smooth transform sizes (24, 40, 72 x 64, 32, 120):
+# every phase one launch per size class, the CG pieces fused into the 5-smooth transforms too
+MIXED_GRIDS = [synth.SUB, synth.Grid(20, 20, 20, 20, 4, 40.0, 40.0, 25.0),
+               synth.Grid(36, 30, 36, 30, 5, 40.0, 45.0, 25.0, decl=15.0), synth.SMALL,
+               synth.Grid(60, 60, 60, 60, 5, 40.0, 40.0, 25.0)]
+
+
+@pytest.mark.parametrize("dtype,tol_m", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_group_step_parity_at_5smooth_sizes(pk, dtype, tol_m):
+    probs, expected = [], []
+    for idx, (g, v) in enumerate(zip(MIXED_GRIDS, VARIANTS)):
+        ops, T, data, _ = problem(g, dense=g.nx <= 36)
+        prm = params(v)
+        gops = [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=dtype) for i in range(2)]
+        probs.append(dict(ops=gops, dobs=data.dobs, wd=data.wd, wdepth=data.wdepth, **solver_kwargs(prm)))
+        st, _ = orrcg.run(ops, data, prm, n_outer=2, n_inner=N_INNER)
+        ref, rec = orrcg.outer_step(ops, data, prm, st, N_INNER)
+        expected.append((st, ref, rec, gops))
+    assert [op.info()["Px"] for _, _, _, ops in expected for op in ops[:1]] == [24, 40, 72, 32, 120]
+    grp = pk.JointRRCGGroup(probs)
+    for i, (st, _, _, _) in enumerate(expected):
+        set_state(grp, i, st, dtype)
+    grp.refresh()
+    grp.step(N_INNER)
+    for i, (_, ref, rec, _) in enumerate(expected):
+        sc = grp.scalars(i)
+        errs = [rel(host(grp.inv[i].m[k]), ref.m[k]) for k in range(2)]
+        print(f"{dtype} inversion {i}: model rel err {errs}", flush=True)
+        assert max(errs) <= tol_m, (i, errs)
+        for k in range(2):
+            assert sc["phi"][k] == pytest.approx(rec["phi"][k], rel=tol_m * 10)
+            assert sc["alpha"][k] == pytest.approx(ref.alpha[k], rel=1e-15)
+        assert sc["k"] == ref.k and not sc["nonfinite"]
+    grp.close()
