@@ -132,9 +132,10 @@ def batched_workload(pk, torch):
     """16 independent joint inversions, n = nx = ny ~ U{64..320}, nz ~ U{16..40}, stepped
     together by the group solver (one launch per phase and transform size for all of them, HIP
     graphs, autotuned launch shapes), FP32 with FP64 reductions; 5 outer x 10 inner steps, on the
-    5-smooth transform sizes (no power-of-two padding).  Beside it: the same group on
-    power-of-two transforms, and the inversions solved one after another by one-inversion
-    solvers (5-smooth transforms, each tuned)."""
+    transform sizes of least estimated cost (BTTB_PAD_AUTO: powers of two, or 5-smooth sizes with
+    one pass through LDS).  Beside it: the same group on the smallest 5-smooth sizes and on
+    powers of two, and the inversions solved one after another by one-inversion solvers (the
+    same sizes, each tuned)."""
     import synth
     grids = synth.uneven_sizes(16)
     prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.95, 0.95), lam=(2.0, 100.0),
@@ -156,8 +157,8 @@ def batched_workload(pk, torch):
         kern.append(T)
     pairs = len(grids) * 2 * BATCH_INNER * BATCH_OUTER
 
-    def make_ops(pad_pow2):
-        return [[pk.Operator(kern[j][i], (g.sx, g.sy), dtype=torch.float32, pad_pow2=pad_pow2) for i in range(2)]
+    def make_ops(pad):
+        return [[pk.Operator(kern[j][i], (g.sx, g.sy), dtype=torch.float32, pad=pad) for i in range(2)]
                 for j, g in enumerate(grids)]
 
     def close(opss):
@@ -165,8 +166,8 @@ def batched_workload(pk, torch):
             for op in ops:
                 op.close()
 
-    def group_run(pad_pow2):
-        opss = make_ops(pad_pow2)
+    def group_run(pad):
+        opss = make_ops(pad)
         grp = pk.JointRRCGGroup([dict(ops=opss[j], **data[j]) for j in range(len(grids))], **prm)
         tune = grp.autotune(reps=5)
         grp.step(BATCH_INNER)  # warm-up outer step (also captures its graph)
@@ -186,10 +187,11 @@ def batched_workload(pk, torch):
                                                       "layer_chunks")},
                 "autotune_candidates": tune["tried"]}, chi
 
-    group5, chi = group_run(False)
-    group2, _ = group_run(True)
-    # the same inversions one at a time (5-smooth transforms; each solver tuned on its own first)
-    opss = make_ops(False)
+    group_a, chi = group_run("auto")
+    group5, _ = group_run("smooth")
+    group2, _ = group_run("pow2")
+    # the same inversions one at a time (the same sizes; each solver tuned on its own first)
+    opss = make_ops("auto")
     t_seq, lat = 0.0, []
     for j in range(len(grids)):
         s1 = pk.JointRRCG(opss[j], **data[j], **prm)
@@ -210,12 +212,13 @@ def batched_workload(pk, torch):
                     f"nz = {min(g.nz for g in grids)}..{max(g.nz for g in grids)}, {BATCH_OUTER} outer x "
                     f"{BATCH_INNER} inner, FP32 with FP64 reductions",
         "sizes": [[g.nx, g.nz] for g in grids],
-        "group": group5,
+        "group": group_a,
+        "group_5smooth_padding": group5,
         "group_pow2_padding": group2,
         "sequential": {"op_pairs_per_s": pairs / t_seq, "solve_s": t_seq,
                        "per_inversion_latency_s": {"min": min(lat), "max": max(lat),
                                                    "mean": sum(lat) / len(lat)}},
-        "group_vs_sequential": t_seq / group5["solve_s"],
+        "group_vs_sequential": t_seq / group_a["solve_s"],
         "phi_after": [[round(a, 1) for a in c] for c in chi],
     }
 

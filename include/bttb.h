@@ -75,6 +75,12 @@ typedef enum { BTTB_F64 = 0, BTTB_F32 = 1 } bttb_precision;
  * smallest 5-smooth multiples of 8, so that the plan takes the register-FFT kernels of the
  * one-plan products.  (Groups and solvers also take 5-smooth plans: see bttb_group_create.) */
 #define BTTB_PAD_POW2 0x10
+/* Flag or-ed into bttb_setup's precision (not with BTTB_PAD_POW2): for each axis, the transform size
+ * of least estimated cost for products in a group -- the next power of two (>= 32) or a 5-smooth
+ * size below it that the group kernels cover, weighing each size's points by a cost factor of its
+ * pass plan (1 for a power of two, from 1.5 for 5-smooth ones).  For uneven batches, where the
+ * power-of-two padding of some grids is up to 4 times the area. */
+#define BTTB_PAD_AUTO 0x40
 /* Flag or-ed into bttb_setup's precision: keep the full complex eigenvalues even when the
  * operator is symmetric.  Without it, a power-of-two plan whose eigenvalues are real and
  * even along x to 1e-14 (FP64) / 1e-6 (FP32) of their largest magnitude -- the case of a

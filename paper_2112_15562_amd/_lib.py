@@ -17,6 +17,7 @@ BTTB_GRAVITY, BTTB_MAGNETIC = 0, 1
 BTTB_OP_FORWARD, BTTB_OP_ADJOINT = 0, 1
 BTTB_ANCHOR_APR, BTTB_ANCHOR_PREV = 0, 1
 BTTB_PAD_POW2 = 0x10
+BTTB_PAD_AUTO = 0x40
 BTTB_EIG_FULL = 0x20
 MAX_TRANSFORM = 2048
 NOALLOC_MAX_SCRATCH = 32 << 20

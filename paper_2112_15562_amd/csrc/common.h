@@ -69,6 +69,8 @@ inline int round_up(int a, int b) { return ceil_div(a, b) * b; }
 FFTDesc make_fft_desc(int N);
 // Smallest 5-smooth multiple of 8 that is >= L.
 int padded_size(int L);
+// BTTB_PAD_AUTO's size for a circle of L points spanning at most n of them (operator.hip).
+int auto_size(int L, int n);
 // Host table exp(-2 pi i e / N), e < N, in FP64 (argument reduced by octant symmetry).
 void twiddles_fp64(int N, double* re_im);
 

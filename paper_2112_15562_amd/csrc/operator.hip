@@ -24,6 +24,8 @@
 #include <vector>
 
 #include "common.h"
+#include "fft_reg.h"
+#include "group.h"
 
 namespace bttb {
 
@@ -40,6 +42,38 @@ int padded_size(int L) {
   int m = ceil_div(std::max(L, 1), 8);
   while (!smooth5(m)) ++m;
   return 8 * m;
+}
+
+// Relative cost of one point of a transform of size N in the register-layout kernels (products
+// and groups): 1 for a power of two; for the 5-smooth sizes of the group kernels, more with every
+// pass through LDS and when the last pass cannot run in registers (measured at 216..576 points:
+// 1.5 for one LDS pass with a register last pass, about 2.1-2.4 for two without).
+static double transform_cost(int N) {
+  if ((N & (N - 1)) == 0) return 1.0;
+  const MixPlan p = mix_plan(N);
+  const int last = p.radix[p.npass - 1];
+  const bool reg = last == 2 || last == 4 || last == 8;
+  const int lds = p.npass - 1 - (reg ? 1 : 0);
+  return 1.2 + 0.3 * lds + (reg ? 0.0 : 0.4);
+}
+
+// The size of BTTB_PAD_AUTO for a circle of L points whose stations and prisms span at most n of
+// them: among the next power of two >= L (at least 32) and the 5-smooth sizes in between that have
+// group kernels and hold n in their first half, the one with the least N sqrt(cost(N)), i.e. the
+// least estimated cost when both axes take it (N^2 points).
+int auto_size(int L, int n) {
+  int best = 32;
+  while (best < L) best <<= 1;
+  double best_cost = (double)best;
+  for (int N = 8 * ceil_div(L, 8); N < best; N += 8) {
+    if (!mixed_size(N) || 2 * n > N) continue;
+    const double c = N * std::sqrt(transform_cost(N));
+    if (c < best_cost) {
+      best_cost = c;
+      best = N;
+    }
+  }
+  return best;
 }
 
 FFTDesc make_fft_desc(int N) {
@@ -736,8 +770,10 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
   if (sx < 1 || sy < 1 || nx < 1 || ny < 1 || nz < 1 || max_batch < 1)
     return fail(BTTB_EINVAL, "bttb_setup: sizes must be >= 1");
   const bool pad_pow2 = (precision & BTTB_PAD_POW2) != 0;
+  const bool pad_auto = (precision & BTTB_PAD_AUTO) != 0;
   const bool eig_full = (precision & BTTB_EIG_FULL) != 0;
-  precision &= ~(BTTB_PAD_POW2 | BTTB_EIG_FULL);
+  precision &= ~(BTTB_PAD_POW2 | BTTB_PAD_AUTO | BTTB_EIG_FULL);
+  if (pad_pow2 && pad_auto) return fail(BTTB_EINVAL, "bttb_setup: BTTB_PAD_POW2 and BTTB_PAD_AUTO exclude each other");
   if (precision != BTTB_F64 && precision != BTTB_F32) return fail(BTTB_EINVAL, "bttb_setup: bad precision");
   const long long Lx = (long long)sx + nx - 1, Ly = (long long)sy + ny - 1;
   if (Lx > BTTB_MAX_TRANSFORM || Ly > BTTB_MAX_TRANSFORM)
@@ -747,8 +783,8 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
     while (v < L) v <<= 1;
     return v;
   };
-  const int Px = pad_pow2 ? pow2_size(Lx) : padded_size((int)Lx);
-  const int Py = pad_pow2 ? pow2_size(Ly) : padded_size((int)Ly);
+  const int Px = pad_pow2 ? pow2_size(Lx) : pad_auto ? auto_size((int)Lx, std::max(sx, nx)) : padded_size((int)Lx);
+  const int Py = pad_pow2 ? pow2_size(Ly) : pad_auto ? auto_size((int)Ly, std::max(sy, ny)) : padded_size((int)Ly);
   if (Px > BTTB_MAX_TRANSFORM || Py > BTTB_MAX_TRANSFORM)
     return fail(BTTB_ESIZE, "bttb_setup: padded transform size exceeds the maximum");
   hipStream_t s = static_cast<hipStream_t>(stream);

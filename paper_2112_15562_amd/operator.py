@@ -54,12 +54,16 @@ class Operator:
     stations: (sx, sy); the prism grid follows from the kernel array's shape.
     dtype: torch.float64 (plain FP64 path) or torch.float32 (FFTs and products in FP32,
     eigenvalues computed in FP64 and rounded).
+    pad: "smooth" (the smallest 5-smooth multiple of 8 >= sx+nx-1, sy+ny-1), "pow2" (powers of two,
+    at least 32; also pad_pow2=True) or "auto" (per axis the power of two or 5-smooth size of least
+    estimated cost in the group kernels).
     full_eig: keep the complex eigenvalues of a symmetric operator (by default a power-of-two
     plan stores only the real, x-even half of them; info()["eig_real_even"]).
     """
 
     def __init__(self, kernels: torch.Tensor, stations: Sequence[int], dtype=torch.float64,
-                 max_batch: int = 1, device="cuda", pad_pow2: bool = False, full_eig: bool = False):
+                 max_batch: int = 1, device="cuda", pad_pow2: bool = False, full_eig: bool = False,
+                 pad: str = "smooth"):
         if dtype not in _DT:
             raise TypeError("dtype must be torch.float32 or torch.float64")
         self.device = torch.device(device)
@@ -77,17 +81,21 @@ class Operator:
         self.dtype = dtype
         self.max_batch = int(max_batch)
         self._plan = C.c_void_p()
-        flags = _DT[dtype] | (L.BTTB_PAD_POW2 if pad_pow2 else 0) | (L.BTTB_EIG_FULL if full_eig else 0)
+        if pad not in ("smooth", "pow2", "auto"):
+            raise ValueError("pad must be 'smooth', 'pow2' or 'auto'")
+        pad = "pow2" if pad_pow2 else pad
+        flags = (_DT[dtype] | {"smooth": 0, "pow2": L.BTTB_PAD_POW2, "auto": L.BTTB_PAD_AUTO}[pad]
+                 | (L.BTTB_EIG_FULL if full_eig else 0))
         L.check(L.lib().bttb_setup(_ptr(k), sx, sy, nx, ny, nz, flags, self.max_batch,
                                    C.c_void_p(_stream(self.device)), C.byref(self._plan)), "bttb_setup")
 
     @classmethod
     def from_geometry(cls, kind: int, geometry, dtype=torch.float64, max_batch: int = 1, device="cuda",
-                      pad_pow2: bool = False, full_eig: bool = False):
+                      pad_pow2: bool = False, full_eig: bool = False, pad: str = "smooth"):
         T = prism_kernels(kind, geometry, device)
         g = _geometry(geometry)
         return cls(T, (g.sx, g.sy), dtype=dtype, max_batch=max_batch, device=device, pad_pow2=pad_pow2,
-                   full_eig=full_eig)
+                   full_eig=full_eig, pad=pad)
 
     # ------------------------------------------------------------------------------
     @property

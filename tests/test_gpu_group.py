@@ -217,6 +217,10 @@ MIXED = [
     (oprism.GRAVITY, synth.Grid(60, 60, 60, 60, 5, 40.0, 40.0, 25.0)),                # 120 = 8 3 5
     (oprism.MAGNETIC, synth.Grid(100, 100, 100, 100, 6, 40.0, 40.0, 25.0)),           # 200 = 8 5 5
     (oprism.MAGNETIC, synth.Grid(108, 108, 108, 108, 4, 40.0, 40.0, 25.0)),           # 216 = 8 27
+    (oprism.GRAVITY, synth.Grid(144, 144, 144, 144, 3, 40.0, 40.0, 25.0)),            # 288: 8, 9, 4
+    (oprism.MAGNETIC, synth.Grid(192, 192, 192, 192, 3, 40.0, 40.0, 25.0)),           # 384: 8, 6, 8
+    (oprism.MAGNETIC, synth.Grid(288, 288, 288, 288, 2, 40.0, 40.0, 25.0)),           # 576: 8, 9, 8
+    (oprism.GRAVITY, synth.Grid(320, 320, 320, 320, 2, 40.0, 40.0, 25.0)),            # 640: 8, 10, 8
 ]
 _MCACHE = {}
 
@@ -237,19 +241,23 @@ def mixed_case(idx):
     return _MCACHE[idx]
 
 
-@pytest.mark.parametrize("shape", [None, (512, 256, 512, 2), (128, 64, 128, 1)], ids=["default", "wide", "narrow"])
+@pytest.mark.parametrize("shape", [None, (512, 256, 512, 2), (128, 128, 128, 1)], ids=["default", "wide", "narrow"])
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_group_products_at_5smooth_sizes(pk, dtype, tol, shape):
     ops = []
     for i, (kind, g) in enumerate(MIXED):
         ops.append(pk.Operator(torch.as_tensor(mixed_case(i)[0], device="cuda"), (g.sx, g.sy), dtype=dtype))
     sizes = [(op.info()["Px"], op.info()["Py"]) for op in ops]
-    assert sizes == [(24, 24), (40, 40), (72, 64), (32, 32), (120, 120), (200, 200), (216, 216)]
+    assert sizes == [(24, 24), (40, 40), (72, 64), (32, 32), (120, 120), (200, 200), (216, 216), (288, 288),
+                     (384, 384), (576, 576), (640, 640)]
     grp = pk.Group(ops)
     if shape is not None:
         if dtype == torch.float64:
             shape = (shape[0], shape[1], min(shape[2], 256), shape[3])
         grp.set_launch(*shape)
+    # 640-point rows take 80 lanes, padded to 128: fewer threads per block are refused
+    with pytest.raises(pk.BTTBError):
+        grp.set_launch(128, 64, 128, 1)
     print(f"{dtype} launch {grp.info()}", flush=True)
     dev = lambda a: torch.as_tensor(a, dtype=dtype, device="cuda")
     xs = [dev(mixed_case(i)[1]) for i in range(len(ops))]
@@ -266,3 +274,16 @@ def test_group_products_at_5smooth_sizes(pk, dtype, tol, shape):
     grp.close()
     for op in ops:
         op.close()
+
+
+def test_auto_padding_chooses_cheaper_sizes(pk):
+    # BTTB_PAD_AUTO: per axis the power of two or a 5-smooth size of least estimated cost; for
+    # grids just above a power of two the 5-smooth sizes with one pass through LDS win
+    expect = {178: 384, 101: 256, 266: 576, 320: 640, 136: 288, 244: 512}
+    for n, P in expect.items():
+        T = torch.zeros((1, 2 * n - 1, 2 * n - 1), dtype=torch.float64, device="cuda")
+        op = pk.Operator(T, (n, n), dtype=torch.float32, pad="auto")
+        assert (op.info()["Px"], op.info()["Py"]) == (P, P), n
+        op.close()
+    with pytest.raises(ValueError):
+        pk.Operator(torch.zeros((1, 7, 7), dtype=torch.float64, device="cuda"), (4, 4), pad="bad")
