@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "eda652b17070804f3bcdf0b4147d426c07a2d8cb158008bbf133cbe28cb38acc",
+    "csrc_sha256": "fc1fe9349502a2fe07f1e14307a8d9e42fcb83a11a139fa76710e39c12d5ff3e",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50671947, 50528423), "fwd_col_eig_sum": (77057260, 4698076),
-        "fwd_row_c2r": (2268379, 532512), "adj_row_r2c": (675547, 1064960),
-        "adj_col_conj_eig": (52041137, 33685504), "adj_row_c2r": (70374215, 16810083),
+        "fwd_row_r2c": (50684463, 50528320), "fwd_col_eig_sum": (77056787, 4210688),
+        "fwd_row_c2r": (1769384, 532512), "adj_row_r2c": (1198021, 1064960),
+        "adj_col_conj_eig": (52012653, 33685504), "adj_row_c2r": (70479961, 16810048),
     },
 }
 
@@ -225,13 +225,16 @@ def batched_workload(pk, torch):
 
 SCAN_LAMS = [(0.0, 0.0)] + [(10.0 ** k, 50.0 * 10.0 ** k) for k in range(1, 8)]  # lambda2 = 50 lambda1
 SCAN_OUTER, SCAN_INNER = 30, 10
+SCAN_SIM_MIN = 0.9
 
 
 def scan_workload(pk, torch):
     """The Lagrange-parameter scan: one joint inversion per fixed (lambda1, lambda2) pair of
     SCAN_LAMS on the 128x128x24 random-box problem, all runs in one group solver, FP32 with FP64
     reductions; SCAN_OUTER x SCAN_INNER steps per run (a run stops counting at its chi^2 test).
-    The time covers the whole call: plan setup for every run, the steps and the choice."""
+    The time covers the whole call: plan setup for every run, the steps and the choice.
+    Run twice: with the joint step length and direction scalars of RRCG:5-6 (the stacked system's
+    norms), and with per-data-set scalars (the Gramian still couples the gradients)."""
     import synth
     g = synth.BATCH
     rho, kap = synth.random_boxes(g, seed_workload=6, index=1)
@@ -243,25 +246,33 @@ def scan_workload(pk, torch):
         op.close()
     sig = [synth.noise_sigma(d[0], 0.02, 0.02), synth.noise_sigma(d[1], 0.02, 1.0)]
     dobs = [d[i] + sig[i] * synth.normal_like(d[i].shape, 6, 10 + i) for i in range(2)]
-    prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.9, 0.9), eps2=1e-9,
-               coupled=True, restart=True, p_norm=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = pk.lambda_scan(T, (g.sx, g.sy), dobs, [1.0 / s_ for s_ in sig],
-                         [synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)], SCAN_LAMS,
-                         n_outer=SCAN_OUTER, n_inner=SCAN_INNER, sim_min=0.9, dtype=torch.float32, **prm)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    pairs = sum(2 * r["k"] * SCAN_INNER for r in res["records"])
-    return {
+    out = {
         "workload": f"{len(SCAN_LAMS)} fixed Lagrange pairs, 128x128 stations over 128x128x24 prisms, "
                     f"{SCAN_OUTER} outer x {SCAN_INNER} inner each, one group solver, FP32 with FP64 reductions",
         "lambdas": [list(l) for l in SCAN_LAMS],
-        "scan_s": dt, "op_pairs_per_s": pairs / dt,
-        "similarity": [round(r["similarity"], 4) for r in res["records"]],
-        "converged": [r["converged"] for r in res["records"]],
-        "selected": res["selected"],
+        "sim_min": SCAN_SIM_MIN,
     }
+    for key, coupled in (("joint_step", True), ("per_data_set_step", False)):
+        prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.9, 0.9), eps2=1e-9,
+                   coupled=coupled, restart=True, p_norm=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = pk.lambda_scan(T, (g.sx, g.sy), dobs, [1.0 / s_ for s_ in sig],
+                             [synth.depth_weight(g, 2.0), synth.depth_weight(g, 3.0)], SCAN_LAMS,
+                             n_outer=SCAN_OUTER, n_inner=SCAN_INNER, sim_min=SCAN_SIM_MIN, dtype=torch.float32,
+                             **prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pairs = sum(2 * r["k"] * SCAN_INNER for r in res["records"])
+        out[key] = {
+            "scan_s": dt, "op_pairs_per_s": pairs / dt,
+            "similarity": [round(r["similarity"], 4) for r in res["records"]],
+            "converged": [r["converged"] for r in res["records"]],
+            "outer_steps": [r["k"] for r in res["records"]],
+            "phi_over_n": [[round(x / (g.sx * g.sy), 3) for x in r["phi"]] for r in res["records"]],
+            "selected": res["selected"],
+        }
+    return out
 
 
 def copy_probe(torch):

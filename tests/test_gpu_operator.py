@@ -82,15 +82,48 @@ def test_eigenvalues_equal_bruteforce_dft(pk, L):
 # ------------------------------------------------------------------------------------
 # prism kernel generator vs the oracle's closed forms
 # ------------------------------------------------------------------------------------
+def gravity_term_scale(g):
+    """Per entry of the gravity kernel array: G times the summed magnitudes of the 24 terms of
+    its 8-corner closed form (Z atan(XY/(ZR)), X ln(Y+R), Y ln(X+R) at each corner).  For
+    distant cells the signed sum cancels to far below its terms, so rounding of the size of the
+    terms, not of the entry, is what either evaluation carries."""
+    og = ogeom(g)
+    u = np.arange(-(g.nx - 1), g.sx).reshape(-1, 1)
+    v = np.arange(-(g.ny - 1), g.sy).reshape(1, -1)
+    x0, y0, z0 = oprism.station_xyz(og, u, v)
+    S = np.empty((g.nz, u.shape[0], v.shape[1]))
+    for r in range(g.nz):
+        xb, yb, zb = oprism.prism_bounds(og, 0, 0, r)
+        acc = 0.0
+        for i in (0, 1):
+            for j in (0, 1):
+                for k in (0, 1):
+                    X, Y, Z = xb[i] - x0, yb[j] - y0, zb[k] - z0
+                    R = np.sqrt(X * X + Y * Y + Z * Z)
+                    acc = acc + np.abs(Z * np.arctan(X * Y / (Z * R))) + np.abs(X * np.log(np.abs(Y) + R)) \
+                        + np.abs(Y * np.log(np.abs(X) + R))
+        S[r] = oprism.C_G * acc
+    return S
+
+
 @pytest.mark.parametrize("g", [synth.SMALL, synth.SUB, RAGGED, ODD, PADDED, synth.MID])
 def test_prism_kernels_match_oracle(pk, g):
     for kind in (pk.GRAVITY, pk.MAGNETIC):
         got = host(pk.prism_kernels(kind, g))
         ref = obttb.kernel_array(kind, ogeom(g))
         assert got.shape == ref.shape
-        # the 8-corner sums cancel for distant and deep cells, leaving rounding of the size
-        # of the corner terms: the bound is relative to the array's largest (near) entry
-        assert np.abs(got - ref).max() <= 4e-12 * np.abs(ref).max()
+        rel = np.abs(got - ref).max() / np.abs(ref).max()
+        if kind == pk.GRAVITY:
+            # each entry within a few ulps of its terms' magnitudes (the sum cancels for
+            # distant and deep cells, by more the larger the grid)
+            ratio = (np.abs(got - ref) / (np.finfo(np.float64).eps * gravity_term_scale(g))).max()
+            print(f"gravity {g.nx}x{g.ny}x{g.nz}: max err / (eps terms) = {ratio:.2f}, "
+                  f"max err / max |T| = {rel:.2e}", flush=True)
+            assert ratio <= 4.0
+        else:
+            # the magnetic closed forms keep their size at distance: relative to the array
+            print(f"magnetic {g.nx}x{g.ny}x{g.nz}: max err / max |T| = {rel:.2e}", flush=True)
+            assert rel <= 1e-14
 
 
 # ------------------------------------------------------------------------------------

@@ -25,16 +25,22 @@ def solver_kwargs(prm):
                 coupled=prm.coupled, restart=prm.restart, p_norm=prm.p_norm, gramian=prm.gramian)
 
 
+@pytest.mark.parametrize("coupled", [True, False], ids=["joint_step", "per_data_set_step"])
 @pytest.mark.parametrize("dtype,tol_m,tol_s", [(torch.float64, 1e-9, 1e-10), (torch.float32, 1e-5, 1e-5)])
-def test_scan_matches_oracle(pk, dtype, tol_m, tol_s):
+def test_scan_matches_oracle(pk, dtype, tol_m, tol_s, coupled):
     g = synth.SMALL
     ops, T, data, _ = problem(g, dense=True)
-    prm = orrcg.Params(**BASE)
+    prm = orrcg.Params(**BASE, coupled=coupled)
     sim_min = 0.8
-    ref = orrcg.lambda_scan(ops, data, prm, LAMS, n_outer=3, n_inner=3, sim_min=sim_min)
-    got = pk.lambda_scan(T, (g.sx, g.sy), data.dobs, data.wd, data.wdepth, LAMS, n_outer=3, n_inner=3,
+    # With per-data-set step lengths the largest pair leaves the regime where the Gramian's
+    # curvature is covered by lambda ||p||^2 in RRCG:6: the oracle's CG then diverges (beta up
+    # to 1e38, negative steps, models thrown between their bounds), so no result independent of
+    # the precision exists.  FP64 still follows the oracle there; FP32 is held on the others.
+    lams = LAMS if coupled or dtype == torch.float64 else LAMS[:3]
+    ref = orrcg.lambda_scan(ops, data, prm, lams, n_outer=3, n_inner=3, sim_min=sim_min)
+    got = pk.lambda_scan(T, (g.sx, g.sy), data.dobs, data.wd, data.wdepth, lams, n_outer=3, n_inner=3,
                          sim_min=sim_min, dtype=dtype, **solver_kwargs(prm))
-    assert len(got["records"]) == len(LAMS)
+    assert len(got["records"]) == len(lams)
     for a, b in zip(got["records"], ref["records"]):
         assert a["lam"] == b["lam"]
         assert a["converged"] == b["converged"] and a["k"] == b["k"]
