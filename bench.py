@@ -134,8 +134,8 @@ def batched_workload(pk, torch):
     graphs, autotuned launch shapes), FP32 with FP64 reductions; 5 outer x 10 inner steps, on the
     transform sizes of least estimated cost (BTTB_PAD_AUTO: powers of two, or 5-smooth sizes with
     one pass through LDS).  Beside it: the same group on the smallest 5-smooth sizes and on
-    powers of two, and the inversions solved one after another by one-inversion solvers (the
-    same sizes, each tuned)."""
+    powers of two, and the inversions solved one after another by one-inversion solvers (on the
+    same sizes and on powers of two, each tuned)."""
     import synth
     grids = synth.uneven_sizes(16)
     prm = dict(lo=(0.0, 0.0), hi=(1.0, 0.1), alpha0=(20000.0, 20000.0), q=(0.95, 0.95), lam=(2.0, 100.0),
@@ -187,26 +187,32 @@ def batched_workload(pk, torch):
                                                       "layer_chunks")},
                 "autotune_candidates": tune["tried"]}, chi
 
+    def seq_run(pad):
+        # the same inversions one at a time (each solver tuned on its own first)
+        opss = make_ops(pad)
+        t_seq, lat = 0.0, []
+        for j in range(len(grids)):
+            s1 = pk.JointRRCG(opss[j], **data[j], **prm)
+            s1.autotune(reps=3)
+            s1.step(BATCH_INNER)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(BATCH_OUTER):
+                s1.step(BATCH_INNER)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lat.append(dt)
+            t_seq += dt
+            s1.close()
+        close(opss)
+        return {"op_pairs_per_s": pairs / t_seq, "solve_s": t_seq,
+                "per_inversion_latency_s": {"min": min(lat), "max": max(lat), "mean": sum(lat) / len(lat)}}
+
     group_a, chi = group_run("auto")
     group5, _ = group_run("smooth")
     group2, _ = group_run("pow2")
-    # the same inversions one at a time (the same sizes; each solver tuned on its own first)
-    opss = make_ops("auto")
-    t_seq, lat = 0.0, []
-    for j in range(len(grids)):
-        s1 = pk.JointRRCG(opss[j], **data[j], **prm)
-        s1.autotune(reps=3)
-        s1.step(BATCH_INNER)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(BATCH_OUTER):
-            s1.step(BATCH_INNER)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        lat.append(dt)
-        t_seq += dt
-        s1.close()
-    close(opss)
+    seq_a = seq_run("auto")
+    seq_2 = seq_run("pow2")
     return {
         "workload": f"16 joint inversions, n = {min(g.nx for g in grids)}..{max(g.nx for g in grids)}, "
                     f"nz = {min(g.nz for g in grids)}..{max(g.nz for g in grids)}, {BATCH_OUTER} outer x "
@@ -215,10 +221,11 @@ def batched_workload(pk, torch):
         "group": group_a,
         "group_5smooth_padding": group5,
         "group_pow2_padding": group2,
-        "sequential": {"op_pairs_per_s": pairs / t_seq, "solve_s": t_seq,
-                       "per_inversion_latency_s": {"min": min(lat), "max": max(lat),
-                                                   "mean": sum(lat) / len(lat)}},
-        "group_vs_sequential": t_seq / group_a["solve_s"],
+        "sequential": seq_a,
+        "sequential_pow2_padding": seq_2,
+        "group_vs_sequential": seq_a["solve_s"] / group_a["solve_s"],
+        "group_vs_sequential_pow2_padding": seq_2["solve_s"] / group2["solve_s"],
+        "group_vs_sequential_pow2_padding_alone": seq_2["solve_s"] / group_a["solve_s"],
         "phi_after": [[round(a, 1) for a in c] for c in chi],
     }
 
