@@ -182,3 +182,51 @@ def test_group_step_parity_at_5smooth_sizes(pk, dtype, tol_m):
             assert sc["alpha"][k] == pytest.approx(ref.alpha[k], rel=1e-15)
         assert sc["k"] == ref.k and not sc["nonfinite"]
     grp.close()
+
+
+# four inversions at the sizes the cost-model padding picks for the uneven batch (288: 8 9 4,
+# 384: 8 6 8, 576: 8 9 8, 640: 8 10 8), the radix-9 / -6 / -10 LDS passes with a register last
+# pass, stepped together by the group solver as the batched bench runs them
+AUTO_GRIDS = [synth.Grid(n, n, n, n, 2, 40.0, 40.0, 25.0) for n in (136, 178, 266, 314)]
+_AUTO_REF = {}
+
+
+def auto_reference():
+    if not _AUTO_REF:
+        for idx, g in enumerate(AUTO_GRIDS):
+            ops, T, data, _ = problem(g, dense=False)
+            prm = params(VARIANTS[idx])
+            st, _ = orrcg.run(ops, data, prm, n_outer=1, n_inner=N_INNER)
+            ref, rec = orrcg.outer_step(ops, data, prm, st, N_INNER)
+            _AUTO_REF[idx] = (g, T, data, prm, st, ref, rec)
+    return _AUTO_REF
+
+
+@pytest.mark.parametrize("dtype,tol_m", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_group_step_parity_at_auto_padded_sizes(pk, dtype, tol_m):
+    refs = auto_reference()
+    probs = []
+    for idx in range(len(AUTO_GRIDS)):
+        g, T, data, prm, _, _, _ = refs[idx]
+        gops = [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=dtype, pad="auto")
+                for i in range(2)]
+        probs.append(dict(ops=gops, dobs=data.dobs, wd=data.wd, wdepth=data.wdepth, **solver_kwargs(prm)))
+    assert [p["ops"][0].info()["Px"] for p in probs] == [288, 384, 576, 640]
+    grp = pk.JointRRCGGroup(probs)
+    for idx in range(len(AUTO_GRIDS)):
+        set_state(grp, idx, refs[idx][4], dtype)
+    grp.refresh()
+    grp.step(N_INNER)
+    for idx in range(len(AUTO_GRIDS)):
+        _, _, _, _, _, ref, rec = refs[idx]
+        sc = grp.scalars(idx)
+        errs = [rel(host(grp.inv[idx].m[k]), ref.m[k]) for k in range(2)]
+        print(f"{dtype} inversion {idx} (P = {probs[idx]['ops'][0].info()['Px']}): model rel err {errs}", flush=True)
+        assert max(errs) <= tol_m, (idx, errs)
+        for k in range(2):
+            assert sc["phi"][k] == pytest.approx(rec["phi"][k], rel=tol_m * 10)
+        assert sc["k"] == ref.k and not sc["nonfinite"]
+    grp.close()
+    for p in probs:
+        for op in p["ops"]:
+            op.close()
