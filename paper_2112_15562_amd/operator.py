@@ -304,7 +304,20 @@ class Group:
 
     def apply_ptrs(self, op: int, ins: torch.Tensor, outs: torch.Tensor, winv: Optional[torch.Tensor] = None,
                    wd: Optional[torch.Tensor] = None) -> None:
-        """Products with device pointer arrays (int64 tensors of one address per member)."""
+        """Products with device pointer arrays: int64 tensors on the group's device holding one
+        address per member (winv and wd entries may be 0).  The arrays' form is checked here; the
+        addresses are not -- each must point to a contiguous vector of that member's dtype and
+        shape (what `apply` checks before it calls this)."""
+        n = len(self.ops)
+        if op not in (L.BTTB_OP_FORWARD, L.BTTB_OP_ADJOINT):
+            raise ValueError("op must be BTTB_OP_FORWARD or BTTB_OP_ADJOINT")
+        for name, a in (("ins", ins), ("outs", outs), ("winv", winv), ("wd", wd)):
+            if a is None:
+                if name in ("ins", "outs"):
+                    raise ValueError(f"{name}: a pointer array is required")
+                continue
+            if a.dtype != torch.int64 or a.numel() != n or a.device != self.device or not a.is_contiguous():
+                raise ValueError(f"{name}: expected a contiguous int64 tensor of {n} addresses on {self.device}")
         L.check(L.lib().bttb_group_apply(self.handle, int(op), _ptr(ins), _ptr(outs), _ptr(winv), _ptr(wd),
                                          C.c_void_p(_stream(self.device))), "bttb_group_apply")
 

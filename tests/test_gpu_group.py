@@ -196,6 +196,12 @@ def test_group_apply_checks_every_vector(pk):
     for kw in bad:
         with pytest.raises((ValueError, TypeError)):
             grp.apply(**kw)
+    # the pointer-array form: int64 arrays of one address per member, on the device
+    px, py = pk.pointer_array(x, dev), pk.pointer_array([torch.empty(o.data_shape, dtype=torch.float64, device=dev)
+                                                         for o in ops], dev)
+    for a, b in [(px[:1], py), (px, py.cpu()), (px.to(torch.int32), py), (px, None)]:
+        with pytest.raises(ValueError):
+            grp.apply_ptrs(F, a, b)
     # entries of the diagonals may be None (identity for that member)
     ys = grp.apply(F, x, winv=[None, wi[1]], wd=[wd[0], None])
     ref0 = ops[0].matvec(x[0], wd=wd[0])
