@@ -408,3 +408,39 @@ def test_error_paths(pk):
     rc = L.lib().bttb_matvec(op.plan, C.c_void_p(buf.data_ptr() + 4), C.c_void_p(out.data_ptr()), None)
     assert rc == L.BTTB_EINVAL
     op.close()
+
+
+# ------------------------------------------------------------------------------------
+# the largest transform (BTTB_MAX_TRANSFORM = 2048 points) along either axis
+# ------------------------------------------------------------------------------------
+LONG = [synth.Grid(1000, 16, 1000, 16, 2, 40.0, 40.0, 25.0), synth.Grid(16, 1000, 16, 1000, 2, 40.0, 40.0, 25.0, decl=20.0)]
+
+
+@pytest.mark.parametrize("g", LONG, ids=["Px2048", "Py2048"])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_products_at_the_largest_transform(pk, g, dtype, tol):
+    og = ogeom(g)
+    rng = np.random.default_rng(g.nx)
+    x = rng.uniform(0.0, 1.0, g.model_shape)
+    r = rng.standard_normal(g.data_shape)
+    ops, refs = [], []
+    for kind in (oprism.GRAVITY, oprism.MAGNETIC):
+        T = obttb.kernel_array(kind, og)
+        op = pk.Operator(torch.as_tensor(T, device="cuda"), (g.sx, g.sy), dtype=dtype, pad="pow2")
+        assert max(op.info()["Px"], op.info()["Py"]) == pk.MAX_TRANSFORM == 2048
+        ops.append(op)
+        refs.append((obttb.fft_matvec(T, x, g.sx, g.sy), obttb.fft_rmatvec(T, r, g.sx, g.sy)))
+    xd, rd = torch.as_tensor(x, dtype=dtype, device="cuda"), torch.as_tensor(r, dtype=dtype, device="cuda")
+    for op, (y, z) in zip(ops, refs):
+        errs = [relerr(host(op.matvec(xd)), y), relerr(host(op.rmatvec(rd)), z)]
+        print(f"{dtype} {g.nx}x{g.ny} one plan: {errs}", flush=True)
+        assert max(errs) <= tol
+    grp = pk.Group(ops)
+    ys, zs = grp.matvec([xd, xd]), grp.rmatvec([rd, rd])
+    for i, (y, z) in enumerate(refs):
+        errs = [relerr(host(ys[i]), y), relerr(host(zs[i]), z)]
+        print(f"{dtype} {g.nx}x{g.ny} group member {i}: {errs}", flush=True)
+        assert max(errs) <= tol
+    grp.close()
+    for op in ops:
+        op.close()
