@@ -174,11 +174,15 @@ def outer_step(ops, data: Data, prm: Params, st: State, n_inner: int):
         num = [dot(p[i], l[i]) for i in range(2)]
         den = [dot(q[i], q[i]) + (st.alpha[i] + prm.lam[i]) * dot(p[i], p[i])
                for i in range(2)]
-        if prm.coupled:                                        # RRCG:6
-            s_ = (num[0] + num[1]) / (den[0] + den[1])
+        # RRCG:6.  Reading: a zero denominator means p = 0 (for alpha + lambda > 0), where
+        # (p, l) = 0 as well: the quadratic of this reweighting step is at its minimum, and the
+        # step is 0 (the iterate stays), the usual end of a CG iteration.
+        if prm.coupled:
+            D = den[0] + den[1]
+            s_ = 0.0 if D == 0.0 else (num[0] + num[1]) / D
             s = [s_, s_]
         else:
-            s = [num[i] / den[i] for i in range(2)]
+            s = [0.0 if den[i] == 0.0 else num[i] / den[i] for i in range(2)]
         m_prev = m                                             # start of this CG step
         mt = [mt[i] - s[i] * p[i] for i in range(2)]           # RRCG:7
         rt = [rt[i] - s[i] * q[i] for i in range(2)]

@@ -228,11 +228,14 @@ __device__ __forceinline__ void step_finish(double* sc, SlotSums<6>& ss, double 
   ss.total(t);
   const double den0 = t[4] + (gload(sc + S_ALPHA) + lam0) * t[2];
   const double den1 = t[5] + (gload(sc + S_ALPHA + 1) + lam1) * t[3];
+  // a zero denominator means p = 0, where (p, l) = 0 too: the quadratic of this reweighting
+  // step is at its minimum and the step is 0 (no update), as a CG iteration ends
   if (coupled) {
-    s[0] = s[1] = (t[0] + t[1]) / (den0 + den1);
+    const double D = den0 + den1;
+    s[0] = s[1] = D == 0.0 ? 0.0 : (t[0] + t[1]) / D;
   } else {
-    s[0] = t[0] / den0;
-    s[1] = t[1] / den1;
+    s[0] = den0 == 0.0 ? 0.0 : t[0] / den0;
+    s[1] = den1 == 0.0 ? 0.0 : t[1] / den1;
   }
   if (record && threadIdx.x == 0) {
     gstore(sc + S_STEP, s[0]);

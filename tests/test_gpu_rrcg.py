@@ -347,3 +347,23 @@ def test_timed_solver_steps_like_an_untimed_one(pk):
     assert sa["phi"] == sb["phi"] and sa["beta"] == sb["beta"] and sa["step"] == sb["step"]
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("coupled", [True, False], ids=["joint_step", "per_data_set_step"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_zero_data_and_prior_stay_at_zero(pk, dtype, coupled):
+    # the degenerate problem whose every objective vanishes at m = 0: zero gradient, zero
+    # direction, the step length's 0/0 taken as 0 (as the oracle does), no non-finite flag
+    g = synth.SMALL
+    _, T, data, _ = problem(g, dense=True)
+    zero = orrcg.Data(dobs=[np.zeros_like(d) for d in data.dobs], wd=data.wd, wdepth=data.wdepth)
+    prm = orrcg.Params(**BASE, coupled=coupled)
+    s, _ = gpu_solver(pk, g, T, zero, prm, dtype)
+    s.run(3, 4)
+    sc = s.scalars()
+    assert not sc["nonfinite"]
+    for k in range(2):
+        assert not host(s.m[k]).any()
+        assert sc["phi"][k] == 0.0 and sc["step"][k] == 0.0
+    assert sc["similarity"] == 0.0
+    s.close()

@@ -342,3 +342,21 @@ def test_previous_iterate_anchor_first_step_and_state(ops6):
     st2, _ = rrcg.outer_step(ops6, data, rrcg.Params(anchor="prev", **kw), st_p, n_inner=3)
     st3, _ = rrcg.outer_step(ops6, data, rrcg.Params(anchor="apr", **kw), st_p, n_inner=3)
     assert not np.array_equal(st2.m[0], st3.m[0])
+
+
+@pytest.mark.parametrize("coupled", [True, False])
+def test_zero_data_and_prior_stay_at_zero(ops6, coupled):
+    # with zero data and a zero prior every reweighted objective (misfit, regulariser and
+    # Gramian term, all non-negative) vanishes at m = 0, so the iteration must stay there:
+    # the first gradient is zero, the direction is zero, and the step length of RRCG:6 (0/0)
+    # is taken as 0
+    g = G6
+    data, _ = _data(g, ops6)
+    zero = rrcg.Data(dobs=[np.zeros_like(d) for d in data.dobs], wd=data.wd, wdepth=data.wdepth)
+    prm = rrcg.Params(alpha0=(50.0, 50.0), q=(0.9, 0.9), lam=(2.0, 100.0), lo=(0.0, 0.0), hi=(1.0, 0.1),
+                      coupled=coupled, restart=True)
+    st, recs = rrcg.run(ops6, zero, prm, n_outer=3, n_inner=4)
+    assert all(np.array_equal(m, np.zeros_like(m)) for m in st.m)
+    assert all(s == [0.0, 0.0] for rec in recs for s in rec["s"])
+    assert recs[-1]["phi"] == [0.0, 0.0]
+    assert rrcg.similarity(st.m[0], st.m[1]) == 0.0
