@@ -30,6 +30,8 @@ Readings where the paper is silent or inconsistent (each listed in the design no
 * RRCG:6 block scalars: alpha-bar ||p-bar||^2 = sum_i alpha_i ||p_i||^2, same for lambda.
 * "coupled=False" gives the stand-alone form (Sec. 3.1.1): beta and s per data set.
 * gramian="weighted" uses the ascent directions of eqs. (steepestascenta/b) on m~.
+* RRCG:6 with a zero denominator (p = 0, where (p, l) = 0 too) takes s = 0: the step's
+  quadratic is at its minimum.
 
 Pins (tests/test_oracle_rrcg.py): Gramian identities (S_G of collinear models is 0,
 l_G vanishes there, S_G >= 0, finite-difference gradient = 2 l_G, the scalar-weight
@@ -41,7 +43,8 @@ with non-uniform W the iteration's limit satisfies RRCG:4 with l_G the finite-di
 half-gradient of the Gramian on m (gramian="original") or on m~ ("weighted"), and not the
 other; the printed single loop (beta carried over) reaches the Tikhonov solution in 3n
 steps; the anchor="prev" limit solves the unregularised system (A m = d on a square one)
-while the m~_apr anchor's is the Tikhonov solution.
+while the m~_apr anchor's is the Tikhonov solution; zero data with a zero prior, whose
+objectives all vanish at m = 0, leave the iteration at m = 0 exactly.
 Full multi-step trajectories are pinned only against these properties.
 """
 from __future__ import annotations
