@@ -131,7 +131,8 @@ BTTB_API int bttb_prism_kernels(int kind, const bttb_geometry* g, double* out, v
  * smallest 5-smooth multiples of 8 >= sx+nx-1, sy+ny-1) and take its FFT2 once
  * (the BCCB eigenvalues, Sec. 2.7.1), in FP64; a BTTB_F32 plan rounds them to float.
  * kernels: dev double [nz][sx+nx-1][sy+ny-1], read during the call only.
- * max_batch: largest batch a single product call may take (>= 1).
+ * max_batch: batch members one product launch transforms together (>= 1); a product call
+ * with a larger batch runs max_batch members at a time (the plan's scratch holds max_batch).
  * Synchronises `stream` before returning.  *out receives the plan. */
 BTTB_API int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny, int nz,
                int precision, int max_batch, void* stream, bttb_plan* out);
@@ -145,8 +146,8 @@ BTTB_API int bttb_rmatvec(bttb_plan plan, const void* r, void* z, void* stream);
 /* General product, batched and weighted (eq. matrixvector):
  *   op = BTTB_OP_FORWARD: out_b = wd . (A (winv . in_b))        in_b [nz][nx][ny] -> out_b [sx][sy]
  *   op = BTTB_OP_ADJOINT: out_b = winv . (A^T (wd . in_b))      in_b [sx][sy] -> out_b [nz][nx][ny]
- * for b < batch (1 <= batch <= max_batch), element strides in_stride / out_stride between
- * batch members (>= the member size).  winv (dev [nz][nx][ny], = 1/W) and wd (dev [sx][sy])
+ * for b < batch (batch >= 1, else BTTB_EINVAL; max_batch members per launch), element
+ * strides in_stride / out_stride between batch members (>= the member size when batch > 1).  winv (dev [nz][nx][ny], = 1/W) and wd (dev [sx][sy])
  * are nullable (NULL = identity) and shared by the whole batch. */
 BTTB_API int bttb_apply(bttb_plan plan, int op, int batch, const void* in, long long in_stride,
                void* out, long long out_stride, const void* winv, const void* wd, void* stream);

@@ -444,3 +444,26 @@ def test_products_at_the_largest_transform(pk, g, dtype, tol):
     grp.close()
     for op in ops:
         op.close()
+
+
+def test_empty_and_chunked_batches(pk):
+    from paper_2112_15562_amd import _lib as L
+    g = synth.SUB
+    op = pk.Operator.from_geometry(pk.MAGNETIC, g, dtype=torch.float64, max_batch=2)
+    # an empty batch gives an empty result without a library call
+    y = op.matvec(torch.zeros((0,) + tuple(op.model_shape), dtype=torch.float64, device="cuda"))
+    z = op.rmatvec(torch.zeros((0, 3) + tuple(op.data_shape), dtype=torch.float64, device="cuda"))
+    assert tuple(y.shape) == (0,) + tuple(op.data_shape) and tuple(z.shape) == (0, 3) + tuple(op.model_shape)
+    # the C entry point refuses batch 0
+    x = torch.rand((5,) + tuple(op.model_shape), dtype=torch.float64, device="cuda")
+    out = torch.empty((5,) + tuple(op.data_shape), dtype=torch.float64, device="cuda")
+    nin, nout = x[0].numel(), out[0].numel()
+    assert L.lib().bttb_apply(op.plan, L.BTTB_OP_FORWARD, 0, x.data_ptr(), nin, out.data_ptr(), nout,
+                              None, None, None) == L.BTTB_EINVAL
+    # a batch above max_batch runs max_batch members at a time: every member as alone
+    ys = op.matvec(x)
+    zs = op.rmatvec(ys)
+    for b in range(5):
+        assert relerr(host(ys[b]), host(op.matvec(x[b].contiguous()))) <= 1e-15
+        assert relerr(host(zs[b]), host(op.rmatvec(ys[b].contiguous()))) <= 1e-15
+    op.close()
