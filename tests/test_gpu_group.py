@@ -293,3 +293,47 @@ def test_auto_padding_chooses_cheaper_sizes(pk):
         op.close()
     with pytest.raises(ValueError):
         pk.Operator(torch.zeros((1, 7, 7), dtype=torch.float64, device="cuda"), (4, 4), pad="bad")
+
+
+# every 5-smooth size with compiled group kernels, as a column transform (Px) and as a row
+# transform (Py): member j has Px = SIZES[j], Py = SIZES[22 - j] (stations over prism centres,
+# n = P / 2, so the plans keep these sizes), in two groups of at most 14 sizes per stage
+ALL_MIXED = [24, 40, 48, 72, 80, 96, 120, 144, 160, 192, 200, 216, 240, 288, 320, 360, 384, 400, 432, 480, 576,
+             600, 640]
+_ACACHE = {}
+
+
+def all_mixed_case(j):
+    if j not in _ACACHE:
+        Px, Py = ALL_MIXED[j], ALL_MIXED[len(ALL_MIXED) - 1 - j]
+        g = synth.Grid(Px // 2, Py // 2, Px // 2, Py // 2, 2, 40.0, 40.0, 25.0, decl=5.0 * j)
+        kind = oprism.GRAVITY if j % 2 == 0 else oprism.MAGNETIC
+        og = oprism.Geometry(g.sx, g.sy, g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, g.top, g.incl, g.decl, g.field)
+        T = obttb.kernel_array(kind, og)
+        x = synth.rng(8, j).uniform(0.0, 1.0, g.model_shape)
+        r = synth.rng(8, 100 + j).standard_normal(g.data_shape)
+        _ACACHE[j] = (g, T, x, r, obttb.fft_matvec(T, x, g.sx, g.sy), obttb.fft_rmatvec(T, r, g.sx, g.sy))
+    return _ACACHE[j]
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_group_products_at_every_compiled_5smooth_size(pk, dtype, tol):
+    assert len(ALL_MIXED) == 23
+    for part in (range(0, 12), range(12, 23)):
+        ops, cases = [], []
+        for j in part:
+            g, T, x, r, y, z = all_mixed_case(j)
+            op = pk.Operator(torch.as_tensor(T, device="cuda"), (g.sx, g.sy), dtype=dtype)
+            assert (op.info()["Px"], op.info()["Py"]) == (ALL_MIXED[j], ALL_MIXED[22 - j])
+            ops.append(op)
+            cases.append((x, r, y, z))
+        grp = pk.Group(ops)
+        ys = grp.matvec([torch.as_tensor(c[0], dtype=dtype, device="cuda") for c in cases])
+        zs = grp.rmatvec([torch.as_tensor(c[1], dtype=dtype, device="cuda") for c in cases])
+        for k, j in enumerate(part):
+            errs = [rel(host(ys[k]), cases[k][2]), rel(host(zs[k]), cases[k][3])]
+            print(f"  {dtype} Px {ALL_MIXED[j]} Py {ALL_MIXED[22 - j]}: {['%.1e' % e for e in errs]}", flush=True)
+            assert max(errs) <= tol, (j, errs)
+        grp.close()
+        for op in ops:
+            op.close()
