@@ -283,13 +283,25 @@ template <typename T>
 struct ColFwdArgs {
   const cx<T>* in;  // U [L][K2][ldin]
   long long in_bs;
-  const cx<T>* eig;  // [L][K2][N]
+  const cx<T>* eig;  // [L][K2][N], or with eig_even real [L][K2][N/2 + 1]
   cx<T>* out;        // V [chunk][K2][ldout]
   long long out_bs, out_cs;
   int L, nin, nout, ldin, ldout, K2, fpb, nchunk;
   FFTDesc fd;
   const cx<T>* tw;
+  int eig_even;
 };
+
+// Eigenvalue k1 of the stored column (l, k2): complex, or from the real store of a symmetric
+// operator (lambda[N - k] = lambda[k], real).
+template <typename T>
+__device__ __forceinline__ cx<T> eig_value(const cx<T>* eig, int even, int K2, int N, int l, int k2, int k1) {
+  if (even) {
+    const T* er = reinterpret_cast<const T*>(eig) + ((long long)l * K2 + k2) * (N / 2 + 1);
+    return cx<T>{er[k1 <= N / 2 ? k1 : N - k1], T(0)};
+  }
+  return eig[((long long)l * K2 + k2) * N + k1];
+}
 
 template <typename T>
 __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs<T> a) {
@@ -312,12 +324,11 @@ __global__ void __launch_bounds__(1024) k_col_fwd(ColFwdArgs<T> a) {
     __syncthreads();
     fft_lds<T, false>(z, a.fd, a.tw, t, TPF, true);
     if (valid) {
-      const cx<T>* e = a.eig + ((long long)l * K2 + k2) * N;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k1 = t + i * TPF;
         const cx<T> x = z[k1];
-        const cx<T> w = e[k1];
+        const cx<T> w = eig_value(a.eig, a.eig_even, K2, N, l, k2, k1);
         const double xr = x.re, xi = x.im, wr = w.re, wi = w.im;
         ar[i] += wr * xr - wi * xi;
         ai[i] += wr * xi + wi * xr;
@@ -339,12 +350,13 @@ template <typename T>
 struct ColAdjArgs {
   const cx<T>* in;  // [K2][ldin]
   long long in_bs;
-  const cx<T>* eig;
+  const cx<T>* eig;  // as ColFwdArgs::eig
   cx<T>* out;  // [L][K2][ldout]
   long long out_bs;
   int L, nin, nout, ldin, ldout, K2, fpb, nchunk;
   FFTDesc fd;
   const cx<T>* tw;
+  int eig_even;
 };
 
 template <typename T>
@@ -368,11 +380,10 @@ __global__ void __launch_bounds__(1024) k_col_adj(ColAdjArgs<T> a) {
   __syncthreads();
   for (int l = l0; l < l1; ++l) {
     if (valid) {
-      const cx<T>* e = a.eig + ((long long)l * K2 + k2) * N;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k1 = t + i * TPF;
-        z[k1] = cmulc(R[i], e[k1]);
+        z[k1] = cmulc(R[i], eig_value(a.eig, a.eig_even, K2, N, l, k2, k1));
       }
     }
     __syncthreads();
@@ -654,7 +665,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
       if (rc) return rc;
       rc = stage(KT_FWD_COL, [&]() -> int {
         ColFwdArgs<T> a{U, U_bs, eig, V, V_bs, V_cs, P->nz, P->nx, P->sx, P->ldx, P->lds, P->K2, P->col_fpb,
-                        P->nchunk, P->fx, twx};
+                        P->nchunk, P->fx, twx, P->eig_even};
         dim3 grid(ceil_div(P->K2, P->col_fpb), P->nchunk, nb);
         hipLaunchKernelGGL(k_col_fwd<T>, grid, dim3(P->col_fpb * TPFx),
                            (size_t)P->col_fpb * P->Px * sizeof(cx<T>), s, a);
@@ -675,7 +686,7 @@ int apply_impl(Plan* P, int op, int batch, const T* in, long long in_stride, T* 
       if (rc) return rc;
       rc = stage(KT_ADJ_COL, [&]() -> int {
         ColAdjArgs<T> a{V, V_bs, eig, U, U_bs, P->nz, P->sx, P->nx, P->lds, P->ldx, P->K2, P->col_fpb,
-                        P->nchunk, P->fx, twx};
+                        P->nchunk, P->fx, twx, P->eig_even};
         dim3 grid(ceil_div(P->K2, P->col_fpb), P->nchunk, nb);
         hipLaunchKernelGGL(k_col_adj<T>, grid, dim3(P->col_fpb * TPFx),
                            (size_t)P->col_fpb * P->Px * sizeof(cx<T>), s, a);
@@ -883,7 +894,7 @@ extern "C" int bttb_setup(const double* kernels, int sx, int sy, int nx, int ny,
                          static_cast<const cx<double>*>(twx64), scale);
     if (hipGetLastError() != hipSuccess) { rc = fail(BTTB_EHIP, "bttb_setup: k_col_setup launch"); break; }
     if (hipStreamSynchronize(s) != hipSuccess) { rc = fail(BTTB_EHIP, "bttb_setup: synchronize"); break; }
-    if (P->fast && !eig_full) rc = precision == BTTB_F64 ? make_eig_even<double>(P, s) : make_eig_even<float>(P, s);
+    if (!eig_full) rc = precision == BTTB_F64 ? make_eig_even<double>(P, s) : make_eig_even<float>(P, s);
   } while (false);
   cleanup_tmp();
   if (rc != BTTB_OK) return cleanup(rc);

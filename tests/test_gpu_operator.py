@@ -267,9 +267,10 @@ def _store_checks(even, full, nz, dtype):
 # complex store: their closed forms evaluate T(i, j) and T(-i, j) with different rounding,
 # which the far-field cancellation amplifies to |Im lambda| ~ 6e-13 (16^2) .. 1e-10 (128^2) of
 # max |lambda|, above the FP64 test (1e-14).
-@pytest.mark.parametrize("g", [synth.SMALL, synth.MID])
+@pytest.mark.parametrize("g", [synth.SMALL, synth.MID, synth.SUB, R35], ids=["P32", "P256", "P24", "P120"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_symmetric_gravity_operator_store(pk, g, dtype):
+    # (the 5-smooth sizes 24 and 120 take the real store through the one-plan LDS kernels too)
     grav = pk.Operator.from_geometry(pk.GRAVITY, g, dtype=dtype)
     full = pk.Operator.from_geometry(pk.GRAVITY, g, dtype=dtype, full_eig=True)
     mag = pk.Operator.from_geometry(pk.MAGNETIC, g, dtype=dtype)
