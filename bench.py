@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--pairs", type=int, default=200, help="timed product pairs per precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-inversion batched workload")
     ap.add_argument("--no-scan", action="store_true", help="skip the Lagrange-parameter scan")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="instead of the benchmark: group product times per transform size, 5-smooth against "
+                         "power-of-two padding, beside the size the cost-model padding picks")
     return ap.parse_args()
 
 
@@ -280,6 +283,63 @@ def scan_workload(pk, torch):
             "selected": res["selected"],
         }
     return out
+
+
+SWEEP_SIZES = [216, 240, 288, 320, 360, 384, 400, 432, 480, 576, 600, 640]
+SWEEP_NZ = 16
+
+
+def group_pair_us(pk, torch, ops, reps=30):
+    """Mean time of one forward and one transpose product of every member of a group (one launch
+    per stage), after the group's own launch-shape tuning; HIP events around `reps` pairs."""
+    grp = pk.Group(ops)
+    tune = grp.autotune(reps=5)
+    xs = [torch.rand(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
+    rs = [torch.randn(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
+    ys = [torch.empty(op.data_shape, dtype=op.dtype, device="cuda") for op in ops]
+    zs = [torch.empty(op.model_shape, dtype=op.dtype, device="cuda") for op in ops]
+    P = [pk.pointer_array(v, "cuda") for v in (xs, ys, rs, zs)]
+    for _ in range(5):
+        grp.apply_ptrs(0, P[0], P[1])
+        grp.apply_ptrs(1, P[2], P[3])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        grp.apply_ptrs(0, P[0], P[1])
+        grp.apply_ptrs(1, P[2], P[3])
+    e1.record()
+    torch.cuda.synchronize()
+    grp.close()
+    return e0.elapsed_time(e1) * 1e3 / reps, tune
+
+
+def size_sweep(pk, torch):
+    """Per 5-smooth transform size P: n x n stations over n x n x SWEEP_NZ prisms with n = P / 2,
+    gravity and magnetic in one group, FP32; the joint product pair at the 5-smooth size and with
+    power-of-two padding, and the size the cost-model padding (BTTB_PAD_AUTO) picks."""
+    import synth
+    rows = []
+    for P in SWEEP_SIZES:
+        n = P // 2
+        g = synth.Grid(n, n, n, n, SWEEP_NZ, 40.0, 40.0, 25.0)
+        T = [pk.prism_kernels(k, g) for k in (pk.GRAVITY, pk.MAGNETIC)]
+        row = {"n": n}
+        for pad in ("smooth", "pow2"):
+            ops = [pk.Operator(T[i], (n, n), dtype=torch.float32, pad=pad) for i in range(2)]
+            us, _ = group_pair_us(pk, torch, ops)
+            row[pad] = {"P": ops[0].info()["Px"], "us_per_joint_pair": round(us, 2)}
+            for op in ops:
+                op.close()
+            log(f"bench: size sweep n={n} {pad}: {row[pad]}")
+        auto = pk.Operator(T[0], (n, n), dtype=torch.float32, pad="auto")
+        row["auto_picks"] = auto.info()["Px"]
+        auto.close()
+        row["smooth_over_pow2"] = round(row["smooth"]["us_per_joint_pair"] / row["pow2"]["us_per_joint_pair"], 3)
+        row["faster"] = "smooth" if row["smooth_over_pow2"] < 1.0 else "pow2"
+        rows.append(row)
+    return {"workload": f"n x n stations over n x n x {SWEEP_NZ} prisms, n = P/2, gravity and magnetic in one "
+                        f"group, FP32, one forward and one transpose product each", "rows": rows}
 
 
 def copy_probe(torch):
@@ -571,6 +631,9 @@ def main():
         b.build()
     import paper_2112_15562_amd as pk
     import synth
+    if args.size_sweep:
+        print(json.dumps({"size_sweep": size_sweep(pk, torch)}), flush=True)
+        return
     g = synth.LARGE
     torch.cuda.set_device(0)
     log("bench: inputs")

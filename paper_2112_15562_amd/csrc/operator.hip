@@ -46,15 +46,17 @@ int padded_size(int L) {
 
 // Relative cost of one point of a transform of size N in the register-layout kernels (products
 // and groups): 1 for a power of two; for the 5-smooth sizes of the group kernels, more with every
-// pass through LDS and when the last pass cannot run in registers (measured at 216..576 points:
-// 1.5 for one LDS pass with a register last pass, about 2.1-2.4 for two without).
+// pass through LDS and when the last pass cannot run in registers.  The constants reproduce
+// which of a 5-smooth size P and the next power of two gives the faster joint products for
+// n = P / 2 at every size from 216 to 640 points (group products of both operators, FP32):
+// 1.8 for one LDS pass with a register last pass, 2.1-2.5 for two.
 static double transform_cost(int N) {
   if ((N & (N - 1)) == 0) return 1.0;
   const MixPlan p = mix_plan(N);
   const int last = p.radix[p.npass - 1];
   const bool reg = last == 2 || last == 4 || last == 8;
   const int lds = p.npass - 1 - (reg ? 1 : 0);
-  return 1.2 + 0.3 * lds + (reg ? 0.0 : 0.4);
+  return 1.5 + 0.3 * lds + (reg ? 0.0 : 0.4);
 }
 
 // The size of BTTB_PAD_AUTO for a circle of L points whose stations and prisms span at most n of
@@ -62,10 +64,11 @@ static double transform_cost(int N) {
 // group kernels and hold n in their first half, the one with the least N sqrt(cost(N)), i.e. the
 // least estimated cost when both axes take it (N^2 points).
 int auto_size(int L, int n) {
-  int best = 32;
-  while (best < L) best <<= 1;
-  double best_cost = (double)best;
-  for (int N = 8 * ceil_div(L, 8); N < best; N += 8) {
+  int p2 = 32;
+  while (p2 < L) p2 <<= 1;
+  int best = p2;
+  double best_cost = (double)p2;
+  for (int N = 8 * ceil_div(L, 8); N < p2; N += 8) {  // every candidate below the power of two
     if (!mixed_size(N) || 2 * n > N) continue;
     const double c = N * std::sqrt(transform_cost(N));
     if (c < best_cost) {

@@ -285,7 +285,8 @@ def test_group_products_at_5smooth_sizes(pk, dtype, tol, shape):
 def test_auto_padding_chooses_cheaper_sizes(pk):
     # BTTB_PAD_AUTO: per axis the power of two or a 5-smooth size of least estimated cost; for
     # grids just above a power of two the 5-smooth sizes with one pass through LDS win
-    expect = {178: 384, 101: 256, 266: 576, 320: 640, 136: 288, 244: 512}
+    # (n = 300: 600 points are cheaper than 1024, and 640 cheaper still)
+    expect = {178: 512, 101: 256, 266: 576, 320: 640, 136: 288, 160: 320, 192: 512, 244: 512, 300: 640}
     for n, P in expect.items():
         T = torch.zeros((1, 2 * n - 1, 2 * n - 1), dtype=torch.float64, device="cuda")
         op = pk.Operator(T, (n, n), dtype=torch.float32, pad="auto")

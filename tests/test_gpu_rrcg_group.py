@@ -184,10 +184,10 @@ def test_group_step_parity_at_5smooth_sizes(pk, dtype, tol_m):
     grp.close()
 
 
-# four inversions at the sizes the cost-model padding picks for the uneven batch (288: 8 9 4,
-# 384: 8 6 8, 576: 8 9 8, 640: 8 10 8), the radix-9 / -6 / -10 LDS passes with a register last
-# pass, stepped together by the group solver as the batched bench runs them
-AUTO_GRIDS = [synth.Grid(n, n, n, n, 2, 40.0, 40.0, 25.0) for n in (136, 178, 266, 314)]
+# four inversions at 5-smooth sizes the cost-model padding picks (288: 8 9 4, 320: 8 5 8,
+# 576: 8 9 8, 640: 8 10 8), the radix-9 / -5 / -10 LDS passes with a register last pass,
+# stepped together by the group solver as the batched bench runs them
+AUTO_GRIDS = [synth.Grid(n, n, n, n, 2, 40.0, 40.0, 25.0) for n in (136, 160, 266, 314)]
 _AUTO_REF = {}
 
 
@@ -211,7 +211,7 @@ def test_group_step_parity_at_auto_padded_sizes(pk, dtype, tol_m):
         gops = [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=dtype, pad="auto")
                 for i in range(2)]
         probs.append(dict(ops=gops, dobs=data.dobs, wd=data.wd, wdepth=data.wdepth, **solver_kwargs(prm)))
-    assert [p["ops"][0].info()["Px"] for p in probs] == [288, 384, 576, 640]
+    assert [p["ops"][0].info()["Px"] for p in probs] == [288, 320, 576, 640]
     grp = pk.JointRRCGGroup(probs)
     for idx in range(len(AUTO_GRIDS)):
         set_state(grp, idx, refs[idx][4], dtype)
