@@ -43,11 +43,11 @@ TIMING_REPEAT = 10
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "dff77f557da61429b558c1d0bc84cd2a885a9975de378fa5aa87ddf5a16699a0",
+    "csrc_sha256": "0ca04932b7ebb217b38e07792393f1a93d92c8c919066694dba9bbd9001c750e",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50684463, 50528320), "fwd_col_eig_sum": (77058451, 4210688),
+        "fwd_row_r2c": (50684463, 50528320), "fwd_col_eig_sum": (77075410, 8447936),
         "fwd_row_c2r": (1769384, 532512), "adj_row_r2c": (675550, 1064960),
-        "adj_col_conj_eig": (52012653, 33685504), "adj_row_c2r": (70328224, 16810080),
+        "adj_col_conj_eig": (52149094, 33685504), "adj_row_c2r": (70595347, 16810080),
     },
 }
 
