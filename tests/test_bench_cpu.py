@@ -36,3 +36,15 @@ def test_b_alg_matches_the_formula():
     n = 32 * 256 * 256
     assert alg["fwd_row_r2c"] == 4 * n * 4 and inter["fwd_row_r2c"] == 32 * 257 * 256 * 8
     assert alg["fwd_col_eig_sum"] == info["eig_bytes"]
+
+
+def test_more_than_one_gpu_is_refused():
+    # one GPU only: --gpus N > 1 exits with status 2 and says so, before touching a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120, cwd=root)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr and res.stdout == ""
