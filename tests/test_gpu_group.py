@@ -338,3 +338,27 @@ def test_group_products_at_every_compiled_5smooth_size(pk, dtype, tol):
         grp.close()
         for op in ops:
             op.close()
+
+
+def test_group_member_limit(pk):
+    # a group holds up to 64 members (the gravity and magnetic operators of 32 inversions): 64
+    # small uneven members give every member's own products; a 65th is refused
+    from paper_2112_15562_amd import _lib as L
+    grids = [synth.Grid(16 + (k % 9), 16 + (k * 5) % 9, 16 + (k % 9), 16 + (k * 5) % 9, 1 + k % 3, 40.0, 40.0, 25.0)
+             for k in range(65)]
+    ops = [pk.Operator.from_geometry(pk.GRAVITY if k % 2 == 0 else pk.MAGNETIC, g, dtype=torch.float32,
+                                     pad="pow2")
+           for k, g in enumerate(grids)]
+    with pytest.raises(L.BTTBError) as e:
+        pk.Group(ops)
+    assert e.value.status == L.BTTB_EINVAL
+    grp = pk.Group(ops[:64])
+    xs = [torch.rand(op.model_shape, dtype=torch.float32, device="cuda") for op in ops[:64]]
+    rs = [torch.randn(op.data_shape, dtype=torch.float32, device="cuda") for op in ops[:64]]
+    ys, zs = grp.matvec(xs), grp.rmatvec(rs)
+    for k in range(64):
+        assert rel(host(ys[k]), host(ops[k].matvec(xs[k]))) <= 1e-6
+        assert rel(host(zs[k]), host(ops[k].rmatvec(rs[k]))) <= 1e-6
+    grp.close()
+    for op in ops:
+        op.close()

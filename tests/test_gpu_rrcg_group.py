@@ -230,3 +230,31 @@ def test_group_step_parity_at_auto_padded_sizes(pk, dtype, tol_m):
     for p in probs:
         for op in p["ops"]:
             op.close()
+
+
+def test_group_solver_inversion_limit(pk):
+    # up to 32 joint inversions per group solver: 32 small ones step together, each as its own
+    # one-inversion solver steps; a 33rd is refused
+    from paper_2112_15562_amd import _lib as L
+    g = synth.SMALL
+    _, T, data, _ = problem(g, dense=True)
+    prm = params(VARIANTS[0])
+    probs = []
+    for k in range(33):
+        ops = [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=torch.float64) for i in range(2)]
+        probs.append(dict(ops=ops, dobs=data.dobs, wd=data.wd, wdepth=data.wdepth, **solver_kwargs(prm)))
+    with pytest.raises(L.BTTBError) as e:
+        pk.JointRRCGGroup(probs)
+    assert e.value.status == L.BTTB_EINVAL
+    grp = pk.JointRRCGGroup(probs[:32])
+    grp.step(N_INNER)
+    one = pk.JointRRCG(probs[32]["ops"], data.dobs, data.wd, data.wdepth, **solver_kwargs(prm))
+    one.step(N_INNER)
+    for i in (0, 17, 31):
+        for k in range(2):
+            assert rel(host(grp.inv[i].m[k]), host(one.m[k])) <= 1e-13
+    one.close()
+    grp.close()
+    for p in probs:
+        for op in p["ops"]:
+            op.close()
