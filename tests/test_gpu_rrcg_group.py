@@ -258,3 +258,39 @@ def test_group_solver_inversion_limit(pk):
     for p in probs:
         for op in p["ops"]:
             op.close()
+
+
+def test_graph_replays_equal_eager_steps_with_several_size_classes(pk):
+    # the four auto-sized inversions (four transform sizes, so every phase is four launches,
+    # FP32 with the first transform riding in the update): each outer step replayed from its HIP
+    # graph equals the eager launches bit for bit, checked after every replay, with host reads
+    # and eager work between the replays
+    refs = auto_reference()
+
+    def build(use_graph):
+        probs = []
+        for idx in range(len(AUTO_GRIDS)):
+            g, T, data, prm, st, _, _ = refs[idx]
+            ops = [pk.Operator(torch.as_tensor(T[i], device="cuda"), (g.sx, g.sy), dtype=torch.float32, pad="auto")
+                   for i in range(2)]
+            probs.append(dict(ops=ops, dobs=data.dobs, wd=data.wd, wdepth=data.wdepth, **solver_kwargs(prm)))
+        grp = pk.JointRRCGGroup(probs, use_graph=use_graph)
+        for idx in range(len(AUTO_GRIDS)):
+            set_state(grp, idx, refs[idx][4], torch.float32)
+        grp.refresh()
+        return grp, probs
+
+    gg, gp = build(True)
+    ge, ep = build(False)
+    for step in range(3):
+        gg.step(N_INNER)
+        ge.step(N_INNER)
+        for idx in range(len(AUTO_GRIDS)):
+            for k in range(2):
+                assert np.array_equal(host(gg.inv[idx].m[k]), host(ge.inv[idx].m[k])), (step, idx, k)
+            assert gg.scalars(idx)["phi"] == ge.scalars(idx)["phi"]
+    for grp, probs in ((gg, gp), (ge, ep)):
+        grp.close()
+        for p in probs:
+            for op in p["ops"]:
+                op.close()
