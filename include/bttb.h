@@ -82,7 +82,7 @@ typedef enum { BTTB_F64 = 0, BTTB_F32 = 1 } bttb_precision;
  * power-of-two padding of some grids is up to 4 times the area. */
 #define BTTB_PAD_AUTO 0x40
 /* Flag or-ed into bttb_setup's precision: keep the full complex eigenvalues even when the
- * operator is symmetric.  Without it, a power-of-two plan whose eigenvalues are real and
+ * operator is symmetric.  Without it, a plan (any padding) whose eigenvalues are real and
  * even along x to 1e-14 (FP64) / 1e-6 (FP32) of their largest magnitude -- the case of a
  * kernel even in both lags, e.g. gravity with the stations above the prism centres, in FP32
  * (in FP64 its closed forms are symmetric only to their evaluation noise) --
@@ -109,7 +109,7 @@ typedef struct {
 /* Plan description returned by bttb_plan_info. */
 typedef struct {
   int sx, sy, nx, ny, nz;
-  int Px, Py;              /* padded BCCB transform sizes (5-smooth multiples of 8) */
+  int Px, Py;              /* padded BCCB transform sizes (powers of two, or 5-smooth multiples of 8) */
   int precision;           /* bttb_precision */
   int max_batch;
   size_t eig_bytes;        /* bytes of the stored eigenvalues (see eig_real_even) */
