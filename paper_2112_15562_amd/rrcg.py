@@ -30,6 +30,8 @@ class _Inversion:
                  use_graph=True):
         if anchor not in ("apr", "prev"):
             raise ValueError("anchor must be 'apr' or 'prev'")
+        if gramian not in ("original", "weighted"):
+            raise ValueError("gramian must be 'original' or 'weighted'")
         self.ops = tuple(ops)
         o = self.ops[0]
         self.dtype, self.device = o.dtype, o.device

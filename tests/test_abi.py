@@ -109,3 +109,11 @@ def test_struct_layouts_match_header(lib):
         assert C.sizeof(py) == got[f"{c}.__size__"], c
         for f, _ in py._fields_:
             assert getattr(py, f).offset == got[f"{c}.{cname.get(f, f)}"], (c, f)
+
+
+def test_binding_rejects_unknown_solver_options(lib):
+    # checked before any operator or device state is touched
+    from paper_2112_15562_amd import rrcg
+    for kw in ({"anchor": "previous"}, {"gramian": "weight"}):
+        with pytest.raises(ValueError):
+            rrcg._Inversion((None, None), [], [], [], **kw)
