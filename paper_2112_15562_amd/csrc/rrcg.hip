@@ -51,7 +51,7 @@ struct Rrcg {
   int coupled, restart, p_norm, gram_w;
   int anchor;      // bttb_anchor
   void* mprev[2];  // caller-owned, BTTB_ANCHOR_PREV only
-  rrcg_group grp;  // power-of-two plans: the step runs as a one-inversion group solver
+  rrcg_group grp;  // plans that can join a product group: the step runs as a one-inversion group solver
   void* m[2];      // caller-owned
   void* p[2];      // caller-owned
   void* rt[2];     // caller-owned
@@ -169,7 +169,7 @@ static int phase_weights(Rrcg* h, hipStream_t s) {
 }
 
 // One CG step (RRCG:2-7) at the outer step's W and alpha; restart_now sets beta = 0.
-// (Power-of-two plans do not come here: their solver is a one-inversion group solver, whose
+// (Plans that can join a product group do not come here: their solver is a one-inversion group solver, whose
 // products carry the gradient, direction and step-length sums in their row transforms.)
 template <typename T>
 static int phase_inner(Rrcg* h, int restart_now, hipStream_t s) {

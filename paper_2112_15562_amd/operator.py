@@ -57,8 +57,8 @@ class Operator:
     pad: "smooth" (the smallest 5-smooth multiple of 8 >= sx+nx-1, sy+ny-1), "pow2" (powers of two,
     at least 32; also pad_pow2=True) or "auto" (per axis the power of two or 5-smooth size of least
     estimated cost in the group kernels).
-    full_eig: keep the complex eigenvalues of a symmetric operator (by default a power-of-two
-    plan stores only the real, x-even half of them; info()["eig_real_even"]).
+    full_eig: keep the complex eigenvalues of a symmetric operator (by default a plan stores only
+    the real, x-even half of them when the operator is symmetric; info()["eig_real_even"]).
     """
 
     def __init__(self, kernels: torch.Tensor, stations: Sequence[int], dtype=torch.float64,
