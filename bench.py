@@ -37,17 +37,17 @@ N_INNER = 50
 COPY_BYTES = 256 << 20   # one side of the calibration copy
 TIMING_REPEAT = 10
 
-# HBM traffic of the solver's product launches, from two rocprofv3 --pmc runs of
-# `bench.py --steps 1 --warmup 0 --no-cpu --no-f64 --no-batch --no-scan --pairs 4` (FETCH_SIZE, then WRITE_SIZE),
+# HBM traffic of the solver's product launches, from two rocprofv3 --pmc runs of `bench.py --steps 1
+# --warmup 0 --no-cpu --no-f64 --no-batch --no-scan --pairs 4 --launch 512,128,128,2` (FETCH_SIZE, then WRITE_SIZE),
 # each scaled by the same counter's reading for the calibration copy (COPY_BYTES read,
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "0ca04932b7ebb217b38e07792393f1a93d92c8c919066694dba9bbd9001c750e",
+    "csrc_sha256": "0b72e5c5afd03679a70e5bcf73fa975a15e325944ca5f313afc0637bab27f2f0",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50684463, 50528320), "fwd_col_eig_sum": (77075410, 8447936),
-        "fwd_row_c2r": (1769384, 532512), "adj_row_r2c": (675550, 1064960),
-        "adj_col_conj_eig": (52149094, 33685504), "adj_row_c2r": (70595347, 16810080),
+        "fwd_row_r2c": (50684463, 50528320), "fwd_col_eig_sum": (77056531, 8442560),
+        "fwd_row_c2r": (2855794, 528416), "adj_row_r2c": (1198021, 1064960),
+        "adj_col_conj_eig": (52012781, 33685504), "adj_row_c2r": (70508503, 16810048),
     },
 }
 
@@ -62,6 +62,9 @@ def parse():
     ap.add_argument("--pairs", type=int, default=200, help="timed product pairs per precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-inversion batched workload")
     ap.add_argument("--no-scan", action="store_true", help="skip the Lagrange-parameter scan")
+    ap.add_argument("--launch", default="",
+                    help="fixed launch shape of the timed solve's products instead of the autotuned one: "
+                         "model_row_threads,data_row_threads,col_threads,layer_chunks (for counter runs)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the benchmark: group product times per transform size, 5-smooth against "
                          "power-of-two padding, beside the size the cost-model padding picks")
@@ -648,7 +651,14 @@ def main():
     torch.cuda.synchronize()
     s32.close()
     s32 = solver(pk, torch, ops32, dobs, wd, wdepth)   # fresh start for the timed solve
-    tune32 = s32.autotune(reps=10)  # launch shape by timing CG steps; the state is restored
+    if args.launch:  # a fixed shape, set before the solver's graphs are captured
+        shape = [int(x) for x in args.launch.split(",")]
+        if len(shape) != 4:
+            raise SystemExit("--launch takes four integers")
+        s32.products().set_launch(*shape)
+        tune32 = dict(zip(("model_row_threads", "data_row_threads", "col_threads", "layer_chunks"), shape))
+    else:
+        tune32 = s32.autotune(reps=10)  # launch shape by timing CG steps; the state is restored
     s32.prepare(N_INNER)            # capture the outer-step graph before the timed region
     torch.cuda.synchronize()
     log("bench: fp32 timed solve")
@@ -791,7 +801,8 @@ def main():
                                                                                       info32["Py"]],
                    "inner_per_step": N_INNER,
                    "launch_shape": {k: tune32[k] for k in ("model_row_threads", "data_row_threads", "col_threads",
-                                                           "layer_chunks")}},
+                                                           "layer_chunks")},
+                   "launch_shape_from": "--launch" if args.launch else "autotune"},
         "outer_step": _dist(outer_ms),
         "rrcg_solve_s": {"f32": t32 * 20 / args.steps, "f64": (t64 * 20 / args.steps) if t64 else None,
                          "outer": 20, "inner": N_INNER},
