@@ -52,7 +52,19 @@ TRAFFIC = {
 }
 
 
-def parse():
+def launch_shape(text):
+    """--launch value: four positive integers separated by commas."""
+    try:
+        shape = [int(x) for x in text.split(",")]
+    except ValueError:
+        shape = []
+    if len(shape) != 4 or min(shape) < 1:
+        raise argparse.ArgumentTypeError("four positive integers: model_row_threads,data_row_threads,"
+                                         "col_threads,layer_chunks")
+    return shape
+
+
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -62,13 +74,13 @@ def parse():
     ap.add_argument("--pairs", type=int, default=200, help="timed product pairs per precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-inversion batched workload")
     ap.add_argument("--no-scan", action="store_true", help="skip the Lagrange-parameter scan")
-    ap.add_argument("--launch", default="",
+    ap.add_argument("--launch", type=launch_shape, default=None,
                     help="fixed launch shape of the timed solve's products instead of the autotuned one: "
                          "model_row_threads,data_row_threads,col_threads,layer_chunks (for counter runs)")
     ap.add_argument("--size-sweep", action="store_true",
                     help="instead of the benchmark: group product times per transform size, 5-smooth against "
                          "power-of-two padding, beside the size the cost-model padding picks")
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 def log(msg):
@@ -652,11 +664,8 @@ def main():
     s32.close()
     s32 = solver(pk, torch, ops32, dobs, wd, wdepth)   # fresh start for the timed solve
     if args.launch:  # a fixed shape, set before the solver's graphs are captured
-        shape = [int(x) for x in args.launch.split(",")]
-        if len(shape) != 4:
-            raise SystemExit("--launch takes four integers")
-        s32.products().set_launch(*shape)
-        tune32 = dict(zip(("model_row_threads", "data_row_threads", "col_threads", "layer_chunks"), shape))
+        s32.products().set_launch(*args.launch)
+        tune32 = dict(zip(("model_row_threads", "data_row_threads", "col_threads", "layer_chunks"), args.launch))
     else:
         tune32 = s32.autotune(reps=10)  # launch shape by timing CG steps; the state is restored
     s32.prepare(N_INNER)            # capture the outer-step graph before the timed region

@@ -48,3 +48,12 @@ def test_more_than_one_gpu_is_refused():
                          text=True, timeout=120, cwd=root)
     assert res.returncode == 2
     assert "one GPU" in res.stderr and res.stdout == ""
+
+
+def test_launch_shape_option():
+    # --launch fixes the timed solve's launch shape; malformed values fail at parsing
+    assert bench.parse(["--launch", "512,128,128,2"]).launch == [512, 128, 128, 2]
+    assert bench.parse([]).launch is None
+    for bad in ("512,128,128", "512,128,x,2", "512,0,128,2"):
+        with pytest.raises(SystemExit):
+            bench.parse(["--launch", bad])
