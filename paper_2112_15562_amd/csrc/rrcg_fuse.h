@@ -84,10 +84,14 @@ __device__ __forceinline__ void wave_sums_to(double (&v)[K], double (&sh)[K][16]
       for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
     }
   } else {
+    // one level of all K butterflies at a time: their lane exchanges are in flight together,
+    // so a level costs one LDS round trip rather than K (each sum adds the same terms in the
+    // same order as K butterflies one after another)
     const int wsz = blockDim.x < 64 ? (int)blockDim.x : 64;
+    for (int off = wsz >> 1; off >= 1; off >>= 1) {
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      for (int off = wsz >> 1; off >= 1; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+      for (int k = 0; k < K; ++k) v[k] += __shfl_xor(v[k], off, 64);
+    }
     if (lane == 0) {
 #pragma unroll
       for (int k = 0; k < K; ++k) sh[k][wid] = v[k];
