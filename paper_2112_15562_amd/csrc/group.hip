@@ -217,7 +217,7 @@ int group_stage_launch(const Group* g, int st, int bt, const Fuse<T>* fz, const 
   if (g->ncls[st] != 1) return BTTB_ESTATE;  // several transform sizes or half forms
   const GClass& C0 = g->cls[st][0];
   const int tr = lanes(C0.N);
-  if (bt < tr || bt % tr) return BTTB_ESTATE;
+  if (bt > 512 || bt < tr || bt % tr) return BTTB_ESTATE;  // the row kernels' block sizes (check_threads)
   const int G = bt / tr;
   const size_t esz = g->precision == BTTB_F64 ? 8 : 4;
   GClass C{};
