@@ -38,16 +38,16 @@ COPY_BYTES = 256 << 20   # one side of the calibration copy
 TIMING_REPEAT = 10
 
 # HBM traffic of the solver's product launches, from two rocprofv3 --pmc runs of `bench.py --steps 1
-# --warmup 0 --no-cpu --no-f64 --no-batch --no-scan --pairs 4 --launch 512,64,256,1` (FETCH_SIZE, then WRITE_SIZE),
+# --warmup 0 --no-cpu --no-f64 --no-batch --no-scan --pairs 4 --launch 512,256,128,2` (FETCH_SIZE, then WRITE_SIZE),
 # each scaled by the same counter's reading for the calibration copy (COPY_BYTES read,
 # COPY_BYTES written).  Valid only for the kernel sources it was taken on: the digest of
 # paper_2112_15562_amd/csrc must match, else traffic is reported as null.
 TRAFFIC = {
-    "csrc_sha256": "aeb9bc46e7b36f2363568339a65b16e0406a21cb1c209c1b7ef8ffc5203a1cba",
+    "csrc_sha256": "0e1e04eeef2b76b7b13fbb2fae01861d300a6c4b7a10343809b08b547e52f10c",
     "bytes": {  # FETCH, WRITE per launch (both operators)
-        "fwd_row_r2c": (50686510, 50528320), "fwd_col_eig_sum": (77040147, 4210688),
-        "fwd_row_c2r": (1786791, 532512), "adj_row_r2c": (1198021, 1064960),
-        "adj_col_conj_eig": (52012653, 33685504), "adj_row_c2r": (71496486, 16810080),
+        "fwd_row_r2c": (50686510, 50528320), "fwd_col_eig_sum": (77040403, 8441344),
+        "fwd_row_c2r": (2868082, 526368), "adj_row_r2c": (1198021, 1064960),
+        "adj_col_conj_eig": (52012781, 33685504), "adj_row_c2r": (71391212, 16810048),
     },
 }
 
