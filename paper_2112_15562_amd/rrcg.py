@@ -192,6 +192,14 @@ class JointRRCG:
         return st
 
     def load_state_dict(self, st: dict) -> None:
+        if self.mprev is not None and "mprev" not in st:
+            raise ValueError("the checkpoint has no m_prev: it comes from a solver with the prior-model anchor")
+        keys = ("m", "p") + (("mprev",) if self.mprev is not None else ())
+        for key in keys:
+            for i in range(2):
+                src, dst = st[key][i], getattr(self, key)[i]
+                if tuple(src.shape) != tuple(dst.shape):  # copy_ would broadcast a smaller tensor
+                    raise ValueError(f"checkpoint {key}[{i}] has shape {tuple(src.shape)}, expected {tuple(dst.shape)}")
         for i in range(2):
             self.m[i].copy_(st["m"][i])
             self.p[i].copy_(st["p"][i])

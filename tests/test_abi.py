@@ -117,3 +117,20 @@ def test_binding_rejects_unknown_solver_options(lib):
     for kw in ({"anchor": "previous"}, {"gramian": "weight"}):
         with pytest.raises(ValueError):
             rrcg._Inversion((None, None), [], [], [], **kw)
+
+
+def test_checkpoint_shapes_are_checked_before_loading(lib):
+    # a wrong-shaped or incomplete checkpoint is refused before any tensor is written
+    import torch
+    from paper_2112_15562_amd import rrcg
+    s = rrcg.JointRRCG.__new__(rrcg.JointRRCG)
+    s.m = [torch.zeros(2, 3, 4), torch.zeros(2, 3, 4)]
+    s.p = [torch.zeros(2, 3, 4), torch.zeros(2, 3, 4)]
+    s.mprev = None
+    good = [torch.ones(2, 3, 4), torch.ones(2, 3, 4)]
+    with pytest.raises(ValueError, match="shape"):
+        s.load_state_dict(dict(m=good, p=[torch.ones(3, 4), torch.ones(2, 3, 4)], scalars={}))
+    assert float(s.m[0].sum()) == 0.0
+    s.mprev = [torch.zeros(2, 3, 4), torch.zeros(2, 3, 4)]
+    with pytest.raises(ValueError, match="m_prev"):
+        s.load_state_dict(dict(m=good, p=good, scalars={}))
