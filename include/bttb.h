@@ -25,10 +25,13 @@
  *     u = station x index minus prism x index, v likewise along y, K_r the response
  *     at the station of a unit-property prism of layer r.
  *   * "dev" pointers are HIP device pointers; the caller owns them, the library
- *     only reads or writes them.  A plan owns its eigenvalues and scratch; they are
- *     allocated in bttb_setup / rrcg_create and freed by bttb_destroy / rrcg_destroy.
- *     No other call allocates, so products and RRCG steps may be captured in a HIP
- *     graph.
+ *     only reads or writes them.  A handle owns its device memory (a plan its eigenvalues
+ *     and scratch), allocated by the call that creates it (bttb_setup, bttb_group_create,
+ *     rrcg_create, rrcg_group_create) and freed by its destroy call; the autotuners and the
+ *     timing calls allocate too.  Products (one-plan, group, bttb_apply_noalloc) and RRCG
+ *     steps of a solver created with use_graph = 0 only launch kernels -- no allocation,
+ *     copy, memset or synchronisation -- so a caller may capture them in a HIP graph and
+ *     replay it (a solver with use_graph = 1 captures and replays its own graphs).
  *   * Data type: vectors are double for a BTTB_F64 plan and float for a BTTB_F32 plan.
  *     RRCG scalars are always double.
  *   * Every call is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
