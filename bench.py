@@ -74,6 +74,7 @@ def parse(argv=None):
     ap.add_argument("--pairs", type=int, default=200, help="timed product pairs per precision")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-inversion batched workload")
     ap.add_argument("--no-scan", action="store_true", help="skip the Lagrange-parameter scan")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation form (8 models, autograd)")
     ap.add_argument("--launch", type=launch_shape, default=None,
                     help="fixed launch shape of the timed solve's products instead of the autotuned one: "
                          "model_row_threads,data_row_threads,col_threads,layer_chunks (for counter runs)")
@@ -251,6 +252,71 @@ def batched_workload(pk, torch):
 SCAN_LAMS = [(0.0, 0.0)] + [(10.0 ** k, 50.0 * 10.0 ** k) for k in range(1, 8)]  # lambda2 = 50 lambda1
 SCAN_OUTER, SCAN_INNER = 30, 10
 SCAN_SIM_MIN = 0.9
+
+
+def differentiation_workload(pk, torch, iters=20):
+    """The differentiation form at B = 8 models on 128x128x24 prisms (128x128 stations), FP32:
+    y = A m through the autograd Function of each operator, then y.backward(u), whose backward
+    is the transpose product A^T u; both operators per iteration (2 B operator pairs).  Timed
+    eagerly through autograd, and as the same products captured into a HIP graph (the form's
+    forward and backward calls with fixed buffers) and replayed."""
+    import synth
+    g = synth.BATCH
+    B = 8
+    T = [pk.prism_kernels(k, g) for k in (pk.GRAVITY, pk.MAGNETIC)]
+    ops = [pk.Operator(T[i], (g.sx, g.sy), dtype=torch.float32, max_batch=B) for i in range(2)]
+    models = np.stack([synth.random_boxes(g, seed_workload=4, index=b)[0] for b in range(B)])
+    m = torch.tensor(models, dtype=torch.float32, device="cuda")
+    u = torch.tensor(synth.normal_like((B,) + g.data_shape, 4, 100), dtype=torch.float32, device="cuda")
+    ms = [m.clone().requires_grad_(True) for _ in ops]
+
+    def eager():
+        for op, mi in zip(ops, ms):
+            mi.grad = None
+            pk.BTTBFunction.apply(mi, op).backward(u)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(iters + 1)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k in range(iters):
+            fn()
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        per = [ev[k].elapsed_time(ev[k + 1]) for k in range(iters)]
+        return float(np.median(per)), _dist(per)
+
+    pairs = 2 * B
+    e_ms, e_dist = timed(eager)
+    ys = [torch.empty((B,) + g.data_shape, dtype=torch.float32, device="cuda") for _ in ops]
+    gs = [torch.empty((B,) + g.model_shape, dtype=torch.float32, device="cuda") for _ in ops]
+
+    def products():
+        for op, y, gr in zip(ops, ys, gs):
+            op.matvec(m, out=y)
+            op.rmatvec(u, out=gr)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        products()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        products()
+    r_ms, r_dist = timed(graph.replay)
+    same = all(torch.equal(gr, mi.grad) for gr, mi in zip(gs, ms))
+    del graph
+    for op in ops:
+        op.close()
+    return {"workload": f"{B} models, 128x128 stations over 128x128x24 prisms, FP32, forward and backward of "
+                        "both operators per iteration",
+            "eager_autograd": {"ms_per_iter": e_ms, "op_pairs_per_s": pairs / (e_ms * 1e-3), "iter_dist": e_dist},
+            "graph_replay": {"ms_per_iter": r_ms, "op_pairs_per_s": pairs / (r_ms * 1e-3), "iter_dist": r_dist},
+            "graph_gradients_equal_autograd": same}
 
 
 def scan_workload(pk, torch):
@@ -778,6 +844,11 @@ def main():
         log("bench: batched uneven inversions")
         batched = batched_workload(pk, torch)
 
+    diff = None
+    if not args.no_diff:
+        log("bench: differentiation form")
+        diff = differentiation_workload(pk, torch)
+
     scan = None
     if not args.no_scan:
         log("bench: Lagrange-parameter scan")
@@ -841,6 +912,7 @@ def main():
         "copy_probe": copy,
         "kernels": kernel_table,
         "batched": batched,
+        "differentiation": diff,
         "lambda_scan": scan,
         "cpu_baseline": cpu,
         "cpu_fft_baseline": cpu_fft,
