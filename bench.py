@@ -619,6 +619,41 @@ def cpu_baseline(g, budget_s=10.0):
                       f"{_cpu_model()}"}
 
 
+def cpu_dense_baselines(budget_s=1.0):
+    """The oracle's dense tier on the host: each operator's m x n matrix built from the prism
+    closed forms, products as FP64 matrix-vector products (BLAS threads as numpy has them), at
+    16x16 stations over 16x16x8 prisms and the 12x12 over 12x12x6 subcase."""
+    import synth
+    from oracle import bttb as obttb
+    from oracle import prism as oprism
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"),
+                      default=None)
+    except Exception:
+        threads = None
+    out = {}
+    for name, g in (("16x16x8", synth.SMALL), ("12x12x6", synth.SUB)):
+        og = _oracle_geometry(g)
+        t0 = time.perf_counter()
+        ops = [obttb.DenseOperator(oprism.dense_matrix(k, og), og) for k in (oprism.GRAVITY, oprism.MAGNETIC)]
+        build = time.perf_counter() - t0
+        x = synth.rng(12, 1).uniform(0.0, 1.0, g.model_shape)
+        v = synth.normal_like(g.data_shape, 12, 2)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            for op in ops:
+                op.matvec(x)
+                op.rmatvec(v)
+                n += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+        out[name] = {"op_pairs_per_s": n / dt, "pairs": n, "matrix_build_s": build, "blas_threads": threads}
+    return out
+
+
 class CpuFFTOperator:
     """A faster FP64 CPU product for the baseline (not the oracle): each layer's BCCB
     eigenvalues taken once with rfft2 on a Px x Py circle (scipy's next fast lengths >=
@@ -854,12 +889,14 @@ def main():
         log("bench: Lagrange-parameter scan")
         scan = scan_workload(pk, torch)
 
-    cpu, cpu_fft = None, None
+    cpu, cpu_fft, cpu_dense = None, None, None
     if not args.no_cpu:
         log("bench: cpu oracle baseline")
         cpu = cpu_baseline(g)
         log("bench: cpu fft baselines")
         cpu_fft = cpu_fft_baselines([("128x128x20", synth.MID), ("256x256x32", g)], rrcg_grid=g)
+        log("bench: cpu dense baselines")
+        cpu_dense = cpu_dense_baselines()
 
     Bavg32, Bavg64 = sum(B32) / 2, sum(B64) / 2
     out = {
@@ -916,6 +953,7 @@ def main():
         "lambda_scan": scan,
         "cpu_baseline": cpu,
         "cpu_fft_baseline": cpu_fft,
+        "cpu_dense_baseline": cpu_dense,
     }
     print(json.dumps(out), flush=True)
 

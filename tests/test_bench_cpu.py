@@ -57,3 +57,9 @@ def test_launch_shape_option():
     for bad in ("512,128,128", "512,128,x,2", "512,0,128,2"):
         with pytest.raises(SystemExit):
             bench.parse(["--launch", bad])
+
+
+def test_dense_baseline_runs_both_sizes():
+    out = bench.cpu_dense_baselines(budget_s=0.05)
+    assert set(out) == {"16x16x8", "12x12x6"}
+    assert all(v["op_pairs_per_s"] > 0 and v["pairs"] >= 2 for v in out.values())
