@@ -232,6 +232,22 @@ def test_large_grid_matches_fft_oracle(pk, dtype):
     _fft_case(pk, g, synth.dyke_and_block(g), dtype, F64_TOL if dtype == torch.float64 else F32_TOL)
 
 
+def test_fp32_forward_error_at_256x256x32(pk):
+    # The FP32 forward product sums its 32 layers' spectra in FP32 inside the column pass.
+    # Its error against the FP64 oracle stays at FP32 rounding: about 2^-24 sqrt(log2 of the
+    # 512 x 512 transform) per transform, plus sqrt(nz) 2^-24 = 3.4e-7 for the layer sum;
+    # held to 1e-6, ten times below the FP32 parity bound.
+    g = synth.LARGE
+    rough = synth.normal_like(g.data_shape, 3, 9)
+    for kind, m in zip((pk.GRAVITY, pk.MAGNETIC), synth.dyke_and_block(g)):
+        T, y_ref, _, _, _ = _fft_refs(g, kind, m, rough)
+        op = pk.Operator(dev(T), (g.sx, g.sy), dtype=torch.float32)
+        e = relerr(host(op.matvec(dev(m, torch.float32))), y_ref)
+        print(f"kind {kind}: FP32 forward rel err at 256x256x32 (32-layer FP32 sum) {e:.2e}", flush=True)
+        assert e <= 1e-6
+        op.close()
+
+
 # ------------------------------------------------------------------------------------
 # symmetric operators: the real, x-even eigenvalue store
 # ------------------------------------------------------------------------------------
